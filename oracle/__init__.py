@@ -1,0 +1,266 @@
+"""CPU oracle for the multi-pole Debye fitting method (test infrastructure).
+
+This package is the plain FP64 reference that the GPU library is checked
+against.  Only the test suite, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg may import it; the GPU library never does, and
+the two share no code.  The arithmetic lives in ``debye_oracle.cpp`` (built to
+``liboracle.so`` by ``oracle/build.py``); this module only marshals numpy
+arrays through ctypes.
+
+Paper: Majchrowska et al., "Modelling Arbitrary Complex Dielectric Properties
+- an automated implementation for gprMax", Sec. II-B (Eqs. 1, 3-7) and
+Sec. III (fitting procedure).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+ST_OK, ST_BADINPUT, ST_SINGULAR = 0, 1, 2
+FLAG_NO_SIGN_FLIP = 1
+KIND_DEBYE, KIND_HN, KIND_CC, KIND_CD, KIND_JONSCHER, KIND_CRIM, KIND_HNSUM = range(7)
+PARAM_STRIDE = 16
+
+_d = C.POINTER(C.c_double)
+_i64 = C.POINTER(C.c_int64)
+_i32 = C.POINTER(C.c_int32)
+_i8 = C.POINTER(C.c_int8)
+_u64 = C.POINTER(C.c_uint64)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIB_PATH)
+        L.orc_philox4x64_10.argtypes = [_u64, _u64, _u64]
+        L.orc_material_eval.argtypes = [C.c_int32, _i8, _d, _i64, _d, C.c_uint64, _d, _d, _d, C.c_int]
+        L.orc_basis.argtypes = [_d, C.c_int64, _d, C.c_int32, _d, _d]
+        L.orc_fit_eval_batch.argtypes = [C.c_int32, _i64, _i64, _i32, _d, _d, _d, _d, C.c_int64,
+                                         C.c_double, C.c_uint32, _d, _d, _d, _i8, C.c_int32, C.c_int]
+        L.orc_fit_grad_batch.argtypes = [C.c_int32, _i64, _i64, _i32, _d, _d, _d, _d, C.c_int64,
+                                         C.c_double, C.c_uint32, _d, _d, _d, _d, _d, _i8, C.c_int]
+        L.orc_fit_cs_grad.argtypes = [C.c_int64, _d, _d, _d, C.c_int32, _d, C.c_double, C.c_uint32,
+                                      C.c_double, _d, _d, _d]
+        L.orc_fit_detail.argtypes = [C.c_int64, _d, _d, _d, C.c_int32, _d, C.c_double, C.c_uint32,
+                                     _d, _d, _d, _d]
+        L.orc_pso_init.argtypes = [C.c_int32, _i64, _i32, C.c_int64, _d, _d, C.c_uint64,
+                                   _d, _d, _d, _d, _d, _i64]
+        L.orc_pso_step.argtypes = [C.c_int32, _i64, _i32, C.c_int64, _d, _d, C.c_double, C.c_double,
+                                   C.c_double, C.c_uint64, C.c_int32, C.c_int32, _d, _d, _d, _d, _d,
+                                   _d, _d, _i64, _d, C.c_int64]
+        L.orc_lbfgs_batch.argtypes = [C.c_int32, _i64, _i32, _d, _d, _d, _d, C.c_int64, C.c_double,
+                                      C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_double, _d, C.c_int]
+        L.orc_afe.argtypes = [C.c_int64, _d, _d, _d, C.c_int32, _d, _d, C.c_double]
+        L.orc_afe.restype = C.c_double
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    if a is None:
+        return None
+    return a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+# ---------------------------------------------------------------------------
+def philox4x64_10(ctr, key):
+    """Philox4x64-10 block for counter ctr[4] and key key[2] (uint64)."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_p(c, _u64), _p(k, _u64), _p(out, _u64))
+    return out
+
+
+def material_eval(kind, params, f_off, omega, noise_seed=0, jac=False, nthreads=0):
+    """Targets eps', eps'' (and optionally d(eps',eps'')/d(eps_inf,d_eps,tau0,alpha,beta)
+    as [F_tot][5][2]) for a ragged batch of materials (Eqs. 3-6)."""
+    kind = np.ascontiguousarray(kind, dtype=np.int8)
+    params = _f64(params).reshape(-1, PARAM_STRIDE)
+    f_off = np.ascontiguousarray(f_off, dtype=np.int64)
+    omega = _f64(omega)
+    M = len(kind)
+    Ft = int(f_off[-1])
+    er = np.empty(Ft)
+    ei = np.empty(Ft)
+    J = np.empty((Ft, 5, 2)) if jac else None
+    rc = lib().orc_material_eval(M, _p(kind, _i8), _p(params, _d), _p(f_off, _i64), _p(omega, _d),
+                                 C.c_uint64(noise_seed), _p(er, _d), _p(ei, _d), _p(J, _d), nthreads)
+    if rc != 0:
+        raise ValueError("material_eval: unknown material kind")
+    return (er, ei, J) if jac else (er, ei)
+
+
+def basis(omega, theta):
+    """Re/Im Debye basis [N][F] for one candidate (Eq. 7 with Eq. 1's sign)."""
+    omega = _f64(omega)
+    theta = _f64(theta)
+    N, F = len(theta), len(omega)
+    re_ = np.empty((N, F))
+    im_ = np.empty((N, F))
+    lib().orc_basis(_p(omega, _d), F, _p(theta, _d), N, _p(re_, _d), _p(im_, _d))
+    return re_, im_
+
+
+class Batch:
+    """Host description of a ragged batch: material m owns frequencies
+    f_off[m]:f_off[m+1] and candidates cand_off[m]:cand_off[m+1]; candidate c
+    stores its log10 tau in theta[c, :n_poles[m]] (row stride ld)."""
+
+    def __init__(self, f_off, cand_off, n_poles, omega, eps_re, eps_im):
+        self.f_off = np.ascontiguousarray(f_off, dtype=np.int64)
+        self.cand_off = np.ascontiguousarray(cand_off, dtype=np.int64)
+        self.n_poles = np.ascontiguousarray(n_poles, dtype=np.int32)
+        self.omega = _f64(omega)
+        self.eps_re = _f64(eps_re)
+        self.eps_im = _f64(eps_im)
+        self.M = len(self.n_poles)
+        self.P = int(self.cand_off[-1])
+
+
+def fit_eval(b: Batch, theta, damping=1e-8, flags=0, precision=64, nthreads=0):
+    """Cost, flipped weights (Delta eps), eps_inf and status for every candidate."""
+    theta = _f64(theta)
+    ld = theta.shape[1]
+    P = b.P
+    cost = np.empty(P)
+    eps_inf = np.empty(P)
+    w = np.full((P, ld), np.nan)
+    st = np.empty(P, dtype=np.int8)
+    lib().orc_fit_eval_batch(b.M, _p(b.f_off, _i64), _p(b.cand_off, _i64), _p(b.n_poles, _i32),
+                             _p(b.omega, _d), _p(b.eps_re, _d), _p(b.eps_im, _d), _p(theta, _d), ld,
+                             damping, flags, _p(cost, _d), _p(w, _d), _p(eps_inf, _d), _p(st, _i8),
+                             precision, nthreads)
+    return cost, w, eps_inf, st
+
+
+def fit_grad(b: Batch, theta, damping=1e-8, flags=0, grad_cost=None, nthreads=0):
+    """Cost and the adjoint gradient: d cost/d log10 tau [P][ld] and the target
+    gradients summed over each material's candidates (weighted by grad_cost)."""
+    theta = _f64(theta)
+    ld = theta.shape[1]
+    P = b.P
+    cost = np.empty(P)
+    gt = np.full((P, ld), np.nan)
+    gr = np.empty(len(b.omega))
+    gi = np.empty(len(b.omega))
+    st = np.empty(P, dtype=np.int8)
+    gc = None if grad_cost is None else _f64(grad_cost)
+    lib().orc_fit_grad_batch(b.M, _p(b.f_off, _i64), _p(b.cand_off, _i64), _p(b.n_poles, _i32),
+                             _p(b.omega, _d), _p(b.eps_re, _d), _p(b.eps_im, _d), _p(theta, _d), ld,
+                             damping, flags, _p(gc, _d), _p(cost, _d), _p(gt, _d), _p(gr, _d),
+                             _p(gi, _d), _p(st, _i8), nthreads)
+    return cost, gt, gr, gi, st
+
+
+def fit_cs_grad(omega, eps_re, eps_im, theta, damping=1e-8, flags=0, h=1e-30, targets=True):
+    """Complex-step derivatives of one candidate's cost."""
+    omega, eps_re, eps_im, theta = map(_f64, (omega, eps_re, eps_im, theta))
+    F, N = len(omega), len(theta)
+    gt = np.empty(N)
+    gr = np.empty(F) if targets else None
+    gi = np.empty(F) if targets else None
+    lib().orc_fit_cs_grad(F, _p(omega, _d), _p(eps_re, _d), _p(eps_im, _d), N, _p(theta, _d),
+                          damping, flags, h, _p(gt, _d), _p(gr, _d), _p(gi, _d))
+    return (gt, gr, gi) if targets else gt
+
+
+def fit_detail(omega, eps_re, eps_im, theta, damping=1e-8, flags=0):
+    """Unflipped LS solution z, scaling d and residuals of one candidate."""
+    omega, eps_re, eps_im, theta = map(_f64, (omega, eps_re, eps_im, theta))
+    F, N = len(omega), len(theta)
+    z, d, rr, ri = np.empty(N), np.empty(N), np.empty(F), np.empty(F)
+    st = lib().orc_fit_detail(F, _p(omega, _d), _p(eps_re, _d), _p(eps_im, _d), N, _p(theta, _d),
+                              damping, flags, _p(z, _d), _p(d, _d), _p(rr, _d), _p(ri, _d))
+    return st, z, d, rr, ri
+
+
+class Swarm:
+    """PSO state in the library's layout (rows of stride ld)."""
+
+    def __init__(self, P, M, ld, hist_len=0):
+        self.x = np.zeros((P, ld))
+        self.v = np.zeros((P, ld))
+        self.pbest_x = np.zeros((P, ld))
+        self.pbest_cost = np.zeros(P)
+        self.gbest_x = np.zeros((M, ld))
+        self.gbest_cost = np.zeros(M)
+        self.gbest_idx = np.zeros(M, dtype=np.int64)
+        self.history = np.full((M, max(hist_len, 1)), np.nan)
+
+    def copy(self):
+        s = Swarm.__new__(Swarm)
+        for k, v in self.__dict__.items():
+            setattr(s, k, v.copy())
+        return s
+
+
+def pso_init(cand_off, n_poles, lb, ub, seed, sw: Swarm):
+    cand_off = np.ascontiguousarray(cand_off, dtype=np.int64)
+    n_poles = np.ascontiguousarray(n_poles, dtype=np.int32)
+    lb, ub = _f64(lb), _f64(ub)
+    lib().orc_pso_init(len(n_poles), _p(cand_off, _i64), _p(n_poles, _i32), sw.x.shape[1], _p(lb, _d),
+                       _p(ub, _d), C.c_uint64(seed), _p(sw.x, _d), _p(sw.v, _d), _p(sw.pbest_x, _d),
+                       _p(sw.pbest_cost, _d), _p(sw.gbest_cost, _d), _p(sw.gbest_idx, _i64))
+
+
+def pso_step(cand_off, n_poles, lb, ub, inertia, c1, c2, seed, t, move, cost, sw: Swarm):
+    cand_off = np.ascontiguousarray(cand_off, dtype=np.int64)
+    n_poles = np.ascontiguousarray(n_poles, dtype=np.int32)
+    lb, ub, cost = _f64(lb), _f64(ub), _f64(cost)
+    lib().orc_pso_step(len(n_poles), _p(cand_off, _i64), _p(n_poles, _i32), sw.x.shape[1], _p(lb, _d),
+                       _p(ub, _d), inertia, c1, c2, C.c_uint64(seed), t, int(move), _p(cost, _d),
+                       _p(sw.x, _d), _p(sw.v, _d), _p(sw.pbest_x, _d), _p(sw.pbest_cost, _d),
+                       _p(sw.gbest_x, _d), _p(sw.gbest_cost, _d), _p(sw.gbest_idx, _i64),
+                       _p(sw.history, _d), sw.history.shape[1])
+
+
+def pso_run(b: Batch, lb, ub, iters, inertia=0.7, c1=1.5, c2=1.5, seed=0, ld=None, damping=1e-8,
+            flags=0, nthreads=0):
+    """Whole swarm fit: init, evaluate, then `iters` x (move + evaluate), then a
+    final bests-only step.  P*(iters+1) evaluations per material."""
+    ld = ld or int(b.n_poles.max())
+    sw = Swarm(b.P, b.M, ld, iters + 1)
+    pso_init(b.cand_off, b.n_poles, lb, ub, seed, sw)
+    cost = fit_eval(b, sw.x, damping, flags, nthreads=nthreads)[0]
+    for t in range(1, iters + 1):
+        pso_step(b.cand_off, b.n_poles, lb, ub, inertia, c1, c2, seed, t, True, cost, sw)
+        cost = fit_eval(b, sw.x, damping, flags, nthreads=nthreads)[0]
+    pso_step(b.cand_off, b.n_poles, lb, ub, inertia, c1, c2, seed, iters + 1, False, cost, sw)
+    return sw
+
+
+def lbfgs(b: Batch, theta, steps=50, mem=10, max_trials=30, c1=1e-4, damping=1e-8, flags=0, nthreads=0):
+    """L-BFGS polish of one candidate per material (theta[M][ld]); returns the
+    polished theta and the cost history [M][steps+1]."""
+    th = _f64(theta).copy()
+    hist = np.empty((b.M, steps + 1))
+    lib().orc_lbfgs_batch(b.M, _p(b.f_off, _i64), _p(b.n_poles, _i32), _p(b.omega, _d), _p(b.eps_re, _d),
+                          _p(b.eps_im, _d), _p(th, _d), th.shape[1], damping, flags, steps, mem,
+                          max_trials, c1, _p(hist, _d), nthreads)
+    return th, hist
+
+
+def afe(omega, eps_re, eps_im, d_eps, tau, eps_inf):
+    """Average fractional error (percent) of a fitted multi-Debye model (Sec. IV)."""
+    omega, eps_re, eps_im, d_eps, tau = map(_f64, (omega, eps_re, eps_im, d_eps, tau))
+    return lib().orc_afe(len(omega), _p(omega, _d), _p(eps_re, _d), _p(eps_im, _d), len(d_eps),
+                         _p(d_eps, _d), _p(tau, _d), float(eps_inf))

@@ -1,0 +1,835 @@
+// Plain CPU reference ("oracle") for the multi-pole Debye fitting method of
+// Majchrowska, Giannakis, Warren and Giannopoulos, "Modelling Arbitrary Complex
+// Dielectric Properties - an automated implementation for gprMax" (2021).
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct reference
+// that the GPU library is checked against.  Only the test suite, the smoke
+// check and the benchmark's CPU-baseline leg load it.  It shares no code,
+// headers, tables or helpers with the GPU library.
+//
+// Everything is written from the definitions, in the order the paper states
+// them, with no blocking, fusion or reordering:
+//   * material models          Eq. (3) Debye, Eq. (4) Havriliak-Negami (and its
+//                              Cole-Cole / Cole-Davidson special cases),
+//                              Eq. (5) Jonscher, Eq. (6) CRIM, and a tabulated
+//                              sum of HN terms with multiplicative noise
+//                              (stand-in for user data, Sec. III-A)
+//   * multi-Debye basis        Eq. (7) with the sign convention of Eq. (1)
+//   * DLS weights              damped least squares on the loss part (Sec. III-A,
+//                              Sec. III-B), solved by Householder QR of the
+//                              stacked damped system (textbook LS)
+//   * sign flip                negative weights flipped (Sec. III-B)
+//   * eps_inf and cost         eps_inf = mean real-part misfit; cost = sum of
+//                              squared real and imaginary residuals (Sec. III-B)
+//   * adjoint gradient         variable-projection derivative of the cost
+//   * complex-step gradient    the same forward map on complex numbers
+//   * Philox4x64-10            Salmon et al., SC'11 (counter-based RNG)
+//   * PSO                      Kennedy-Eberhart particle swarm (Sec. III-A)
+//   * L-BFGS polish            Liu-Nocedal two-loop recursion, Armijo backtracking
+//
+// Floating point: FP64 (the paper's NumPy/SciPy implementation is FP64), built
+// with -O2 -ffp-contract=off and no fast-math.  The forward model is templated
+// on its scalar type: double is the contract, long double (x87 80-bit) is used
+// to attribute disagreements, std::complex<double> gives complex-step
+// derivatives.
+//
+// Parity pins for every function live in tests/test_oracle_*.py.
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+using cd = std::complex<double>;
+
+// Status codes (shared meaning with the library's public header, defined here
+// independently).
+enum { ST_OK = 0, ST_BADINPUT = 1, ST_SINGULAR = 2 };
+enum { FLAG_NO_SIGN_FLIP = 1u };
+
+// Largest |log10 tau| accepted; beyond it a candidate is reported BADINPUT.
+constexpr double THETA_LIMIT = 64.0;
+constexpr double LN10 = 2.302585092994045684017991454684364208;
+
+// ---------------------------------------------------------------------------
+// scalar helpers so that one template serves double, long double and the
+// complex-step type
+// ---------------------------------------------------------------------------
+inline double re(double x) { return x; }
+inline long double re(long double x) { return x; }
+inline double re(const cd &x) { return x.real(); }
+
+// |z| written as z*sign(Re z): equal to fabs for real types and the analytic
+// continuation needed by the complex-step method.
+template <class T> inline T flip_abs(const T &z) { return re(z) < 0 ? T(-z) : z; }
+
+template <class T> inline T pow10_t(const T &t) { return std::pow(T(10), t); }
+inline double pow10_t(const double &t) { return std::pow(10.0, t); }
+inline long double pow10_t(const long double &t) { return std::pow(10.0L, t); }
+
+template <class T> inline bool finite_t(const T &x) { return std::isfinite(re(x)); }
+inline bool finite_t(const cd &x) { return std::isfinite(x.real()) && std::isfinite(x.imag()); }
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+// as 1, 2, 3", SC'11).  Counter c[4], key k[2].
+// ---------------------------------------------------------------------------
+inline void mulhilo64(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo) {
+  unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+  hi = (uint64_t)(p >> 64);
+  lo = (uint64_t)p;
+}
+
+void philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+  uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(M0, c0, hi0, lo0);
+    mulhilo64(M1, c2, hi1, lo1);
+    uint64_t n0 = hi1 ^ c1 ^ k0;
+    uint64_t n1 = lo1;
+    uint64_t n2 = hi0 ^ c3 ^ k1;
+    uint64_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// uniform double in [0, 1) from the top 53 bits of a 64-bit word
+inline double u01(uint64_t r) { return (double)(r >> 11) * 0x1.0p-53; }
+
+// Stream identifiers used as the last counter word.
+enum { STREAM_PSO_INIT = 0, STREAM_PSO_STEP = 1, STREAM_NOISE = 2 };
+
+// ---------------------------------------------------------------------------
+// Material models (relaxation functions).  eps = eps' - j eps'' (Eq. 1).
+// ---------------------------------------------------------------------------
+enum {
+  KIND_DEBYE = 0,    // Eq. 3:  (eps_inf, d_eps, tau0)
+  KIND_HN = 1,       // Eq. 4:  (eps_inf, d_eps, tau0, alpha, beta)
+  KIND_CC = 2,       // Eq. 4 with beta = 1
+  KIND_CD = 3,       // Eq. 4 with alpha = 1
+  KIND_JONSCHER = 4, // (eps_inf, chi, omega_p, n): eps_inf + chi (j w/w_p)^(n-1)
+  KIND_CRIM = 5,     // Eq. 6, a = 1/2, water Debye phase + lossless matrix:
+                     // (eps_inf_w, d_eps_w, tau_w, f_w, eps_m)
+  KIND_HNSUM = 6,    // (eps_inf, n_terms, [d_eps, tau0, alpha, beta] x 3, noise)
+  N_KINDS = 7
+};
+constexpr int PARAM_STRIDE = 16;
+
+// One Havriliak-Negami term d_eps / (1 + (j w tau0)^alpha)^beta, principal
+// branches, written with complex library arithmetic (Eq. 4).
+inline cd hn_term(double w, double d_eps, double tau0, double alpha, double beta) {
+  cd jwt(0.0, w * tau0);
+  cd p = std::pow(jwt, alpha);
+  cd base = 1.0 + p;
+  return d_eps / std::pow(base, beta);
+}
+
+// d eps / d(eps_inf, d_eps, tau0, alpha, beta) for one HN term (+eps_inf).
+inline void hn_term_jac(double w, double d_eps, double tau0, double alpha, double beta, cd out[5]) {
+  cd jwt(0.0, w * tau0);
+  cd p = std::pow(jwt, alpha);
+  cd base = 1.0 + p;
+  cd bmb = std::pow(base, -beta);                 // base^-beta
+  cd bmb1 = std::pow(base, -beta - 1.0);          // base^(-beta-1)
+  out[0] = cd(1.0, 0.0);
+  out[1] = bmb;
+  out[2] = -beta * d_eps * bmb1 * (alpha * p / tau0);
+  out[3] = -beta * d_eps * bmb1 * (p * std::log(jwt));
+  out[4] = -d_eps * bmb * std::log(base);
+}
+
+int material_one(int kind, const double *p, int64_t F, const double *omega, uint64_t noise_seed,
+                 int64_t mat_index, double *eps_re, double *eps_im, double *jac) {
+  if (kind < 0 || kind >= N_KINDS) return -1;
+  for (int64_t k = 0; k < F; ++k) {
+    const double w = omega[k];
+    cd eps;
+    switch (kind) {
+    case KIND_DEBYE:
+      eps = p[0] + p[1] / cd(1.0, w * p[2]);
+      break;
+    case KIND_HN:
+      eps = p[0] + hn_term(w, p[1], p[2], p[3], p[4]);
+      break;
+    case KIND_CC:
+      eps = p[0] + hn_term(w, p[1], p[2], p[3], 1.0);
+      break;
+    case KIND_CD:
+      eps = p[0] + hn_term(w, p[1], p[2], 1.0, p[4]);
+      break;
+    case KIND_JONSCHER: {
+      cd jy(0.0, w / p[2]);
+      eps = p[0] + p[1] * std::pow(jy, p[3] - 1.0);
+      break;
+    }
+    case KIND_CRIM: {
+      cd eps_w = p[0] + p[1] / cd(1.0, w * p[2]);
+      cd root = p[3] * std::sqrt(eps_w) + (1.0 - p[3]) * std::sqrt(cd(p[4], 0.0));
+      eps = root * root;
+      break;
+    }
+    case KIND_HNSUM: {
+      int nt = (int)p[1];
+      eps = cd(p[0], 0.0);
+      for (int t = 0; t < nt && t < 3; ++t)
+        eps += hn_term(w, p[2 + 4 * t], p[3 + 4 * t], p[4 + 4 * t], p[5 + 4 * t]);
+      break;
+    }
+    }
+    double er = eps.real(), ei = -eps.imag();
+    if (kind == KIND_HNSUM && p[14] != 0.0) {
+      // multiplicative Gaussian noise, Box-Muller on Philox uniforms
+      uint64_t ctr[4] = {(uint64_t)k, 0, 0, STREAM_NOISE};
+      uint64_t key[2] = {noise_seed, (uint64_t)mat_index};
+      uint64_t r[4];
+      philox4x64_10(ctr, key, r);
+      double u1 = u01(r[0]), u2 = u01(r[1]);
+      double rad = std::sqrt(-2.0 * std::log(1.0 - u1));
+      double n1 = rad * std::cos(2.0 * M_PI * u2);
+      double n2 = rad * std::sin(2.0 * M_PI * u2);
+      er = er * (1.0 + p[14] * n1);
+      ei = ei * (1.0 + p[14] * n2);
+    }
+    eps_re[k] = er;
+    eps_im[k] = ei;
+    if (jac) {
+      double *J = jac + k * 10;
+      if (kind <= KIND_CD) {
+        double a = (kind == KIND_CD || kind == KIND_DEBYE) ? 1.0 : p[3];
+        double b = (kind == KIND_CC || kind == KIND_DEBYE) ? 1.0 : p[4];
+        cd d[5];
+        hn_term_jac(w, p[1], p[2], a, b, d);
+        for (int q = 0; q < 5; ++q) {
+          J[2 * q] = d[q].real();
+          J[2 * q + 1] = -d[q].imag();
+        }
+      } else {
+        for (int q = 0; q < 10; ++q) J[q] = std::numeric_limits<double>::quiet_NaN();
+      }
+    }
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Multi-Debye basis, Eq. (7) split by Eq. (1):
+//   1/(1 + j w tau) = R - j I,  R = 1/(1+x^2),  I = x/(1+x^2),  x = w tau
+// ---------------------------------------------------------------------------
+template <class T> inline void basis_point(double w, const T &tau, T &R, T &I) {
+  T x = w * tau;
+  T den = T(1) + x * x;
+  R = T(1) / den;
+  I = x / den;
+}
+
+// ---------------------------------------------------------------------------
+// Forward map for one candidate.
+// ---------------------------------------------------------------------------
+template <class T> struct Fit {
+  int status = ST_OK;
+  T cost{}, eps_inf{};
+  std::vector<T> tau, d, z, w;      // N
+  std::vector<T> R, I;              // [F][N]
+  std::vector<T> rre, rim;          // residuals, F
+  std::vector<T> Rqr;               // N x N upper factor of the scaled damped system
+};
+
+template <class T>
+Fit<T> fit_forward(int64_t F, const double *omega, const T *eps_re, const T *eps_im, int N,
+                   const T *theta, double damping, unsigned flags) {
+  Fit<T> out;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  out.cost = T(nan);
+  out.eps_inf = T(nan);
+  out.z.assign(N, T(nan));
+  out.w.assign(N, T(nan));
+
+  // input checks: non-finite data, or |log10 tau| beyond the accepted range
+  bool bad = false;
+  for (int i = 0; i < N; ++i)
+    if (!finite_t(theta[i]) || std::fabs(re(theta[i])) > THETA_LIMIT) bad = true;
+  for (int64_t k = 0; k < F; ++k)
+    if (!std::isfinite(omega[k]) || !finite_t(eps_re[k]) || !finite_t(eps_im[k])) bad = true;
+  if (bad) { out.status = ST_BADINPUT; return out; }
+
+  // step 1: relaxation times and basis
+  out.tau.resize(N);
+  for (int i = 0; i < N; ++i) out.tau[i] = pow10_t(theta[i]);
+  out.R.resize((size_t)F * N);
+  out.I.resize((size_t)F * N);
+  for (int64_t k = 0; k < F; ++k)
+    for (int i = 0; i < N; ++i)
+      basis_point(omega[k], out.tau[i], out.R[k * N + i], out.I[k * N + i]);
+
+  // step 2: Marquardt scaling d_i = ||I_{:,i}||_2, then the damped least
+  // squares  min || (I D^-1) zt - eps'' ||^2 + damping ||zt||^2  solved by
+  // Householder QR of the stacked matrix [I D^-1 ; sqrt(damping) Id_N].
+  out.d.resize(N);
+  for (int i = 0; i < N; ++i) {
+    T s = T(0);
+    for (int64_t k = 0; k < F; ++k) s += out.I[k * N + i] * out.I[k * N + i];
+    out.d[i] = std::sqrt(s);
+    if (!(re(out.d[i]) > 0)) { out.status = ST_SINGULAR; out.cost = T(INFINITY); return out; }
+  }
+  const int64_t m = F + N;
+  std::vector<T> A((size_t)m * N, T(0)), y(m, T(0));
+  for (int64_t k = 0; k < F; ++k) {
+    for (int i = 0; i < N; ++i) A[k * N + i] = out.I[k * N + i] / out.d[i];
+    y[k] = eps_im[k];
+  }
+  const T sq = std::sqrt(T(damping));
+  for (int i = 0; i < N; ++i) A[(F + i) * N + i] = sq;
+
+  for (int j = 0; j < N; ++j) {
+    T sigma = T(0);
+    for (int64_t r = j; r < m; ++r) sigma += A[r * N + j] * A[r * N + j];
+    if (re(sigma) == 0) continue;
+    T alpha = std::sqrt(sigma);
+    if (re(A[j * N + j]) > 0) alpha = -alpha;
+    // v = x - alpha e1 (stored in a scratch vector), H = Id - 2 v v^T / (v^T v)
+    std::vector<T> v(m - j);
+    for (int64_t r = j; r < m; ++r) v[r - j] = A[r * N + j];
+    v[0] -= alpha;
+    T vv = T(0);
+    for (auto &e : v) vv += e * e;
+    for (int c = j; c < N; ++c) {
+      T dot = T(0);
+      for (int64_t r = j; r < m; ++r) dot += v[r - j] * A[r * N + c];
+      T f = T(2) * dot / vv;
+      for (int64_t r = j; r < m; ++r) A[r * N + c] -= f * v[r - j];
+    }
+    T dot = T(0);
+    for (int64_t r = j; r < m; ++r) dot += v[r - j] * y[r];
+    T f = T(2) * dot / vv;
+    for (int64_t r = j; r < m; ++r) y[r] -= f * v[r - j];
+  }
+  out.Rqr.assign((size_t)N * N, T(0));
+  for (int i = 0; i < N; ++i)
+    for (int j = i; j < N; ++j) out.Rqr[i * N + j] = A[i * N + j];
+
+  // rank check, tolerance max(F, N) * unit roundoff * max|R_jj| (the usual
+  // numerical-rank threshold); only reachable without damping
+  {
+    double rmax = 0, rmin = INFINITY;
+    for (int i = 0; i < N; ++i) {
+      double a = std::fabs((double)re(out.Rqr[i * N + i]));
+      rmax = std::max(rmax, a);
+      rmin = std::min(rmin, a);
+    }
+    if (rmin <= (double)std::max<int64_t>(F, N) * 0x1.0p-53 * rmax || rmax == 0) {
+      out.status = ST_SINGULAR;
+      out.cost = T(INFINITY);
+      return out;
+    }
+  }
+  // back substitution  Rqr zt = (Q^T y)[0:N],  z = D^-1 zt
+  std::vector<T> zt(N);
+  for (int i = N - 1; i >= 0; --i) {
+    T s = y[i];
+    for (int j = i + 1; j < N; ++j) s -= out.Rqr[i * N + j] * zt[j];
+    zt[i] = s / out.Rqr[i * N + i];
+  }
+  for (int i = 0; i < N; ++i) out.z[i] = zt[i] / out.d[i];
+
+  // step 3: negative weights flipped (penalty reading of Sec. III-B)
+  for (int i = 0; i < N; ++i) out.w[i] = (flags & FLAG_NO_SIGN_FLIP) ? out.z[i] : flip_abs(out.z[i]);
+
+  // step 4: eps_inf = mean over frequencies of the real-part misfit
+  T acc = T(0);
+  for (int64_t k = 0; k < F; ++k) {
+    T s = eps_re[k];
+    for (int i = 0; i < N; ++i) s -= out.w[i] * out.R[k * N + i];
+    acc += s;
+  }
+  out.eps_inf = acc / T((double)F);
+
+  // step 5: residuals and cost (real + imaginary part)
+  out.rre.resize(F);
+  out.rim.resize(F);
+  T cost = T(0);
+  for (int64_t k = 0; k < F; ++k) {
+    T a = eps_re[k] - out.eps_inf, b = eps_im[k];
+    for (int i = 0; i < N; ++i) {
+      a -= out.w[i] * out.R[k * N + i];
+      b -= out.w[i] * out.I[k * N + i];
+    }
+    out.rre[k] = a;
+    out.rim[k] = b;
+    cost += a * a + b * b;
+  }
+  out.cost = cost;
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Variable-projection adjoint of the cost (derived for this method):
+//   M z = I^T eps'',  M = I^T I + damping diag(I^T I)
+//   g_w   = -2 (R^T r' + I^T r'')            (eps_inf is a mean: no term)
+//   mu    = M^-1 (s o g_w),  s = sign(z) (or 1 without the flip)
+//   dC/dtheta_i = -2 w_i (dR_i^T r' + dI_i^T r'') + mu_i dI_i^T (eps'' - I z)
+//                 - z_i dI_i^T (I mu) - 2 damping mu_i z_i dI_i^T I_i
+//   dC/deps'_k  = 2 r'_k,   dC/deps''_k = 2 r''_k + (I mu)_k
+// with dR/dtheta = -2 ln10 x^2 R^2 and dI/dtheta = ln10 x R^2 (1 - x^2).
+// M is applied through the QR factor: M = D Rqr^T Rqr D.
+// ---------------------------------------------------------------------------
+struct GradOut {
+  int status;
+  double cost;
+  std::vector<double> g_theta, g_re, g_im;
+};
+
+GradOut fit_grad(int64_t F, const double *omega, const double *eps_re, const double *eps_im, int N,
+                 const double *theta, double damping, unsigned flags) {
+  Fit<double> f = fit_forward<double>(F, omega, eps_re, eps_im, N, theta, damping, flags);
+  GradOut g;
+  g.status = f.status;
+  g.cost = f.cost;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  g.g_theta.assign(N, nan);
+  g.g_re.assign(F, nan);
+  g.g_im.assign(F, nan);
+  if (f.status != ST_OK) return g;
+
+  std::vector<double> gw(N, 0.0), sg(N);
+  for (int i = 0; i < N; ++i) {
+    double s = 0;
+    for (int64_t k = 0; k < F; ++k) s += f.R[k * N + i] * f.rre[k] + f.I[k * N + i] * f.rim[k];
+    gw[i] = -2.0 * s;
+    sg[i] = (flags & FLAG_NO_SIGN_FLIP) ? 1.0 : (f.z[i] < 0 ? -1.0 : 1.0);
+  }
+  // mu = D^-1 Rqr^-1 Rqr^-T D^-1 (s o g_w)
+  std::vector<double> u(N), v(N), mu(N);
+  for (int i = 0; i < N; ++i) {
+    double s = sg[i] * gw[i] / f.d[i];
+    for (int j = 0; j < i; ++j) s -= f.Rqr[j * N + i] * u[j];
+    u[i] = s / f.Rqr[i * N + i];
+  }
+  for (int i = N - 1; i >= 0; --i) {
+    double s = u[i];
+    for (int j = i + 1; j < N; ++j) s -= f.Rqr[i * N + j] * v[j];
+    v[i] = s / f.Rqr[i * N + i];
+  }
+  for (int i = 0; i < N; ++i) mu[i] = v[i] / f.d[i];
+
+  std::vector<double> Iz(F), Imu(F);
+  for (int64_t k = 0; k < F; ++k) {
+    double a = 0, b = 0;
+    for (int i = 0; i < N; ++i) {
+      a += f.I[k * N + i] * f.z[i];
+      b += f.I[k * N + i] * mu[i];
+    }
+    Iz[k] = a;
+    Imu[k] = b;
+  }
+  for (int i = 0; i < N; ++i) {
+    double t1 = 0, t2 = 0, t3 = 0, t4 = 0;
+    for (int64_t k = 0; k < F; ++k) {
+      double x = omega[k] * f.tau[i];
+      double R = f.R[k * N + i], I = f.I[k * N + i];
+      double dR = -2.0 * LN10 * x * x * R * R;
+      double dI = LN10 * x * R * R * (1.0 - x * x);
+      t1 += dR * f.rre[k] + dI * f.rim[k];
+      t2 += dI * (eps_im[k] - Iz[k]);
+      t3 += dI * Imu[k];
+      t4 += dI * I;
+    }
+    g.g_theta[i] = -2.0 * f.w[i] * t1 + mu[i] * t2 - f.z[i] * t3 - 2.0 * damping * mu[i] * f.z[i] * t4;
+  }
+  for (int64_t k = 0; k < F; ++k) {
+    g.g_re[k] = 2.0 * f.rre[k];
+    g.g_im[k] = 2.0 * f.rim[k] + Imu[k];
+  }
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// L-BFGS polish of one candidate (Liu & Nocedal 1989; two-loop recursion as in
+// Nocedal & Wright, Algorithm 7.4), Armijo backtracking by halving.
+// ---------------------------------------------------------------------------
+struct LbfgsCfg {
+  int steps, mem, max_trials;
+  double c1;
+};
+
+int lbfgs_one(int64_t F, const double *omega, const double *eps_re, const double *eps_im, int N,
+              double *theta, double damping, unsigned flags, const LbfgsCfg &cfg, double *cost_hist) {
+  std::vector<double> th(theta, theta + N);
+  GradOut g = fit_grad(F, omega, eps_re, eps_im, N, th.data(), damping, flags);
+  double C = g.cost;
+  std::vector<double> grad = g.g_theta;
+  std::vector<std::vector<double>> S, Y;
+  std::vector<double> rho;
+  int taken = 0;
+  for (int step = 0; step < cfg.steps; ++step) {
+    if (cost_hist) cost_hist[step] = C;
+    if (g.status != ST_OK || !std::isfinite(C)) continue;
+    // search direction d = -H g
+    std::vector<double> q = grad, a(S.size());
+    for (int j = (int)S.size() - 1; j >= 0; --j) {
+      double s = 0;
+      for (int i = 0; i < N; ++i) s += S[j][i] * q[i];
+      a[j] = rho[j] * s;
+      for (int i = 0; i < N; ++i) q[i] -= a[j] * Y[j][i];
+    }
+    double gamma = 1.0;
+    if (!S.empty()) {
+      double sy = 0, yy = 0;
+      for (int i = 0; i < N; ++i) { sy += S.back()[i] * Y.back()[i]; yy += Y.back()[i] * Y.back()[i]; }
+      gamma = sy / yy;
+    }
+    for (int i = 0; i < N; ++i) q[i] *= gamma;
+    for (int j = 0; j < (int)S.size(); ++j) {
+      double s = 0;
+      for (int i = 0; i < N; ++i) s += Y[j][i] * q[i];
+      double b = rho[j] * s;
+      for (int i = 0; i < N; ++i) q[i] += (a[j] - b) * S[j][i];
+    }
+    std::vector<double> d(N);
+    double gd = 0;
+    for (int i = 0; i < N; ++i) { d[i] = -q[i]; gd += grad[i] * d[i]; }
+    if (S.empty() || !(gd < 0)) {
+      // steepest descent, scaled so the largest component moves one decade
+      S.clear(); Y.clear(); rho.clear();
+      double gmax = 0;
+      for (int i = 0; i < N; ++i) gmax = std::max(gmax, std::fabs(grad[i]));
+      if (!(gmax > 0)) continue;
+      double sc = std::min(1.0, 1.0 / gmax);
+      gd = 0;
+      for (int i = 0; i < N; ++i) { d[i] = -grad[i] * sc; gd += grad[i] * d[i]; }
+    }
+    // Armijo backtracking: alpha = 1, 1/2, 1/4, ...
+    double alpha = 1.0;
+    bool ok = false;
+    std::vector<double> tt(N);
+    double Ct = 0;
+    for (int t = 0; t < cfg.max_trials; ++t) {
+      for (int i = 0; i < N; ++i) tt[i] = th[i] + alpha * d[i];
+      Fit<double> ft = fit_forward<double>(F, omega, eps_re, eps_im, N, tt.data(), damping, flags);
+      Ct = ft.cost;
+      if (ft.status == ST_OK && Ct <= C + cfg.c1 * alpha * gd) { ok = true; break; }
+      alpha *= 0.5;
+    }
+    if (!ok) continue;
+    GradOut gt = fit_grad(F, omega, eps_re, eps_im, N, tt.data(), damping, flags);
+    std::vector<double> s(N), y(N);
+    double sy = 0;
+    for (int i = 0; i < N; ++i) { s[i] = tt[i] - th[i]; y[i] = gt.g_theta[i] - grad[i]; sy += s[i] * y[i]; }
+    if (sy > 1e-300) {
+      S.push_back(s); Y.push_back(y); rho.push_back(1.0 / sy);
+      if ((int)S.size() > cfg.mem) { S.erase(S.begin()); Y.erase(Y.begin()); rho.erase(rho.begin()); }
+    }
+    th = tt;
+    C = gt.cost;
+    grad = gt.g_theta;
+    g = gt;
+    ++taken;
+  }
+  for (int i = 0; i < N; ++i) theta[i] = th[i];
+  if (cost_hist) cost_hist[cfg.steps] = C;
+  return taken;
+}
+
+int nthreads_or_default(int nthreads) {
+#ifdef _OPENMP
+  return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+  (void)nthreads;
+  return 1;
+#endif
+}
+
+inline int mat_of(const int64_t *cand_off, int32_t M, int64_t c) {
+  // largest m with cand_off[m] <= c
+  int lo = 0, hi = M - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (cand_off[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+} // namespace
+
+// ===========================================================================
+// C entry points (loaded with ctypes by the tests and the benchmark)
+// ===========================================================================
+extern "C" {
+
+int orc_philox4x64_10(const uint64_t *ctr, const uint64_t *key, uint64_t *out) {
+  philox4x64_10(ctr, key, out);
+  return 0;
+}
+
+int orc_material_eval(int32_t M, const int8_t *kind, const double *params, const int64_t *f_off,
+                      const double *omega, uint64_t noise_seed, double *eps_re, double *eps_im,
+                      double *jac, int nthreads) {
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic) num_threads(nthreads_or_default(nthreads)) reduction(| : bad)
+  for (int32_t m = 0; m < M; ++m) {
+    int64_t a = f_off[m], F = f_off[m + 1] - f_off[m];
+    if (material_one(kind[m], params + (size_t)m * PARAM_STRIDE, F, omega + a, noise_seed, m,
+                     eps_re + a, eps_im + a, jac ? jac + a * 10 : nullptr) != 0)
+      bad |= 1;
+  }
+  return bad ? -1 : 0;
+}
+
+int orc_basis(const double *omega, int64_t F, const double *theta, int32_t N, double *re_out,
+              double *im_out) {
+  for (int i = 0; i < N; ++i) {
+    double tau = pow10_t(theta[i]);
+    for (int64_t k = 0; k < F; ++k) basis_point(omega[k], tau, re_out[i * F + k], im_out[i * F + k]);
+  }
+  return 0;
+}
+
+// Batched forward.  Candidate c of material m has log10 tau at theta[c*ld + i],
+// i < n_poles[m]; weights use the same layout.  Any output pointer may be NULL.
+int orc_fit_eval_batch(int32_t M, const int64_t *f_off, const int64_t *cand_off, const int32_t *n_poles,
+                       const double *omega, const double *eps_re, const double *eps_im,
+                       const double *theta, int64_t ld, double damping, uint32_t flags, double *cost,
+                       double *weights, double *eps_inf, int8_t *status, int32_t precision,
+                       int nthreads) {
+  const int64_t P = cand_off[M];
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads_or_default(nthreads))
+  for (int64_t c = 0; c < P; ++c) {
+    int m = mat_of(cand_off, M, c);
+    int64_t a = f_off[m], F = f_off[m + 1] - f_off[m];
+    int N = n_poles[m];
+    if (precision == 80) {
+      std::vector<long double> er(F), ei(F), th(N);
+      for (int64_t k = 0; k < F; ++k) { er[k] = eps_re[a + k]; ei[k] = eps_im[a + k]; }
+      for (int i = 0; i < N; ++i) th[i] = theta[c * ld + i];
+      Fit<long double> f = fit_forward<long double>(F, omega + a, er.data(), ei.data(), N, th.data(), damping, flags);
+      if (cost) cost[c] = (double)f.cost;
+      if (eps_inf) eps_inf[c] = (double)f.eps_inf;
+      if (status) status[c] = (int8_t)f.status;
+      if (weights) for (int i = 0; i < N; ++i) weights[c * ld + i] = (double)f.w[i];
+    } else {
+      Fit<double> f = fit_forward<double>(F, omega + a, eps_re + a, eps_im + a, N, theta + c * ld, damping, flags);
+      if (cost) cost[c] = f.cost;
+      if (eps_inf) eps_inf[c] = f.eps_inf;
+      if (status) status[c] = (int8_t)f.status;
+      if (weights) for (int i = 0; i < N; ++i) weights[c * ld + i] = f.w[i];
+    }
+  }
+  return 0;
+}
+
+// Batched adjoint.  grad_cost (NULL = ones) weights each candidate; the target
+// gradients are summed over the candidates of each material (layout of omega).
+int orc_fit_grad_batch(int32_t M, const int64_t *f_off, const int64_t *cand_off, const int32_t *n_poles,
+                       const double *omega, const double *eps_re, const double *eps_im,
+                       const double *theta, int64_t ld, double damping, uint32_t flags,
+                       const double *grad_cost, double *cost, double *grad_theta, double *grad_re,
+                       double *grad_im, int8_t *status, int nthreads) {
+  const int64_t P = cand_off[M];
+  std::vector<GradOut> all(P);
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads_or_default(nthreads))
+  for (int64_t c = 0; c < P; ++c) {
+    int m = mat_of(cand_off, M, c);
+    int64_t a = f_off[m], F = f_off[m + 1] - f_off[m];
+    int N = n_poles[m];
+    all[c] = fit_grad(F, omega + a, eps_re + a, eps_im + a, N, theta + c * ld, damping, flags);
+    double gc = grad_cost ? grad_cost[c] : 1.0;
+    if (cost) cost[c] = all[c].cost;
+    if (status) status[c] = (int8_t)all[c].status;
+    if (grad_theta) for (int i = 0; i < N; ++i) grad_theta[c * ld + i] = gc * all[c].g_theta[i];
+  }
+  if (grad_re || grad_im) {
+    for (int32_t m = 0; m < M; ++m) {
+      int64_t a = f_off[m], F = f_off[m + 1] - f_off[m];
+      for (int64_t k = 0; k < F; ++k) {
+        double sr = 0, si = 0;
+        for (int64_t c = cand_off[m]; c < cand_off[m + 1]; ++c) {
+          double gc = grad_cost ? grad_cost[c] : 1.0;
+          sr += gc * all[c].g_re[k];
+          si += gc * all[c].g_im[k];
+        }
+        if (grad_re) grad_re[a + k] = sr;
+        if (grad_im) grad_im[a + k] = si;
+      }
+    }
+  }
+  return 0;
+}
+
+// Complex-step derivative of the cost of one candidate: with respect to every
+// log10 tau (grad_theta[N]) and every target value (grad_re/grad_im[F]).
+int orc_fit_cs_grad(int64_t F, const double *omega, const double *eps_re, const double *eps_im, int32_t N,
+                    const double *theta, double damping, uint32_t flags, double h, double *grad_theta,
+                    double *grad_re, double *grad_im) {
+  std::vector<cd> th(N), er(F), ei(F);
+  for (int i = 0; i < N; ++i) th[i] = theta[i];
+  for (int64_t k = 0; k < F; ++k) { er[k] = eps_re[k]; ei[k] = eps_im[k]; }
+  if (grad_theta) {
+    for (int i = 0; i < N; ++i) {
+      th[i] = cd(theta[i], h);
+      Fit<cd> f = fit_forward<cd>(F, omega, er.data(), ei.data(), N, th.data(), damping, flags);
+      grad_theta[i] = f.cost.imag() / h;
+      th[i] = theta[i];
+    }
+  }
+  if (grad_re || grad_im) {
+    for (int64_t k = 0; k < F; ++k) {
+      if (grad_re) {
+        er[k] = cd(eps_re[k], h);
+        Fit<cd> f = fit_forward<cd>(F, omega, er.data(), ei.data(), N, th.data(), damping, flags);
+        grad_re[k] = f.cost.imag() / h;
+        er[k] = eps_re[k];
+      }
+      if (grad_im) {
+        ei[k] = cd(eps_im[k], h);
+        Fit<cd> f = fit_forward<cd>(F, omega, er.data(), ei.data(), N, th.data(), damping, flags);
+        grad_im[k] = f.cost.imag() / h;
+        ei[k] = eps_im[k];
+      }
+    }
+  }
+  return 0;
+}
+
+// Per-candidate internals for tests: unflipped LS solution z, scaling d and
+// the residuals.  Returns the status.
+int orc_fit_detail(int64_t F, const double *omega, const double *eps_re, const double *eps_im, int32_t N,
+                   const double *theta, double damping, uint32_t flags, double *z, double *d,
+                   double *rre, double *rim) {
+  Fit<double> f = fit_forward<double>(F, omega, eps_re, eps_im, N, theta, damping, flags);
+  if (f.status != ST_OK) return f.status;
+  for (int i = 0; i < N; ++i) { if (z) z[i] = f.z[i]; if (d) d[i] = f.d[i]; }
+  for (int64_t k = 0; k < F; ++k) { if (rre) rre[k] = f.rre[k]; if (rim) rim[k] = f.rim[k]; }
+  return f.status;
+}
+
+// ---------------------------------------------------------------------------
+// Particle swarm over log10 tau (one swarm per material).
+//   init:  x = lb + (ub-lb) u0,  v = (ub-lb) (2 u1 - 1),  pbest_x = x,
+//          best costs = +inf, no global best yet (gbest_idx = -1)
+//          u0,u1 from Philox(key=(seed, m), ctr=(d, p, 0, STREAM_PSO_INIT)) words 0,1
+//   step t (t >= 1) after the swarm has been evaluated (cost[c] = f(x_c)):
+//     pbest: strict improvement; gbest: lowest-index argmin of pbest if strictly
+//     better; history[m*hist_ld + t-1] = gbest cost;
+//     move (if requested):  r1,r2 from Philox(key=(seed,m), ctr=(d,p,t,STREAM_PSO_STEP))
+//       v = ((inertia*v) + ((c1*r1)*(pbest-x))) + ((c2*r2)*(gbest-x));  x = clamp(x+v)
+// ---------------------------------------------------------------------------
+int orc_pso_init(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int64_t ld, const double *lb,
+                 const double *ub, uint64_t seed, double *x, double *v, double *pbest_x,
+                 double *pbest_cost, double *gbest_cost, int64_t *gbest_idx) {
+  for (int32_t m = 0; m < M; ++m) {
+    for (int64_t c = cand_off[m]; c < cand_off[m + 1]; ++c) {
+      int64_t p = c - cand_off[m];
+      for (int d = 0; d < n_poles[m]; ++d) {
+        uint64_t ctr[4] = {(uint64_t)d, (uint64_t)p, 0, STREAM_PSO_INIT}, key[2] = {seed, (uint64_t)m}, r[4];
+        philox4x64_10(ctr, key, r);
+        double span = ub[m] - lb[m];
+        x[c * ld + d] = lb[m] + span * u01(r[0]);
+        v[c * ld + d] = span * (2.0 * u01(r[1]) - 1.0);
+        pbest_x[c * ld + d] = x[c * ld + d];
+      }
+      pbest_cost[c] = INFINITY;
+    }
+    gbest_cost[m] = INFINITY;
+    gbest_idx[m] = -1;
+  }
+  return 0;
+}
+
+int orc_pso_step(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int64_t ld, const double *lb,
+                 const double *ub, double inertia, double c1, double c2, uint64_t seed, int32_t t,
+                 int32_t move, const double *cost, double *x, double *v, double *pbest_x,
+                 double *pbest_cost, double *gbest_x, double *gbest_cost, int64_t *gbest_idx,
+                 double *history, int64_t hist_ld) {
+  for (int32_t m = 0; m < M; ++m) {
+    const int N = n_poles[m];
+    const int64_t c0 = cand_off[m], c1e = cand_off[m + 1];
+    for (int64_t c = c0; c < c1e; ++c) {
+      if (cost[c] < pbest_cost[c]) {
+        pbest_cost[c] = cost[c];
+        for (int d = 0; d < N; ++d) pbest_x[c * ld + d] = x[c * ld + d];
+      }
+    }
+    // lowest-index argmin of the personal bests (NaN never wins)
+    int64_t best = -1;
+    for (int64_t c = c0; c < c1e; ++c) {
+      if (std::isnan(pbest_cost[c])) continue;
+      if (best < 0 || pbest_cost[c] < pbest_cost[best]) best = c;
+    }
+    if (best >= 0 && pbest_cost[best] < gbest_cost[m]) {
+      gbest_cost[m] = pbest_cost[best];
+      gbest_idx[m] = best - c0;
+      for (int d = 0; d < N; ++d) gbest_x[m * ld + d] = pbest_x[best * ld + d];
+    }
+    if (history) history[m * hist_ld + (t - 1)] = gbest_cost[m];
+    if (!move) continue;
+    for (int64_t c = c0; c < c1e; ++c) {
+      int64_t p = c - c0;
+      for (int d = 0; d < N; ++d) {
+        uint64_t ctr[4] = {(uint64_t)d, (uint64_t)p, (uint64_t)t, STREAM_PSO_STEP}, key[2] = {seed, (uint64_t)m}, r[4];
+        philox4x64_10(ctr, key, r);
+        double r1 = u01(r[0]), r2 = u01(r[1]);
+        double xi = x[c * ld + d];
+        double vel = inertia * v[c * ld + d];
+        vel = vel + (c1 * r1) * (pbest_x[c * ld + d] - xi);
+        // a swarm with no finite cost yet has no global best: no social term
+        if (gbest_idx[m] >= 0) vel = vel + (c2 * r2) * (gbest_x[m * ld + d] - xi);
+        v[c * ld + d] = vel;
+        double xn = xi + vel;
+        xn = xn < lb[m] ? lb[m] : (xn > ub[m] ? ub[m] : xn);
+        x[c * ld + d] = xn;
+      }
+    }
+  }
+  return 0;
+}
+
+// L-BFGS polish of one candidate per material (theta[m*ld + i], in place).
+// cost_hist (optional) receives steps+1 values per material.
+int orc_lbfgs_batch(int32_t M, const int64_t *f_off, const int32_t *n_poles, const double *omega,
+                    const double *eps_re, const double *eps_im, double *theta, int64_t ld, double damping,
+                    uint32_t flags, int32_t steps, int32_t mem, int32_t max_trials, double c1,
+                    double *cost_hist, int nthreads) {
+  LbfgsCfg cfg{steps, mem, max_trials, c1};
+#pragma omp parallel for schedule(dynamic) num_threads(nthreads_or_default(nthreads))
+  for (int32_t m = 0; m < M; ++m) {
+    int64_t a = f_off[m], F = f_off[m + 1] - f_off[m];
+    lbfgs_one(F, omega + a, eps_re + a, eps_im + a, n_poles[m], theta + m * ld, damping, flags, cfg,
+              cost_hist ? cost_hist + (size_t)m * (steps + 1) : nullptr);
+  }
+  return 0;
+}
+
+// Average fractional error (Sec. IV): mean |r'|/|eps'| + mean |r''|/|eps''|,
+// in percent, for the model eps_inf + sum_n d_eps_n / (1 + j w tau_n).
+// Frequencies with eps'' == 0 are left out of the imaginary mean.
+double orc_afe(int64_t F, const double *omega, const double *eps_re, const double *eps_im, int32_t N,
+               const double *d_eps, const double *tau, double eps_inf) {
+  double sr = 0, si = 0;
+  int64_t ni = 0;
+  for (int64_t k = 0; k < F; ++k) {
+    cd model(eps_inf, 0.0);
+    for (int i = 0; i < N; ++i) model += d_eps[i] / cd(1.0, omega[k] * tau[i]);
+    double mr = model.real(), mi = -model.imag();
+    sr += std::fabs(eps_re[k] - mr) / std::fabs(eps_re[k]);
+    if (eps_im[k] != 0) { si += std::fabs(eps_im[k] - mi) / std::fabs(eps_im[k]); ++ni; }
+  }
+  return 100.0 * (sr / (double)F + (ni ? si / (double)ni : 0.0));
+}
+
+int orc_num_threads(void) { return nthreads_or_default(0); }
+
+} // extern "C"

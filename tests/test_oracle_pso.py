@@ -1,0 +1,136 @@
+"""Pins of the oracle's counter-based RNG (against numpy's Philox), the particle
+swarm (a hand-worked step and invariants) and the L-BFGS polish."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+@pytest.mark.parametrize("ctr,key", [([0, 0, 0, 0], [0, 0]), ([5, 7, 11, 2], [123, 456]),
+                                     ([2**64 - 1, 3, 2**63, 1], [2**64 - 2, 99])])
+def test_philox_matches_numpy(orc, ctr, key):
+    # numpy's Philox is 4x64-10; it advances the counter before producing a block
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                          counter=np.array(ctr, dtype=np.uint64))
+    want = bg.random_raw(4)
+    c1 = list(ctr)
+    c1[0] = (c1[0] + 1) % 2**64
+    if c1[0] == 0:
+        c1[1] = (c1[1] + 1) % 2**64
+    got = orc.philox4x64_10(c1, key)
+    np.testing.assert_array_equal(got, want)
+
+
+def _u01(r):
+    return float(int(r) >> 11) * 2.0 ** -53
+
+
+def test_pso_hand_worked_two_particles(orc):
+    # one material, two particles, one dimension
+    cand_off = [0, 2]
+    n_poles = [1]
+    lb, ub = [-12.0], [-6.0]
+    seed = 42
+    sw = orc.Swarm(2, 1, 1, 4)
+    orc.pso_init(cand_off, n_poles, lb, ub, seed, sw)
+    for p in range(2):
+        r = orc.philox4x64_10([0, p, 0, 0], [seed, 0])
+        assert sw.x[p, 0] == -12.0 + 6.0 * _u01(r[0])
+        assert sw.v[p, 0] == 6.0 * (2.0 * _u01(r[1]) - 1.0)
+        assert sw.pbest_x[p, 0] == sw.x[p, 0]
+    assert np.all(sw.pbest_cost == np.inf) and sw.gbest_cost[0] == np.inf and sw.gbest_idx[0] == -1
+    x0, v0 = sw.x.copy(), sw.v.copy()
+    cost = np.array([3.0, 2.0])
+    orc.pso_step(cand_off, n_poles, lb, ub, 0.7, 1.5, 1.5, seed, 1, True, cost, sw)
+    assert list(sw.pbest_cost) == [3.0, 2.0]
+    assert sw.gbest_cost[0] == 2.0 and sw.gbest_idx[0] == 1 and sw.gbest_x[0, 0] == x0[1, 0]
+    assert sw.history[0, 0] == 2.0
+    for p in range(2):
+        r = orc.philox4x64_10([0, p, 1, 1], [seed, 0])
+        r1, r2 = _u01(r[0]), _u01(r[1])
+        vel = 0.7 * v0[p, 0]
+        vel = vel + (1.5 * r1) * (x0[p, 0] - x0[p, 0])
+        vel = vel + (1.5 * r2) * (x0[1, 0] - x0[p, 0])
+        assert sw.v[p, 0] == vel
+        assert sw.x[p, 0] == min(max(x0[p, 0] + vel, -12.0), -6.0)
+    # ties: equal costs keep the earlier best; lower index wins among equals
+    x1 = sw.x.copy()
+    orc.pso_step(cand_off, n_poles, lb, ub, 0.7, 1.5, 1.5, seed, 2, False, np.array([2.0, 2.0]), sw)
+    assert list(sw.pbest_cost) == [2.0, 2.0]
+    assert sw.pbest_x[0, 0] == x1[0, 0] and sw.pbest_x[1, 0] == x0[1, 0]
+    assert sw.gbest_idx[0] == 1          # not strictly better: gbest unchanged
+    assert np.array_equal(sw.x, x1)      # bests-only step does not move
+    sw2 = orc.Swarm(2, 1, 1, 4)
+    orc.pso_init(cand_off, n_poles, lb, ub, seed, sw2)
+    orc.pso_step(cand_off, n_poles, lb, ub, 0.7, 1.5, 1.5, seed, 1, False, np.array([5.0, 5.0]), sw2)
+    assert sw2.gbest_idx[0] == 0
+    # NaN never becomes a best
+    sw3 = orc.Swarm(2, 1, 1, 4)
+    orc.pso_init(cand_off, n_poles, lb, ub, seed, sw3)
+    orc.pso_step(cand_off, n_poles, lb, ub, 0.7, 1.5, 1.5, seed, 1, True, np.array([np.nan, np.nan]), sw3)
+    assert np.all(sw3.pbest_cost == np.inf) and sw3.gbest_idx[0] == -1
+    assert np.all(np.isfinite(sw3.x))
+
+
+def test_pso_invariants_and_resume(orc):
+    wl = W.mixed_uniform(M=3, F=120, N=4, P=24, iters=12, seed=1)
+    er, ei = orc.material_eval(wl.kind, wl.params, wl.f_off, wl.omega)
+    b = orc.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, er, ei)
+    sw = orc.pso_run(b, wl.lb, wl.ub, wl.iters, seed=3)
+    assert np.all(sw.x >= wl.lb[0]) and np.all(sw.x <= wl.ub[0])
+    h = sw.history
+    assert np.all(np.diff(h, axis=1) <= 0)                      # gbest never worsens
+    for m in range(wl.M):
+        a, e = wl.cand_off[m], wl.cand_off[m + 1]
+        assert sw.gbest_cost[m] == sw.pbest_cost[a:e].min()
+        c = orc.fit_eval(orc.Batch(wl.f_off[m:m + 2] - wl.f_off[m], [0, 1], wl.n_poles[m:m + 1],
+                                   wl.omega[wl.f_off[m]:wl.f_off[m + 1]], er[wl.f_off[m]:wl.f_off[m + 1]],
+                                   ei[wl.f_off[m]:wl.f_off[m + 1]]), sw.gbest_x[m:m + 1])[0]
+        assert c[0] == sw.gbest_cost[m]
+    # counter-based RNG: stopping and resuming from saved state is bit-exact
+    s1 = orc.Swarm(b.P, b.M, 4, 13)
+    orc.pso_init(b.cand_off, b.n_poles, wl.lb, wl.ub, 3, s1)
+    cost = orc.fit_eval(b, s1.x)[0]
+    for t in range(1, 7):
+        orc.pso_step(b.cand_off, b.n_poles, wl.lb, wl.ub, 0.7, 1.5, 1.5, 3, t, True, cost, s1)
+        cost = orc.fit_eval(b, s1.x)[0]
+    saved, saved_cost = s1.copy(), cost.copy()
+    for t in range(7, 13):
+        orc.pso_step(b.cand_off, b.n_poles, wl.lb, wl.ub, 0.7, 1.5, 1.5, 3, t, True, saved_cost, saved)
+        saved_cost = orc.fit_eval(b, saved.x)[0]
+    orc.pso_step(b.cand_off, b.n_poles, wl.lb, wl.ub, 0.7, 1.5, 1.5, 3, 13, False, saved_cost, saved)
+    np.testing.assert_array_equal(saved.x, sw.x)
+    np.testing.assert_array_equal(saved.gbest_cost, sw.gbest_cost)
+
+
+def test_pso_finds_single_pole_global_minimum(orc):
+    om = W.log_grid(1e6, 1e10, 200)
+    params = np.zeros((1, 16))
+    params[0, :5] = [3.0, 20.0, 1e-9, 0.8, 0.7]
+    er, ei = orc.material_eval([W.KIND_HN], params, [0, 200], om)
+    grid = np.arange(-12, -7, 1e-4)
+    gb = orc.Batch([0, 200], [0, len(grid)], [1], om, er, ei)
+    cmin = orc.fit_eval(gb, grid[:, None])[0].min()
+    b = orc.Batch([0, 200], [0, 20], [1], om, er, ei)
+    sw = orc.pso_run(b, [-12.0], [-7.0], 30, seed=0)
+    assert sw.gbest_cost[0] <= cmin * (1 + 1e-6)
+    # polishing from there keeps it at the grid minimum with a vanishing gradient
+    th, hist = orc.lbfgs(orc.Batch([0, 200], [0, 1], [1], om, er, ei), sw.gbest_x, steps=10)
+    assert hist[0, -1] <= cmin
+    _, g, _, _, _ = orc.fit_grad(orc.Batch([0, 200], [0, 1], [1], om, er, ei), th)
+    assert abs(g[0, 0]) < 1e-6 * hist[0, -1]
+
+
+def test_lbfgs_monotone_and_improves(orc):
+    wl = W.hn_cc(M=3, F=300, N=6, P=32, iters=10, seed=2)
+    er, ei = orc.material_eval(wl.kind, wl.params, wl.f_off, wl.omega)
+    b = orc.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, er, ei)
+    sw = orc.pso_run(b, wl.lb, wl.ub, wl.iters, seed=5)
+    bm = orc.Batch(wl.f_off, np.arange(wl.M + 1), wl.n_poles, wl.omega, er, ei)
+    th, hist = orc.lbfgs(bm, sw.gbest_x, steps=30)
+    assert np.all(np.diff(hist, axis=1) <= 0)
+    assert np.all(hist[:, -1] < 0.9 * hist[:, 0])
+    c = orc.fit_eval(bm, th)[0]
+    np.testing.assert_array_equal(c, hist[:, -1])
