@@ -1,0 +1,255 @@
+/*
+ * debyefit.h - C ABI of the MI355X (gfx950) library for the batched
+ * multi-pole Debye fitting method of Majchrowska, Giannakis, Warren and
+ * Giannopoulos, "Modelling Arbitrary Complex Dielectric Properties - an
+ * automated implementation for gprMax" (2021).
+ *
+ * The method (Sec. III-B) fits  eps(w) = eps_inf + sum_n d_eps_n / (1 + j w tau_n)
+ * (Eq. 7, with eps = eps' - j eps'' as in Eq. 1) to a target spectrum.  A
+ * global optimiser searches the relaxation times; for every candidate set
+ * the pole weights come from a damped least-squares (DLS) fit to the loss
+ * part eps'', negative weights are flipped to positive as a penalty, eps_inf
+ * is the mean real-part misfit and the cost is the sum of squared real and
+ * imaginary residuals over the frequency points.
+ *
+ * Conventions for every entry point
+ *  - All array pointers are DEVICE pointers unless the name ends in _host.
+ *    The caller owns every buffer; the library neither frees nor keeps them
+ *    after the call returns (a plan keeps only its own buffers).
+ *  - Calls enqueue work on `stream` and return without synchronising.
+ *  - Return value: DEBYE_OK (0) or a negative DEBYE_E* code.  Argument errors
+ *    are detected on the host before anything is enqueued; the message is
+ *    available from debye_last_error() (per thread).
+ *  - Numerical trouble is reported per candidate in `status` (DEBYE_ST_*).
+ *  - FP64 throughout.
+ *  - Candidate log10(tau) values and weights are stored in rows of stride
+ *    `ld` (>= the material's pole count); only the first n_poles[m] entries of
+ *    a row are read or written.
+ */
+#ifndef DEBYEFIT_H
+#define DEBYEFIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DEBYE_MAX_POLES 24
+
+/* return codes */
+enum {
+  DEBYE_OK = 0,
+  DEBYE_EINVAL = -1, /* NULL pointer, unknown enum value, shape mismatch */
+  DEBYE_ERANGE = -2, /* size out of range: M < 1, F < 1, N < 1 or N > DEBYE_MAX_POLES,
+                        ld < N, damping < 0 or not finite */
+  DEBYE_EHIP = -3,   /* HIP runtime / launch failure (text in debye_last_error) */
+  DEBYE_ENOMEM = -4  /* device allocation inside a plan failed */
+};
+
+/* per-candidate status */
+enum {
+  DEBYE_ST_OK = 0,
+  DEBYE_ST_BADINPUT = 1, /* non-finite log10(tau), |log10 tau| > 64, or non-finite
+                            omega / eps' / eps'' of the material: cost = NaN */
+  DEBYE_ST_SINGULAR = 2  /* the scaled damped normal matrix is numerically singular
+                            (only reachable with damping ~ 0, e.g. duplicate
+                            relaxation times): cost = +Inf, weights = NaN */
+};
+
+/* flags */
+enum {
+  DEBYE_FLAG_NO_SIGN_FLIP = 1u /* keep signed LS weights (w = z instead of |z|) */
+};
+
+/* material kinds for debye_material_eval (parameter rows of DEBYE_PARAM_STRIDE) */
+enum {
+  DEBYE_KIND_DEBYE = 0,    /* Eq. 3: (eps_inf, d_eps, tau0) */
+  DEBYE_KIND_HN = 1,       /* Eq. 4: (eps_inf, d_eps, tau0, alpha, beta) */
+  DEBYE_KIND_CC = 2,       /* Eq. 4 with beta = 1 (Cole-Cole): params[4] ignored */
+  DEBYE_KIND_CD = 3,       /* Eq. 4 with alpha = 1 (Cole-Davidson): params[3] ignored */
+  DEBYE_KIND_JONSCHER = 4, /* (eps_inf, chi, omega_p, n): eps_inf + chi (j w / omega_p)^(n-1) */
+  DEBYE_KIND_CRIM = 5,     /* Eq. 6 with a = 1/2: Debye water phase (eps_inf_w, d_eps_w,
+                              tau_w) at volume fraction f_w in a lossless matrix eps_m:
+                              (eps_inf_w, d_eps_w, tau_w, f_w, eps_m) */
+  DEBYE_KIND_HNSUM = 6     /* tabulated-style data: eps_inf + up to three HN terms,
+                              (eps_inf, n_terms, [d_eps, tau0, alpha, beta] x 3 at
+                              params[2..13], noise at params[14]); values are multiplied
+                              by (1 + noise * g) with g standard normal (Box-Muller on
+                              Philox4x64-10, key (noise_seed, m), counter (k, 0, 0, 2)) */
+};
+#define DEBYE_PARAM_STRIDE 16
+
+/* ------------------------------------------------------------------------
+ * Ragged batch of materials.  Material m owns frequency points
+ * [f_off[m], f_off[m+1]) of omega/eps_re/eps_im and candidates
+ * [cand_off[m], cand_off[m+1]); it is fitted with n_poles[m] poles.
+ * ------------------------------------------------------------------------ */
+typedef struct debye_batch {
+  int32_t n_mat;           /* M >= 1 */
+  int32_t max_poles;       /* max_m n_poles[m] (host value), 1..DEBYE_MAX_POLES */
+  int64_t n_freq;          /* f_off[M] (host value) */
+  int64_t n_cand;          /* cand_off[M] (host value) */
+  const int64_t *f_off;    /* [M+1] device */
+  const int64_t *cand_off; /* [M+1] device */
+  const int32_t *n_poles;  /* [M]   device */
+  const double *omega;     /* [n_freq] angular frequency 2 pi f (rad/s), > 0 */
+  const double *eps_re;    /* [n_freq] eps'  */
+  const double *eps_im;    /* [n_freq] eps'' (loss, >= 0 for passive media) */
+} debye_batch;
+
+/* A plan holds the launch schedule for one batch shape: candidates grouped by
+ * pole count, lanes per candidate, work lists sorted by cost (longest first),
+ * and workspace.  Build it once per shape from HOST copies of the offsets;
+ * reuse it for every call on batches of that shape (e.g. every iteration of
+ * an optimiser).  `flags` is reserved (0). */
+typedef struct debye_plan debye_plan;
+
+int debye_plan_create(const debye_batch *shape, const int64_t *f_off_host, const int64_t *cand_off_host,
+                      const int32_t *n_poles_host, uint32_t flags, debye_plan **out);
+int debye_plan_destroy(debye_plan *plan);
+
+/* Override the schedule's frequency split (lanes per candidate along the
+ * frequency axis, a power of two; 0 restores the automatic choice) for pole
+ * count n_poles (0 = all). Used by the autotuner and the tests. */
+int debye_plan_set_freq_split(debye_plan *plan, int32_t n_poles, int32_t split);
+
+/* Schedule introspection: with i < 0 returns the number of pole-count buckets;
+ * otherwise fills the pole count, pole split, frequency split and number of
+ * work tiles of bucket i. */
+int debye_plan_info(const debye_plan *plan, int32_t i, int32_t *n_poles, int32_t *pole_split, int32_t *freq_split,
+                    int64_t *n_tiles);
+
+/* Text of the last error on this thread ("" if none). */
+const char *debye_last_error(void);
+
+/* Library version string. */
+const char *debye_version(void);
+
+/* ------------------------------------------------------------------------
+ * Debye basis (Eq. 7 split by Eq. 1): for every candidate c and pole i,
+ *   x = omega[k] * 10^log10_tau[c*ld+i],  re[(c*N+i)*F+k] = 1/(1+x^2),
+ *   im[(c*N+i)*F+k] = x/(1+x^2).
+ * omega [F], log10_tau [n_cand][ld], re/im [n_cand][N][F].
+ * ------------------------------------------------------------------------ */
+int debye_basis(const double *omega, int64_t F, const double *log10_tau, int64_t ld, int64_t n_cand,
+                int32_t N, double *re, double *im, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Cost evaluation (Sec. III-B), one result per candidate c of material m:
+ *   tau_i = 10^log10_tau[c*ld+i]; R_ki = 1/(1+x^2), I_ki = x/(1+x^2), x = w_k tau_i
+ *   z   = argmin || I z - eps'' ||^2 + damping * sum_i (||I_:,i|| z_i)^2
+ *         (damped least squares with Marquardt column scaling)
+ *   w_i = |z_i|  (unless DEBYE_FLAG_NO_SIGN_FLIP)
+ *   eps_inf = mean_k (eps'_k - sum_i w_i R_ki)
+ *   cost = sum_k (eps'_k - eps_inf - sum_i w_i R_ki)^2 + (eps''_k - sum_i w_i I_ki)^2
+ * Outputs (each may be NULL except cost): cost [n_cand], weights [n_cand][ld]
+ * (the fitted d_eps_i = w_i), eps_inf [n_cand], status [n_cand].
+ * damping >= 0 (1e-8 is the library default used by the optimisers).
+ * ------------------------------------------------------------------------ */
+int debye_fit_eval(const debye_plan *plan, const debye_batch *b, const double *log10_tau, int64_t ld,
+                   double damping, uint32_t flags, double *cost, double *weights, double *eps_inf,
+                   int8_t *status, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Cost and its variable-projection adjoint.  With M = I^T I + damping diag(I^T I),
+ * M z = I^T eps'', s = sign(z) (1 without the flip), r', r'' the residuals:
+ *   g_w = -2 (R^T r' + I^T r''),  mu = M^-1 (s o g_w)
+ *   dC/dlog10tau_i = -2 w_i (dR_i.r' + dI_i.r'') + mu_i dI_i.(eps'' - I z)
+ *                    - z_i dI_i.(I mu) - 2 damping mu_i z_i dI_i.I_i
+ *   dC/deps'_k = 2 r'_k,  dC/deps''_k = 2 r''_k + (I mu)_k
+ * (dR/dlog10tau = -2 ln10 x^2 R^2, dI/dlog10tau = ln10 x R^2 (1 - x^2)).
+ * grad_cost [n_cand] (NULL = all ones) scales each candidate.
+ * grad_log10_tau [n_cand][ld] receives grad_cost[c] * dC/dlog10tau.
+ * grad_eps_re / grad_eps_im [n_freq] (both NULL or both set) receive the target
+ * gradients summed over the candidates of each material (fixed order, so the
+ * result is deterministic).
+ * ------------------------------------------------------------------------ */
+int debye_fit_eval_grad(const debye_plan *plan, const debye_batch *b, const double *log10_tau, int64_t ld,
+                        double damping, uint32_t flags, const double *grad_cost, double *cost,
+                        double *grad_log10_tau, double *grad_eps_re, double *grad_eps_im, int8_t *status,
+                        hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Target synthesis (Eqs. 3-6): eps_re/eps_im [n_freq] for every material
+ * (kind [M] int8, params [M][DEBYE_PARAM_STRIDE]); jac (NULL or [n_freq][5][2])
+ * receives d(eps', eps'')/d(eps_inf, d_eps, tau0, alpha, beta) for the
+ * Debye/HN/CC/CD kinds (NaN for the others).
+ * ------------------------------------------------------------------------ */
+int debye_material_eval(int32_t M, const int8_t *kind, const double *params, const int64_t *f_off,
+                        int64_t n_freq, const double *omega, uint64_t noise_seed, double *eps_re,
+                        double *eps_im, double *jac, hipStream_t stream);
+
+/* Material-parameter gradient (chain rule through Eq. 4): for every material
+ * m, grad_params[m][q] = sum_k jac[k][q][0] grad_re[k] + jac[k][q][1] grad_im[k]
+ * over its frequency points, q = eps_inf, d_eps, tau0, alpha, beta; entries
+ * 5..15 of each row are set to 0.  jac as produced by debye_material_eval;
+ * grad_re/grad_im [n_freq] (e.g. the target gradients of debye_fit_eval_grad);
+ * grad_params [M][DEBYE_PARAM_STRIDE].  Deterministic (fixed reduction order). */
+int debye_material_vjp(int32_t M, const int64_t *f_off, int64_t n_freq, const double *jac, const double *grad_re,
+                       const double *grad_im, double *grad_params, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Particle swarm over log10(tau), one swarm per material (Sec. III-A/B: PSO
+ * for the relaxation times, Kennedy & Eberhart).  Random numbers are
+ * Philox4x64-10 (Salmon et al. 2011) words with key (seed, m) and counter
+ * (dimension, particle, iteration, stream), u = (word >> 11) * 2^-53.
+ *
+ * pso_init: x = lb + (ub-lb) u0, v = (ub-lb)(2 u1 - 1) from counter (d, p, 0, 0);
+ *   pbest_x = x; pbest_cost = +Inf; gbest_cost = +Inf; gbest_idx = -1.
+ * pso_step (after `cost` = f(x) for the whole swarm), iteration t >= 1:
+ *   pbest updated where cost < pbest_cost (strictly; NaN never wins);
+ *   the lowest-index minimum of pbest_cost replaces the global best if strictly
+ *   better; history[m*hist_ld + t-1] = gbest_cost[m] (history may be NULL);
+ *   if move: r1, r2 from counter (d, p, t, 1),
+ *     v = ((inertia*v) + ((c1*r1)*(pbest-x))) + ((c2*r2)*(gbest-x))
+ *     (the social term is omitted while gbest_idx < 0), x = clamp(x + v, lb, ub).
+ *   Evaluation order is fixed and no fused multiply-add is used, so results
+ *   are bit-reproducible.
+ * lb, ub [M]; x, v, pbest_x [n_cand][ld]; pbest_cost [n_cand];
+ * gbest_x [M][ld]; gbest_cost [M]; gbest_idx [M] (index within the material).
+ * ------------------------------------------------------------------------ */
+typedef struct debye_pso_params {
+  double inertia, c1, c2;
+  uint64_t seed;
+} debye_pso_params;
+
+int debye_pso_init(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_pso_params p,
+                   double *x, double *v, double *pbest_x, double *pbest_cost, double *gbest_cost,
+                   int64_t *gbest_idx, hipStream_t stream);
+int debye_pso_step(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_pso_params p,
+                   int32_t t, int32_t move, const double *cost, double *x, double *v, double *pbest_x,
+                   double *pbest_cost, double *gbest_x, double *gbest_cost, int64_t *gbest_idx,
+                   double *history, int64_t hist_ld, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Gradient polish: L-BFGS (Liu & Nocedal 1989; two-loop recursion, memory
+ * `mem`), Armijo backtracking alpha = 1, 1/2, ... (max_trials, constant c1),
+ * on one candidate per material, theta [M][ld] in place, inside the search box
+ * [lb[m], ub[m]] (device [M]): every trial point is projected onto the box and
+ * the sufficient-decrease test uses the projected displacement p,
+ * C(trial) <= C + c1 g.p.  The first step (and any step whose quasi-Newton
+ * direction is not a descent direction) is steepest descent scaled so that its
+ * largest component is at most 1; a step with no acceptable trial leaves theta
+ * unchanged; pairs with s.y <= 1e-300 are skipped.  All trials of a step are
+ * evaluated in one batched launch.  cost_hist [M][steps+1] (may be NULL)
+ * receives the cost before each step and at the end (non-increasing).  `b` must
+ * describe one candidate per material (cand_off[m] = m).  The call allocates
+ * and frees its own workspace and synchronises `stream` before returning.
+ * ------------------------------------------------------------------------ */
+typedef struct debye_lbfgs_params {
+  int32_t steps, mem, max_trials;
+  double c1;
+} debye_lbfgs_params;
+
+int debye_lbfgs_polish(const debye_batch *b, const int64_t *f_off_host, const int32_t *n_poles_host,
+                       double *theta, int64_t ld, const double *lb, const double *ub, double damping,
+                       uint32_t flags, debye_lbfgs_params p, double *cost_hist, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEBYEFIT_H */

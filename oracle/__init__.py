@@ -57,7 +57,7 @@ def lib():
         L.orc_pso_step.argtypes = [C.c_int32, _i64, _i32, C.c_int64, _d, _d, C.c_double, C.c_double,
                                    C.c_double, C.c_uint64, C.c_int32, C.c_int32, _d, _d, _d, _d, _d,
                                    _d, _d, _i64, _d, C.c_int64]
-        L.orc_lbfgs_batch.argtypes = [C.c_int32, _i64, _i32, _d, _d, _d, _d, C.c_int64, C.c_double,
+        L.orc_lbfgs_batch.argtypes = [C.c_int32, _i64, _i32, _d, _d, _d, _d, C.c_int64, _d, _d, C.c_double,
                                       C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_double, _d, C.c_int]
         L.orc_afe.argtypes = [C.c_int64, _d, _d, _d, C.c_int32, _d, _d, C.c_double]
         L.orc_afe.restype = C.c_double
@@ -248,14 +248,18 @@ def pso_run(b: Batch, lb, ub, iters, inertia=0.7, c1=1.5, c2=1.5, seed=0, ld=Non
     return sw
 
 
-def lbfgs(b: Batch, theta, steps=50, mem=10, max_trials=30, c1=1e-4, damping=1e-8, flags=0, nthreads=0):
-    """L-BFGS polish of one candidate per material (theta[M][ld]); returns the
-    polished theta and the cost history [M][steps+1]."""
+def lbfgs(b: Batch, theta, lb, ub, steps=50, mem=10, max_trials=30, c1=1e-4, damping=1e-8, flags=0,
+          nthreads=0):
+    """L-BFGS polish of one candidate per material (theta[M][ld]) inside the
+    box [lb[m], ub[m]]; returns the polished theta and the cost history
+    [M][steps+1]."""
     th = _f64(theta).copy()
+    lb = _f64(np.broadcast_to(lb, (b.M,)))
+    ub = _f64(np.broadcast_to(ub, (b.M,)))
     hist = np.empty((b.M, steps + 1))
     lib().orc_lbfgs_batch(b.M, _p(b.f_off, _i64), _p(b.n_poles, _i32), _p(b.omega, _d), _p(b.eps_re, _d),
-                          _p(b.eps_im, _d), _p(th, _d), th.shape[1], damping, flags, steps, mem,
-                          max_trials, c1, _p(hist, _d), nthreads)
+                          _p(b.eps_im, _d), _p(th, _d), th.shape[1], _p(lb, _d), _p(ub, _d), damping, flags,
+                          steps, mem, max_trials, c1, _p(hist, _d), nthreads)
     return th, hist
 
 

@@ -467,7 +467,8 @@ struct LbfgsCfg {
 };
 
 int lbfgs_one(int64_t F, const double *omega, const double *eps_re, const double *eps_im, int N,
-              double *theta, double damping, unsigned flags, const LbfgsCfg &cfg, double *cost_hist) {
+              double *theta, double lb, double ub, double damping, unsigned flags, const LbfgsCfg &cfg,
+              double *cost_hist) {
   std::vector<double> th(theta, theta + N);
   GradOut g = fit_grad(F, omega, eps_re, eps_im, N, th.data(), damping, flags);
   double C = g.cost;
@@ -512,16 +513,23 @@ int lbfgs_one(int64_t F, const double *omega, const double *eps_re, const double
       gd = 0;
       for (int i = 0; i < N; ++i) { d[i] = -grad[i] * sc; gd += grad[i] * d[i]; }
     }
-    // Armijo backtracking: alpha = 1, 1/2, 1/4, ...
+    // Armijo backtracking alpha = 1, 1/2, 1/4, ... on the search box: the trial
+    // point is projected onto [lb, ub] and the sufficient-decrease test uses the
+    // projected displacement p:  C(trial) <= C + c1 g.p
     double alpha = 1.0;
     bool ok = false;
     std::vector<double> tt(N);
     double Ct = 0;
     for (int t = 0; t < cfg.max_trials; ++t) {
-      for (int i = 0; i < N; ++i) tt[i] = th[i] + alpha * d[i];
+      double gp = 0;
+      for (int i = 0; i < N; ++i) {
+        double v = th[i] + alpha * d[i];
+        tt[i] = v < lb ? lb : (v > ub ? ub : v);
+        gp += grad[i] * (tt[i] - th[i]);
+      }
       Fit<double> ft = fit_forward<double>(F, omega, eps_re, eps_im, N, tt.data(), damping, flags);
       Ct = ft.cost;
-      if (ft.status == ST_OK && Ct <= C + cfg.c1 * alpha * gd) { ok = true; break; }
+      if (ft.status == ST_OK && Ct <= C + cfg.c1 * gp) { ok = true; break; }
       alpha *= 0.5;
     }
     if (!ok) continue;
@@ -534,7 +542,7 @@ int lbfgs_one(int64_t F, const double *omega, const double *eps_re, const double
       if ((int)S.size() > cfg.mem) { S.erase(S.begin()); Y.erase(Y.begin()); rho.erase(rho.begin()); }
     }
     th = tt;
-    C = gt.cost;
+    C = Ct;
     grad = gt.g_theta;
     g = gt;
     ++taken;
@@ -797,17 +805,18 @@ int orc_pso_step(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int
   return 0;
 }
 
-// L-BFGS polish of one candidate per material (theta[m*ld + i], in place).
-// cost_hist (optional) receives steps+1 values per material.
+// L-BFGS polish of one candidate per material (theta[m*ld + i], in place),
+// kept inside the search box [lb[m], ub[m]].  cost_hist (optional) receives
+// steps+1 values per material.
 int orc_lbfgs_batch(int32_t M, const int64_t *f_off, const int32_t *n_poles, const double *omega,
-                    const double *eps_re, const double *eps_im, double *theta, int64_t ld, double damping,
-                    uint32_t flags, int32_t steps, int32_t mem, int32_t max_trials, double c1,
-                    double *cost_hist, int nthreads) {
+                    const double *eps_re, const double *eps_im, double *theta, int64_t ld, const double *lb,
+                    const double *ub, double damping, uint32_t flags, int32_t steps, int32_t mem,
+                    int32_t max_trials, double c1, double *cost_hist, int nthreads) {
   LbfgsCfg cfg{steps, mem, max_trials, c1};
 #pragma omp parallel for schedule(dynamic) num_threads(nthreads_or_default(nthreads))
   for (int32_t m = 0; m < M; ++m) {
     int64_t a = f_off[m], F = f_off[m + 1] - f_off[m];
-    lbfgs_one(F, omega + a, eps_re + a, eps_im + a, n_poles[m], theta + m * ld, damping, flags, cfg,
+    lbfgs_one(F, omega + a, eps_re + a, eps_im + a, n_poles[m], theta + m * ld, lb[m], ub[m], damping, flags, cfg,
               cost_hist ? cost_hist + (size_t)m * (steps + 1) : nullptr);
   }
   return 0;

@@ -1,0 +1,333 @@
+"""Python binding of the MI355X (gfx950) Debye fitting library.
+
+Majchrowska et al., "Modelling Arbitrary Complex Dielectric Properties - an
+automated implementation for gprMax": the multi-pole Debye expansion (Eq. 7)
+is fitted by a hybrid scheme (Sec. III-B) - a swarm optimiser over the
+relaxation times and a damped least-squares solve for the weights - here run
+for thousands of materials at once on one GPU.
+
+Every computation runs in the hand-written HIP kernels of ``libdebyefit.so``
+(C ABI in ``include/debyefit.h``).  This module only marshals torch device
+tensors (memory) and the current torch stream into those calls; it has no
+CPU fallback and raises if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdebyefit.so")
+
+OK, EINVAL, ERANGE, EHIP, ENOMEM = 0, -1, -2, -3, -4
+ST_OK, ST_BADINPUT, ST_SINGULAR = 0, 1, 2
+FLAG_NO_SIGN_FLIP = 1
+MAX_POLES = 24
+PARAM_STRIDE = 16
+DEFAULT_DAMPING = 1e-8
+
+EXPORTED = ["debye_plan_create", "debye_plan_destroy", "debye_plan_set_freq_split", "debye_plan_info",
+            "debye_last_error", "debye_version", "debye_basis", "debye_fit_eval", "debye_fit_eval_grad",
+            "debye_material_eval", "debye_material_vjp", "debye_pso_init", "debye_pso_step",
+            "debye_lbfgs_polish"]
+
+
+class DebyeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"debyefit error {code}: {msg}")
+        self.code = code
+
+
+class _CBatch(C.Structure):
+    _fields_ = [("n_mat", C.c_int32), ("max_poles", C.c_int32), ("n_freq", C.c_int64), ("n_cand", C.c_int64),
+                ("f_off", C.c_void_p), ("cand_off", C.c_void_p), ("n_poles", C.c_void_p),
+                ("omega", C.c_void_p), ("eps_re", C.c_void_p), ("eps_im", C.c_void_p)]
+
+
+class _CPso(C.Structure):
+    _fields_ = [("inertia", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("seed", C.c_uint64)]
+
+
+class _CLbfgs(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("mem", C.c_int32), ("max_trials", C.c_int32), ("c1", C.c_double)]
+
+
+_lib = None
+_vp = C.c_void_p
+
+
+def lib():
+    """Load libdebyefit.so (built in-tree by paper_2109_01928_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    i32, i64, dbl, u32 = C.c_int32, C.c_int64, C.c_double, C.c_uint32
+    L.debye_last_error.restype = C.c_char_p
+    L.debye_version.restype = C.c_char_p
+    L.debye_plan_create.argtypes = [C.POINTER(_CBatch), _vp, _vp, _vp, u32, C.POINTER(_vp)]
+    L.debye_plan_destroy.argtypes = [_vp]
+    L.debye_plan_set_freq_split.argtypes = [_vp, i32, i32]
+    L.debye_plan_info.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
+    L.debye_basis.argtypes = [_vp, i64, _vp, i64, i64, i32, _vp, _vp, _vp]
+    L.debye_fit_eval.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, _vp, _vp, _vp, _vp, _vp]
+    L.debye_fit_eval_grad.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.debye_material_eval.argtypes = [i32, _vp, _vp, _vp, i64, _vp, C.c_uint64, _vp, _vp, _vp, _vp]
+    L.debye_material_vjp.argtypes = [i32, _vp, i64, _vp, _vp, _vp, _vp, _vp]
+    L.debye_pso_init.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CPso, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.debye_pso_step.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CPso, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, _vp, _vp, i64, _vp]
+    L.debye_lbfgs_polish.argtypes = [C.POINTER(_CBatch), _vp, _vp, _vp, i64, _vp, _vp, dbl, u32, _CLbfgs, _vp, _vp]
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != OK:
+        raise DebyeError(rc, lib().debye_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, dtype, device):
+    return torch.as_tensor(np.asarray(x), dtype=dtype).to(device).contiguous()
+
+
+# ---------------------------------------------------------------------------
+class Batch:
+    """A ragged batch resident on the GPU: material m owns frequency points
+    f_off[m]:f_off[m+1] and candidates cand_off[m]:cand_off[m+1] and is fitted
+    with n_poles[m] poles.  Host copies of the shape are kept for planning."""
+
+    def __init__(self, f_off, cand_off, n_poles, omega, eps_re, eps_im, device="cuda"):
+        self.f_off_h = np.ascontiguousarray(np.asarray(f_off, dtype=np.int64))
+        self.cand_off_h = np.ascontiguousarray(np.asarray(cand_off, dtype=np.int64))
+        self.n_poles_h = np.ascontiguousarray(np.asarray(n_poles, dtype=np.int32))
+        self.device = device
+        self.f_off = _dev(self.f_off_h, torch.int64, device)
+        self.cand_off = _dev(self.cand_off_h, torch.int64, device)
+        self.n_poles = _dev(self.n_poles_h, torch.int32, device)
+        self.omega = omega if torch.is_tensor(omega) else _dev(omega, torch.float64, device)
+        self.eps_re = eps_re if torch.is_tensor(eps_re) else _dev(eps_re, torch.float64, device)
+        self.eps_im = eps_im if torch.is_tensor(eps_im) else _dev(eps_im, torch.float64, device)
+        self.M = len(self.n_poles_h)
+        self.P = int(self.cand_off_h[-1])
+        self.F = int(self.f_off_h[-1])
+        self.max_poles = int(self.n_poles_h.max())
+
+    def cstruct(self):
+        for t in (self.omega, self.eps_re, self.eps_im):
+            assert t.dtype == torch.float64 and t.is_contiguous() and t.numel() == self.F
+        return _CBatch(self.M, self.max_poles, self.F, self.P, self.f_off.data_ptr(), self.cand_off.data_ptr(),
+                       self.n_poles.data_ptr(), self.omega.data_ptr(), self.eps_re.data_ptr(), self.eps_im.data_ptr())
+
+    def with_targets(self, eps_re, eps_im):
+        b = object.__new__(Batch)
+        b.__dict__.update(self.__dict__)
+        b.eps_re, b.eps_im = eps_re.contiguous(), eps_im.contiguous()
+        return b
+
+
+class Plan:
+    """Launch schedule for one batch shape (see debye_plan_create)."""
+
+    def __init__(self, b: Batch):
+        self.handle = _vp()
+        cb = b.cstruct()
+        _check(lib().debye_plan_create(C.byref(cb), b.f_off_h.ctypes.data_as(_vp), b.cand_off_h.ctypes.data_as(_vp),
+                                       b.n_poles_h.ctypes.data_as(_vp), 0, C.byref(self.handle)))
+
+    def set_freq_split(self, split, n_poles=0):
+        _check(lib().debye_plan_set_freq_split(self.handle, n_poles, split))
+
+    def info(self):
+        L = lib()
+        n = L.debye_plan_info(self.handle, -1, None, None, None, None)
+        out = []
+        for i in range(n):
+            N, sp, sf = C.c_int32(), C.c_int32(), C.c_int32()
+            nt = C.c_int64()
+            _check(L.debye_plan_info(self.handle, i, C.byref(N), C.byref(sp), C.byref(sf), C.byref(nt)))
+            out.append(dict(n_poles=N.value, pole_split=sp.value, freq_split=sf.value, tiles=nt.value))
+        return out
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.debye_plan_destroy(self.handle)
+            self.handle = None
+
+
+# ---------------------------------------------------------------------------
+def fit_eval(plan: Plan, b: Batch, theta, damping=DEFAULT_DAMPING, flags=0, want_weights=True, out=None):
+    """Cost (and weights, eps_inf, status) of every candidate (debye_fit_eval)."""
+    ld = theta.shape[1]
+    P = b.P
+    dev = theta.device
+    if out is None:
+        cost = torch.empty(P, dtype=torch.float64, device=dev)
+        w = torch.empty((P, ld), dtype=torch.float64, device=dev) if want_weights else None
+        einf = torch.empty(P, dtype=torch.float64, device=dev) if want_weights else None
+        st = torch.empty(P, dtype=torch.int8, device=dev)
+    else:
+        cost, w, einf, st = out
+    cb = b.cstruct()
+    _check(lib().debye_fit_eval(plan.handle, C.byref(cb), _ptr(theta), ld, float(damping), flags, _ptr(cost), _ptr(w),
+                                _ptr(einf), _ptr(st), _stream()))
+    return cost, w, einf, st
+
+
+def fit_eval_grad(plan: Plan, b: Batch, theta, damping=DEFAULT_DAMPING, flags=0, grad_cost=None, targets=False):
+    """Cost and the variable-projection adjoint (debye_fit_eval_grad)."""
+    ld = theta.shape[1]
+    dev = theta.device
+    cost = torch.empty(b.P, dtype=torch.float64, device=dev)
+    g = torch.empty((b.P, ld), dtype=torch.float64, device=dev)
+    st = torch.empty(b.P, dtype=torch.int8, device=dev)
+    gr = torch.empty(b.F, dtype=torch.float64, device=dev) if targets else None
+    gi = torch.empty(b.F, dtype=torch.float64, device=dev) if targets else None
+    gc = None if grad_cost is None else grad_cost.to(torch.float64).contiguous()
+    cb = b.cstruct()
+    _check(lib().debye_fit_eval_grad(plan.handle, C.byref(cb), _ptr(theta), ld, float(damping), flags, _ptr(gc),
+                                     _ptr(cost), _ptr(g), _ptr(gr), _ptr(gi), _ptr(st), _stream()))
+    return cost, g, gr, gi, st
+
+
+def material_eval(kind, params, b_or_f_off, omega=None, noise_seed=0, jac=False, device="cuda"):
+    """Targets eps', eps'' (and the HN-family Jacobian) on the GPU (debye_material_eval)."""
+    if isinstance(b_or_f_off, Batch):
+        f_off, omega, F = b_or_f_off.f_off, b_or_f_off.omega, b_or_f_off.F
+    else:
+        f_off = _dev(b_or_f_off, torch.int64, device)
+        F = int(np.asarray(b_or_f_off)[-1])
+        omega = omega if torch.is_tensor(omega) else _dev(omega, torch.float64, device)
+    kind_t = kind if torch.is_tensor(kind) else _dev(np.asarray(kind, np.int8), torch.int8, device)
+    par = params if torch.is_tensor(params) else _dev(np.asarray(params, np.float64).reshape(-1, PARAM_STRIDE),
+                                                      torch.float64, device)
+    er = torch.empty(F, dtype=torch.float64, device=omega.device)
+    ei = torch.empty(F, dtype=torch.float64, device=omega.device)
+    J = torch.empty((F, 5, 2), dtype=torch.float64, device=omega.device) if jac else None
+    _check(lib().debye_material_eval(len(kind_t), _ptr(kind_t), _ptr(par), _ptr(f_off), F, _ptr(omega),
+                                     C.c_uint64(noise_seed), _ptr(er), _ptr(ei), _ptr(J), _stream()))
+    return (er, ei, J) if jac else (er, ei)
+
+
+def basis(omega, theta, N):
+    """Debye basis re/im [n_cand][N][F] (debye_basis)."""
+    F = omega.numel()
+    n = theta.shape[0]
+    re = torch.empty((n, N, F), dtype=torch.float64, device=omega.device)
+    im = torch.empty_like(re)
+    _check(lib().debye_basis(_ptr(omega), F, _ptr(theta), theta.shape[1], n, N, _ptr(re), _ptr(im), _stream()))
+    return re, im
+
+
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Swarm:
+    x: torch.Tensor
+    v: torch.Tensor
+    pbest_x: torch.Tensor
+    pbest_cost: torch.Tensor
+    gbest_x: torch.Tensor
+    gbest_cost: torch.Tensor
+    gbest_idx: torch.Tensor
+    history: torch.Tensor
+
+    @staticmethod
+    def empty(P, M, ld, hist_len, device="cuda"):
+        f = dict(dtype=torch.float64, device=device)
+        return Swarm(torch.zeros((P, ld), **f), torch.zeros((P, ld), **f), torch.zeros((P, ld), **f),
+                     torch.zeros(P, **f), torch.zeros((M, ld), **f), torch.zeros(M, **f),
+                     torch.zeros(M, dtype=torch.int64, device=device),
+                     torch.full((M, max(hist_len, 1)), float("nan"), **f))
+
+
+def pso_init(b: Batch, lb, ub, sw: Swarm, inertia=0.7, c1=1.5, c2=1.5, seed=0):
+    cb = b.cstruct()
+    p = _CPso(inertia, c1, c2, seed)
+    _check(lib().debye_pso_init(C.byref(cb), sw.x.shape[1], _ptr(lb), _ptr(ub), p, _ptr(sw.x), _ptr(sw.v),
+                                _ptr(sw.pbest_x), _ptr(sw.pbest_cost), _ptr(sw.gbest_cost), _ptr(sw.gbest_idx),
+                                _stream()))
+
+
+def pso_step(b: Batch, lb, ub, sw: Swarm, t, move, cost, inertia=0.7, c1=1.5, c2=1.5, seed=0, history=True):
+    cb = b.cstruct()
+    p = _CPso(inertia, c1, c2, seed)
+    h = sw.history if history else None
+    _check(lib().debye_pso_step(C.byref(cb), sw.x.shape[1], _ptr(lb), _ptr(ub), p, int(t), int(move), _ptr(cost),
+                                _ptr(sw.x), _ptr(sw.v), _ptr(sw.pbest_x), _ptr(sw.pbest_cost), _ptr(sw.gbest_x),
+                                _ptr(sw.gbest_cost), _ptr(sw.gbest_idx), _ptr(h), sw.history.shape[1], _stream()))
+
+
+def lbfgs_polish(b1: Batch, theta, lb, ub, steps=50, mem=10, max_trials=30, c1=1e-4, damping=DEFAULT_DAMPING,
+                 flags=0, history=True):
+    """L-BFGS polish of one candidate per material (theta [M][ld], in place)
+    inside the box [lb[m], ub[m]] (device tensors [M])."""
+    hist = torch.empty((b1.M, steps + 1), dtype=torch.float64, device=theta.device) if history else None
+    cb = b1.cstruct()
+    _check(lib().debye_lbfgs_polish(C.byref(cb), b1.f_off_h.ctypes.data_as(_vp), b1.n_poles_h.ctypes.data_as(_vp),
+                                    _ptr(theta), theta.shape[1], _ptr(lb), _ptr(ub), float(damping), flags,
+                                    _CLbfgs(steps, mem, max_trials, c1), _ptr(hist), _stream()))
+    return hist
+
+
+# ---------------------------------------------------------------------------
+class DebyeCost(torch.autograd.Function):
+    """cost[c] = C(theta[c], eps'[m(c)], eps''[m(c)]) with the adjoint of
+    debye_fit_eval_grad as backward (gradients for theta, eps', eps'')."""
+
+    @staticmethod
+    def forward(ctx, theta, eps_re, eps_im, plan, batch, damping=DEFAULT_DAMPING, flags=0):
+        b = batch.with_targets(eps_re.detach(), eps_im.detach())
+        cost = fit_eval(plan, b, theta.detach().contiguous(), damping, flags, want_weights=False)[0]
+        ctx.save_for_backward(theta, eps_re, eps_im)
+        ctx.plan, ctx.batch, ctx.damping, ctx.flags = plan, batch, damping, flags
+        return cost
+
+    @staticmethod
+    def backward(ctx, grad_cost):
+        theta, eps_re, eps_im = ctx.saved_tensors
+        b = ctx.batch.with_targets(eps_re.detach(), eps_im.detach())
+        want_t = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        _, g, gr, gi, _ = fit_eval_grad(ctx.plan, b, theta.detach().contiguous(), ctx.damping, ctx.flags,
+                                        grad_cost=grad_cost.contiguous(), targets=want_t)
+        return g, gr, gi, None, None, None, None
+
+
+class HNTarget(torch.autograd.Function):
+    """Havriliak-Negami-family targets (Eq. 4) from params [M][16] with the
+    analytic Jacobian of debye_material_eval as backward (columns eps_inf,
+    d_eps, tau0, alpha, beta)."""
+
+    @staticmethod
+    def forward(ctx, params, kind, batch):
+        er, ei, J = material_eval(kind, params.detach().contiguous(), batch, jac=True)
+        ctx.save_for_backward(J)
+        ctx.f_off = batch.f_off
+        ctx.M = params.shape[0]
+        return er, ei
+
+    @staticmethod
+    def backward(ctx, g_re, g_im):
+        (J,) = ctx.saved_tensors
+        return material_vjp(ctx.f_off, J, g_re, g_im, ctx.M), None, None
+
+
+def material_vjp(f_off, jac, g_re, g_im, M):
+    """Material-parameter gradient from the target gradients (debye_material_vjp)."""
+    gp = torch.empty((M, PARAM_STRIDE), dtype=torch.float64, device=jac.device)
+    _check(lib().debye_material_vjp(M, _ptr(f_off), jac.shape[0], _ptr(jac), _ptr(g_re.contiguous()),
+                                    _ptr(g_im.contiguous()), _ptr(gp), _stream()))
+    return gp

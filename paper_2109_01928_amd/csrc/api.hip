@@ -1,0 +1,562 @@
+// C ABI of the Debye fitting library (declared in include/debyefit.h):
+// argument validation on the host, launch planning and kernel dispatch.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/debyefit.h"
+#include "common.hpp"
+#include "fit_eval.hpp"
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(DEBYE_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define CHECK_HIP(expr, what)                   \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// Lanes per wave that the schedule tries to keep busy: the GPU has 256 CUs x 4
+// SIMDs; at two waves per SIMD a batch needs about 2048 waves to fill it.
+constexpr int64_t TARGET_WAVES = 2048;
+constexpr int MAX_LDS_PER_BLOCK = 64 * 1024;
+
+}  // namespace
+
+struct Bucket {
+  int32_t N = 0, SP = 1, SF = 1, cpw = 64;
+  int64_t n_cands = 0, n_tiles = 0, max_f = 0, work = 0;
+  std::vector<int32_t> mats;
+  int32_t *d_lane_cand = nullptr, *d_lane_mat = nullptr, *d_mats = nullptr;
+};
+
+struct debye_plan {
+  int32_t M = 0, max_poles = 0;
+  int64_t n_freq = 0, n_cand = 0;
+  std::vector<int64_t> f_off, cand_off;
+  std::vector<int32_t> n_poles;
+  std::vector<Bucket> buckets;
+  std::map<int32_t, int32_t> sf_override;  // N (0 = all) -> frequency split
+  double *d_record = nullptr;
+  int64_t rec_ld = 0;
+};
+
+namespace {
+
+void free_bucket(Bucket &b) {
+  if (b.d_lane_cand) (void)hipFree(b.d_lane_cand);
+  if (b.d_lane_mat) (void)hipFree(b.d_lane_mat);
+  if (b.d_mats) (void)hipFree(b.d_mats);
+  b.d_lane_cand = b.d_lane_mat = b.d_mats = nullptr;
+}
+
+int pick_split(const debye_plan &p, const Bucket &b) {
+  auto it = p.sf_override.find(b.N);
+  if (it == p.sf_override.end()) it = p.sf_override.find(0);
+  const int max_sf = 64 / b.SP;
+  if (it != p.sf_override.end() && it->second > 0) return std::min(it->second, max_sf);
+  // smallest power of two that gives TARGET_WAVES waves, without splitting
+  // short spectra below 16 points per lane
+  const int64_t avg_f = b.n_cands ? b.work / (b.n_cands * b.N) : 1;
+  int sf = 1;
+  while (sf < max_sf && (b.n_cands * b.SP * sf + 63) / 64 < TARGET_WAVES && avg_f / (2 * sf) >= 16) sf *= 2;
+  // the SP > 1 path keeps each candidate's normal matrix in LDS
+  const int lds = dfit::lds_bytes_per_candidate(b.N);
+  while (lds > 0 && sf < max_sf && (64 / (b.SP * sf)) * lds > MAX_LDS_PER_BLOCK) sf *= 2;
+  return sf;
+}
+
+int build_tiles(debye_plan &p, Bucket &b) {
+  free_bucket(b);
+  b.SF = pick_split(p, b);
+  b.cpw = 64 / (b.SP * b.SF);
+  // longest spectra first, candidates of a material kept together
+  std::vector<int32_t> order = b.mats;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return (p.f_off[x + 1] - p.f_off[x]) > (p.f_off[y + 1] - p.f_off[y]);
+  });
+  std::vector<int32_t> lc, lm;
+  lc.reserve(b.n_cands + b.cpw);
+  for (int32_t m : order)
+    for (int64_t c = p.cand_off[m]; c < p.cand_off[m + 1]; ++c) {
+      lc.push_back((int32_t)c);
+      lm.push_back(m);
+    }
+  while (lc.size() % b.cpw) {
+    lc.push_back(-1);
+    lm.push_back(0);
+  }
+  b.n_tiles = (int64_t)lc.size() / b.cpw;
+  if (b.n_tiles == 0) return DEBYE_OK;
+  if (hipMalloc(&b.d_lane_cand, lc.size() * 4) != hipSuccess || hipMalloc(&b.d_lane_mat, lm.size() * 4) != hipSuccess ||
+      hipMalloc(&b.d_mats, b.mats.size() * 4) != hipSuccess)
+    return fail(DEBYE_ENOMEM, "plan: device allocation failed");
+  CHECK_HIP(hipMemcpy(b.d_lane_cand, lc.data(), lc.size() * 4, hipMemcpyHostToDevice), "plan upload");
+  CHECK_HIP(hipMemcpy(b.d_lane_mat, lm.data(), lm.size() * 4, hipMemcpyHostToDevice), "plan upload");
+  CHECK_HIP(hipMemcpy(b.d_mats, b.mats.data(), b.mats.size() * 4, hipMemcpyHostToDevice), "plan upload");
+  return DEBYE_OK;
+}
+
+int check_batch(const debye_batch *b) {
+  if (!b) return fail(DEBYE_EINVAL, "batch is NULL");
+  if (b->n_mat < 1) return fail(DEBYE_ERANGE, "n_mat must be >= 1 (got %d)", b->n_mat);
+  if (b->max_poles < 1 || b->max_poles > DEBYE_MAX_POLES)
+    return fail(DEBYE_ERANGE, "max_poles must be in 1..%d (got %d)", DEBYE_MAX_POLES, b->max_poles);
+  if (b->n_freq < 1) return fail(DEBYE_ERANGE, "n_freq must be >= 1");
+  if (b->n_cand < 0) return fail(DEBYE_ERANGE, "n_cand must be >= 0");
+  if (!b->f_off || !b->cand_off || !b->n_poles || !b->omega || !b->eps_re || !b->eps_im)
+    return fail(DEBYE_EINVAL, "batch has a NULL device pointer");
+  return DEBYE_OK;
+}
+
+int check_plan_batch(const debye_plan *p, const debye_batch *b, int64_t ld) {
+  if (!p) return fail(DEBYE_EINVAL, "plan is NULL");
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (b->n_mat != p->M || b->n_cand != p->n_cand || b->n_freq != p->n_freq || b->max_poles != p->max_poles)
+    return fail(DEBYE_EINVAL, "batch shape does not match the plan (M %d/%d, candidates %lld/%lld, points %lld/%lld)",
+                b->n_mat, p->M, (long long)b->n_cand, (long long)p->n_cand, (long long)b->n_freq, (long long)p->n_freq);
+  if (ld < p->max_poles) return fail(DEBYE_ERANGE, "ld (%lld) < max_poles (%d)", (long long)ld, p->max_poles);
+  return DEBYE_OK;
+}
+
+int check_damping(double damping, uint32_t flags) {
+  if (!(damping >= 0.0) || !std::isfinite(damping)) return fail(DEBYE_ERANGE, "damping must be finite and >= 0");
+  if (flags & ~(uint32_t)DEBYE_FLAG_NO_SIGN_FLIP) return fail(DEBYE_EINVAL, "unknown flag bits 0x%x", flags);
+  return DEBYE_OK;
+}
+
+dfit::FitArgs fit_args(const debye_plan *p, const Bucket &bk, const debye_batch *b, const double *theta, int64_t ld,
+                       double damping, uint32_t flags) {
+  dfit::FitArgs a{};
+  a.f_off = b->f_off;
+  a.omega = b->omega;
+  a.eps_re = b->eps_re;
+  a.eps_im = b->eps_im;
+  a.theta = theta;
+  a.ld = ld;
+  a.damping = damping;
+  a.flags = flags;
+  a.freq_split = bk.SF;
+  a.cand_per_wave = bk.cpw;
+  a.lane_cand = bk.d_lane_cand;
+  a.lane_mat = bk.d_lane_mat;
+  (void)p;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *debye_last_error(void) { return g_error.c_str(); }
+const char *debye_version(void) { return "debyefit 0.1 (gfx950, FP64)"; }
+
+int debye_plan_create(const debye_batch *shape, const int64_t *f_off_host, const int64_t *cand_off_host,
+                      const int32_t *n_poles_host, uint32_t flags, debye_plan **out) {
+  if (!out) return fail(DEBYE_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_batch(shape);
+  if (rc) return rc;
+  if (!f_off_host || !cand_off_host || !n_poles_host) return fail(DEBYE_EINVAL, "host shape arrays are NULL");
+  if (flags) return fail(DEBYE_EINVAL, "plan flags must be 0");
+  const int32_t M = shape->n_mat;
+  if (f_off_host[0] != 0 || cand_off_host[0] != 0) return fail(DEBYE_EINVAL, "offsets must start at 0");
+  int32_t maxN = 0;
+  for (int32_t m = 0; m < M; ++m) {
+    if (f_off_host[m + 1] - f_off_host[m] < 1)
+      return fail(DEBYE_ERANGE, "material %d has %lld frequency points (need >= 1)", m,
+                  (long long)(f_off_host[m + 1] - f_off_host[m]));
+    if (cand_off_host[m + 1] < cand_off_host[m]) return fail(DEBYE_EINVAL, "cand_off is decreasing at %d", m);
+    if (n_poles_host[m] < 1 || n_poles_host[m] > DEBYE_MAX_POLES)
+      return fail(DEBYE_ERANGE, "material %d: n_poles %d outside 1..%d", m, n_poles_host[m], DEBYE_MAX_POLES);
+    maxN = std::max(maxN, n_poles_host[m]);
+  }
+  if (f_off_host[M] != shape->n_freq || cand_off_host[M] != shape->n_cand)
+    return fail(DEBYE_EINVAL, "n_freq / n_cand do not match the offsets");
+  if (maxN != shape->max_poles) return fail(DEBYE_EINVAL, "max_poles (%d) != max of n_poles (%d)", shape->max_poles, maxN);
+  if (cand_off_host[M] > INT32_MAX) return fail(DEBYE_ERANGE, "more than 2^31-1 candidates");
+
+  debye_plan *p = new debye_plan();
+  p->M = M;
+  p->max_poles = maxN;
+  p->n_freq = shape->n_freq;
+  p->n_cand = shape->n_cand;
+  p->f_off.assign(f_off_host, f_off_host + M + 1);
+  p->cand_off.assign(cand_off_host, cand_off_host + M + 1);
+  p->n_poles.assign(n_poles_host, n_poles_host + M);
+  std::map<int32_t, Bucket> by_n;
+  for (int32_t m = 0; m < M; ++m) {
+    const int64_t P = cand_off_host[m + 1] - cand_off_host[m];
+    if (P == 0) continue;
+    Bucket &b = by_n[n_poles_host[m]];
+    b.N = n_poles_host[m];
+    b.SP = dfit::pole_split(b.N);
+    b.mats.push_back(m);
+    b.n_cands += P;
+    const int64_t F = f_off_host[m + 1] - f_off_host[m];
+    b.max_f = std::max(b.max_f, F);
+    b.work += P * F * b.N;
+  }
+  for (auto &kv : by_n) p->buckets.push_back(std::move(kv.second));
+  // largest work first
+  std::stable_sort(p->buckets.begin(), p->buckets.end(), [](const Bucket &x, const Bucket &y) { return x.work > y.work; });
+  for (auto &b : p->buckets) {
+    rc = build_tiles(*p, b);
+    if (rc) {
+      debye_plan_destroy(p);
+      return rc;
+    }
+  }
+  *out = p;
+  return DEBYE_OK;
+}
+
+int debye_plan_destroy(debye_plan *p) {
+  if (!p) return DEBYE_OK;
+  for (auto &b : p->buckets) free_bucket(b);
+  if (p->d_record) (void)hipFree(p->d_record);
+  delete p;
+  return DEBYE_OK;
+}
+
+int debye_plan_set_freq_split(debye_plan *p, int32_t n_poles, int32_t split) {
+  if (!p) return fail(DEBYE_EINVAL, "plan is NULL");
+  if (split < 0 || split > 64 || (split & (split - 1))) return fail(DEBYE_ERANGE, "split must be 0 or a power of two <= 64");
+  if (split == 0) p->sf_override.erase(n_poles);
+  else p->sf_override[n_poles] = split;
+  for (auto &b : p->buckets) {
+    int rc = build_tiles(*p, b);
+    if (rc) return rc;
+  }
+  return DEBYE_OK;
+}
+
+int debye_plan_info(const debye_plan *p, int32_t i, int32_t *n_poles, int32_t *pole_split, int32_t *freq_split,
+                    int64_t *n_tiles) {
+  if (!p) return fail(DEBYE_EINVAL, "plan is NULL");
+  if (i < 0) return (int)p->buckets.size();
+  if (i >= (int)p->buckets.size()) return fail(DEBYE_ERANGE, "bucket index out of range");
+  const Bucket &b = p->buckets[i];
+  if (n_poles) *n_poles = b.N;
+  if (pole_split) *pole_split = b.SP;
+  if (freq_split) *freq_split = b.SF;
+  if (n_tiles) *n_tiles = b.n_tiles;
+  return DEBYE_OK;
+}
+
+int debye_basis(const double *omega, int64_t F, const double *log10_tau, int64_t ld, int64_t n_cand, int32_t N,
+                double *re, double *im, hipStream_t stream) {
+  if (!omega || !log10_tau || !re || !im) return fail(DEBYE_EINVAL, "NULL pointer");
+  if (F < 1 || N < 1 || N > DEBYE_MAX_POLES || n_cand < 0) return fail(DEBYE_ERANGE, "bad size (F %lld, N %d)", (long long)F, N);
+  if (ld < N) return fail(DEBYE_ERANGE, "ld < N");
+  if (n_cand == 0) return DEBYE_OK;
+  CHECK_HIP(dfit::launch_basis(omega, F, log10_tau, ld, n_cand, N, re, im, stream), "debye_basis launch");
+  return DEBYE_OK;
+}
+
+int debye_fit_eval(const debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld, double damping,
+                   uint32_t flags, double *cost, double *weights, double *eps_inf, int8_t *status, hipStream_t stream) {
+  int rc = check_plan_batch(p, b, ld);
+  if (rc) return rc;
+  if ((rc = check_damping(damping, flags))) return rc;
+  if (!log10_tau || !cost) return fail(DEBYE_EINVAL, "log10_tau and cost must not be NULL");
+  for (const Bucket &bk : p->buckets) {
+    if (!bk.n_tiles) continue;
+    dfit::FitArgs a = fit_args(p, bk, b, log10_tau, ld, damping, flags);
+    a.cost = cost;
+    a.weights = weights;
+    a.eps_inf = eps_inf;
+    a.status = status;
+    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, false, stream), "debye_fit_eval launch");
+  }
+  return DEBYE_OK;
+}
+
+int debye_fit_eval_grad(const debye_plan *pc, const debye_batch *b, const double *log10_tau, int64_t ld,
+                        double damping, uint32_t flags, const double *grad_cost, double *cost,
+                        double *grad_log10_tau, double *grad_eps_re, double *grad_eps_im, int8_t *status,
+                        hipStream_t stream) {
+  int rc = check_plan_batch(pc, b, ld);
+  if (rc) return rc;
+  if ((rc = check_damping(damping, flags))) return rc;
+  if (!log10_tau || !cost) return fail(DEBYE_EINVAL, "log10_tau and cost must not be NULL");
+  if ((grad_eps_re == nullptr) != (grad_eps_im == nullptr))
+    return fail(DEBYE_EINVAL, "grad_eps_re and grad_eps_im must both be set or both be NULL");
+  debye_plan *p = const_cast<debye_plan *>(pc);
+  const bool targets = grad_eps_re != nullptr;
+  if (targets && !p->d_record) {
+    p->rec_ld = 3 * p->max_poles + 2;
+    if (hipMalloc(&p->d_record, (size_t)std::max<int64_t>(p->n_cand, 1) * p->rec_ld * 8) != hipSuccess) {
+      p->d_record = nullptr;
+      return fail(DEBYE_ENOMEM, "adjoint workspace allocation failed");
+    }
+  }
+  for (const Bucket &bk : p->buckets) {
+    if (!bk.n_tiles) continue;
+    dfit::FitArgs a = fit_args(p, bk, b, log10_tau, ld, damping, flags);
+    a.cost = cost;
+    a.status = status;
+    a.grad_cost = grad_cost;
+    a.grad_theta = grad_log10_tau;
+    a.record = targets ? p->d_record : nullptr;
+    a.rec_ld = p->rec_ld;
+    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, true, stream), "debye_fit_eval_grad launch");
+  }
+  if (targets) {
+    // materials without candidates get zero target gradients
+    CHECK_HIP(hipMemsetAsync(grad_eps_re, 0, (size_t)p->n_freq * 8, stream), "memset");
+    CHECK_HIP(hipMemsetAsync(grad_eps_im, 0, (size_t)p->n_freq * 8, stream), "memset");
+    for (const Bucket &bk : p->buckets) {
+      if (!bk.n_tiles) continue;
+      dfit::TargetGradArgs t{};
+      t.f_off = b->f_off;
+      t.cand_off = b->cand_off;
+      t.omega = b->omega;
+      t.eps_re = b->eps_re;
+      t.eps_im = b->eps_im;
+      t.theta = log10_tau;
+      t.ld = ld;
+      t.record = p->d_record;
+      t.rec_ld = p->rec_ld;
+      t.mat_list = bk.d_mats;
+      t.grad_re = grad_eps_re;
+      t.grad_im = grad_eps_im;
+      CHECK_HIP(dfit::launch_target_grad(bk.N, t, bk.max_f, (int32_t)bk.mats.size(), stream), "target gradient launch");
+    }
+  }
+  return DEBYE_OK;
+}
+
+int debye_material_eval(int32_t M, const int8_t *kind, const double *params, const int64_t *f_off, int64_t n_freq,
+                        const double *omega, uint64_t noise_seed, double *eps_re, double *eps_im, double *jac,
+                        hipStream_t stream) {
+  if (M < 1) return fail(DEBYE_ERANGE, "M must be >= 1");
+  if (n_freq < 1) return fail(DEBYE_ERANGE, "n_freq must be >= 1");
+  if (!kind || !params || !f_off || !omega || !eps_re || !eps_im) return fail(DEBYE_EINVAL, "NULL pointer");
+  dfit::MaterialArgs a{M, kind, params, f_off, n_freq, omega, noise_seed, eps_re, eps_im, jac};
+  CHECK_HIP(dfit::launch_material(a, stream), "debye_material_eval launch");
+  return DEBYE_OK;
+}
+
+int debye_material_vjp(int32_t M, const int64_t *f_off, int64_t n_freq, const double *jac, const double *grad_re,
+                       const double *grad_im, double *grad_params, hipStream_t stream) {
+  if (M < 1) return fail(DEBYE_ERANGE, "M must be >= 1");
+  if (n_freq < 1) return fail(DEBYE_ERANGE, "n_freq must be >= 1");
+  if (!f_off || !jac || !grad_re || !grad_im || !grad_params) return fail(DEBYE_EINVAL, "NULL pointer");
+  CHECK_HIP(dfit::launch_material_vjp(M, f_off, jac, grad_re, grad_im, grad_params, stream), "debye_material_vjp launch");
+  return DEBYE_OK;
+}
+
+static int pso_check(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_pso_params p) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (ld < b->max_poles) return fail(DEBYE_ERANGE, "ld < max_poles");
+  if (!lb || !ub) return fail(DEBYE_EINVAL, "lb/ub are NULL");
+  if (!std::isfinite(p.inertia) || !std::isfinite(p.c1) || !std::isfinite(p.c2))
+    return fail(DEBYE_ERANGE, "PSO coefficients must be finite");
+  return DEBYE_OK;
+}
+
+int debye_pso_init(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_pso_params p, double *x,
+                   double *v, double *pbest_x, double *pbest_cost, double *gbest_cost, int64_t *gbest_idx,
+                   hipStream_t stream) {
+  int rc = pso_check(b, ld, lb, ub, p);
+  if (rc) return rc;
+  if (!x || !v || !pbest_x || !pbest_cost || !gbest_cost || !gbest_idx) return fail(DEBYE_EINVAL, "NULL state pointer");
+  dfit::PsoArgs a{};
+  a.M = b->n_mat;
+  a.cand_off = b->cand_off;
+  a.n_poles = b->n_poles;
+  a.ld = ld;
+  a.lb = lb;
+  a.ub = ub;
+  a.seed = p.seed;
+  a.x = x;
+  a.v = v;
+  a.pbest_x = pbest_x;
+  a.pbest_cost = pbest_cost;
+  a.gbest_cost = gbest_cost;
+  a.gbest_idx = gbest_idx;
+  CHECK_HIP(dfit::launch_pso_init(a, b->n_cand, stream), "debye_pso_init launch");
+  return DEBYE_OK;
+}
+
+int debye_pso_step(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_pso_params p, int32_t t,
+                   int32_t move, const double *cost, double *x, double *v, double *pbest_x, double *pbest_cost,
+                   double *gbest_x, double *gbest_cost, int64_t *gbest_idx, double *history, int64_t hist_ld,
+                   hipStream_t stream) {
+  int rc = pso_check(b, ld, lb, ub, p);
+  if (rc) return rc;
+  if (t < 1) return fail(DEBYE_ERANGE, "iteration t must be >= 1");
+  if (history && hist_ld < t) return fail(DEBYE_ERANGE, "hist_ld (%lld) < t (%d)", (long long)hist_ld, t);
+  if (!cost || !x || !v || !pbest_x || !pbest_cost || !gbest_x || !gbest_cost || !gbest_idx)
+    return fail(DEBYE_EINVAL, "NULL state pointer");
+  dfit::PsoArgs a{};
+  a.M = b->n_mat;
+  a.cand_off = b->cand_off;
+  a.n_poles = b->n_poles;
+  a.ld = ld;
+  a.lb = lb;
+  a.ub = ub;
+  a.inertia = p.inertia;
+  a.c1 = p.c1;
+  a.c2 = p.c2;
+  a.seed = p.seed;
+  a.t = t;
+  a.move = move ? 1 : 0;
+  a.cost = cost;
+  a.x = x;
+  a.v = v;
+  a.pbest_x = pbest_x;
+  a.pbest_cost = pbest_cost;
+  a.gbest_x = gbest_x;
+  a.gbest_cost = gbest_cost;
+  a.gbest_idx = gbest_idx;
+  a.history = history;
+  a.hist_ld = hist_ld;
+  CHECK_HIP(dfit::launch_pso_step(a, stream), "debye_pso_step launch");
+  return DEBYE_OK;
+}
+
+int debye_lbfgs_polish(const debye_batch *b, const int64_t *f_off_host, const int32_t *n_poles_host, double *theta,
+                       int64_t ld, const double *lb, const double *ub, double damping, uint32_t flags,
+                       debye_lbfgs_params lp, double *cost_hist, hipStream_t stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if ((rc = check_damping(damping, flags))) return rc;
+  if (!theta || !f_off_host || !n_poles_host || !lb || !ub) return fail(DEBYE_EINVAL, "NULL pointer");
+  if (ld < b->max_poles) return fail(DEBYE_ERANGE, "ld < max_poles");
+  if (b->n_cand != b->n_mat) return fail(DEBYE_EINVAL, "polish needs exactly one candidate per material");
+  if (lp.steps < 0 || lp.mem < 1 || lp.mem > DFIT_MAX_MEM || lp.max_trials < 1 || lp.max_trials > 64 ||
+      !(lp.c1 > 0.0 && lp.c1 < 1.0))
+    return fail(DEBYE_ERANGE, "L-BFGS parameters out of range (steps >= 0, mem 1..%d, trials 1..64, 0 < c1 < 1)",
+                DFIT_MAX_MEM);
+  if (lp.steps == 0) return DEBYE_OK;
+  const int32_t M = b->n_mat;
+  const int T = lp.max_trials;
+  std::vector<int64_t> one(M + 1), trials(M + 1);
+  for (int32_t m = 0; m <= M; ++m) {
+    one[m] = m;
+    trials[m] = (int64_t)m * T;
+  }
+  // device workspace
+  struct Buf {
+    void *p = nullptr;
+    ~Buf() {
+      if (p) (void)hipFree(p);
+    }
+  };
+  Buf w_trial_off, w_ws;
+  const int64_t n1 = (int64_t)M * ld, nT = (int64_t)M * T;
+  const size_t doubles = (size_t)(n1 /*grad*/ + 2 * (int64_t)M * lp.mem * ld /*S,Y*/ + (int64_t)M * lp.mem /*rho*/ +
+                                  n1 /*dir*/ + M /*gd*/ + nT * ld /*trial theta*/ + nT /*trial cost*/ + n1 /*new theta*/ +
+                                  M /*new cost*/ + n1 /*new grad*/ + M /*cost*/ + M /*accepted cost*/);
+  const size_t ints = (size_t)(3 * M);  // hist_n, hist_head, accepted
+  const size_t bytes = doubles * 8 + ints * 4 + (size_t)nT /*trial status*/ + (size_t)M /*new status*/ + 64;
+  if (hipMalloc(&w_ws.p, bytes) != hipSuccess) return fail(DEBYE_ENOMEM, "polish workspace allocation failed");
+  if (hipMalloc(&w_trial_off.p, (size_t)(M + 1) * 8) != hipSuccess) return fail(DEBYE_ENOMEM, "polish workspace allocation failed");
+  double *dp = (double *)w_ws.p;
+  auto take = [&](int64_t n) {
+    double *r = dp;
+    dp += n;
+    return r;
+  };
+  double *grad = take(n1), *S = take((int64_t)M * lp.mem * ld), *Y = take((int64_t)M * lp.mem * ld),
+         *rho = take((int64_t)M * lp.mem), *dir = take(n1), *gd = take(M), *trial_theta = take(nT * ld),
+         *trial_cost = take(nT), *new_theta = take(n1), *new_cost = take(M), *new_grad = take(n1), *cost = take(M),
+         *acc_cost = take(M);
+  int32_t *ip = (int32_t *)dp;
+  int32_t *hist_n = ip, *hist_head = ip + M, *accepted = ip + 2 * M;
+  int8_t *trial_status = (int8_t *)(ip + 3 * M);
+  int8_t *new_status = trial_status + nT;
+  CHECK_HIP(hipMemcpyAsync(w_trial_off.p, trials.data(), (M + 1) * 8, hipMemcpyHostToDevice, stream), "upload");
+  CHECK_HIP(hipMemsetAsync(hist_n, 0, (size_t)2 * M * 4, stream), "memset");
+
+  debye_batch bt = *b;
+  bt.cand_off = (const int64_t *)w_trial_off.p;
+  bt.n_cand = nT;
+  std::vector<int64_t> f_h(f_off_host, f_off_host + M + 1);
+  debye_plan *p1 = nullptr, *pT = nullptr;
+  if ((rc = debye_plan_create(b, f_h.data(), one.data(), n_poles_host, 0, &p1))) return rc;
+  if ((rc = debye_plan_create(&bt, f_h.data(), trials.data(), n_poles_host, 0, &pT))) {
+    debye_plan_destroy(p1);
+    return rc;
+  }
+  auto done = [&](int r) {
+    (void)hipStreamSynchronize(stream);
+    debye_plan_destroy(p1);
+    debye_plan_destroy(pT);
+    return r;
+  };
+  dfit::LbfgsArgs la{};
+  la.M = M;
+  la.n_poles = b->n_poles;
+  la.ld = ld;
+  la.mem = lp.mem;
+  la.max_trials = T;
+  la.c1 = lp.c1;
+  la.lb = lb;
+  la.ub = ub;
+  la.theta = theta;
+  la.cost = cost;
+  la.acc_cost = acc_cost;
+  la.grad = grad;
+  la.S = S;
+  la.Y = Y;
+  la.rho = rho;
+  la.hist_n = hist_n;
+  la.hist_head = hist_head;
+  la.dir = dir;
+  la.gd = gd;
+  la.trial_theta = trial_theta;
+  la.trial_cost = trial_cost;
+  la.trial_status = trial_status;
+  la.new_theta = new_theta;
+  la.accepted = accepted;
+  la.new_cost = new_cost;
+  la.new_grad = new_grad;
+  la.new_status = new_status;
+  la.cost_hist = cost_hist;
+  la.steps = lp.steps;
+  if ((rc = debye_fit_eval_grad(p1, b, theta, ld, damping, flags, nullptr, cost, grad, nullptr, nullptr, new_status, stream)))
+    return done(rc);
+  for (int32_t s = 0; s < lp.steps; ++s) {
+    la.step = s;
+    hipError_t e = dfit::launch_lbfgs_direction(la, stream);
+    if (e != hipSuccess) return done(hip_fail(e, "lbfgs direction"));
+    if ((rc = debye_fit_eval(pT, &bt, trial_theta, ld, damping, flags, trial_cost, nullptr, nullptr, trial_status, stream)))
+      return done(rc);
+    if ((e = dfit::launch_lbfgs_select(la, stream)) != hipSuccess) return done(hip_fail(e, "lbfgs select"));
+    if ((rc = debye_fit_eval_grad(p1, b, new_theta, ld, damping, flags, nullptr, new_cost, new_grad, nullptr, nullptr,
+                                  new_status, stream)))
+      return done(rc);
+    if ((e = dfit::launch_lbfgs_update(la, stream)) != hipSuccess) return done(hip_fail(e, "lbfgs update"));
+  }
+  return done(DEBYE_OK);
+}
+
+}  // extern "C"

@@ -1,0 +1,739 @@
+// Batched multi-Debye DLS cost evaluation and its variable-projection adjoint
+// for gfx950 (MI355X), FP64.
+//
+// Method (paper Sec. III-B; Eq. 7 basis with the sign of Eq. 1):
+//   tau_i = 10^theta_i, x_ki = w_k tau_i, R_ki = 1/(1+x^2), I_ki = x R_ki
+//   weights: damped least squares on the loss part with Marquardt scaling,
+//     (D^-1 G D^-1 + damping Id) zt = D^-1 b,  G = I^T I, b = I^T eps'', D = diag(G)^1/2,
+//     z = D^-1 zt, solved by Cholesky plus one corrected-semi-normal-equations
+//     step (a residual pass over the frequencies, I^T r accumulated in
+//     double-double) because log-spaced Debye columns are nearly collinear;
+//   flip: w = |z| (penalty for negative weights);
+//   eps_inf = (sum_k eps'_k - sum_i w_i S_i) / F,  S_i = sum_k R_ki;
+//   cost = sum_k (eps'_k - eps_inf - (R w)_k)^2 + (eps''_k - (I w)_k)^2.
+//
+// Work decomposition (one wavefront per work tile, one tile per 64-lane block):
+//   - a candidate is served by SP x SF lanes: SP lanes split its poles (the
+//     "ring" split below) and SF lanes split its frequency points;
+//   - the 64/(SP*SF) candidates of a wave are listed by the plan (any mix of
+//     materials with the same pole count);
+//   - every F-reduction is a per-lane register accumulation followed by a
+//     fixed butterfly over the SF lanes, so results are deterministic;
+//   - the basis is recomputed in registers in each pass and never stored.
+//
+// Ring split of the Gram matrix for SP > 1 poles-per-lane groups: the NP =
+// NB*SP (padded) poles are placed on a ring; lane q owns poles q*NB .. q*NB+NB-1
+// and accumulates, for each owned pole p and each offset d = 0..NP/2, the
+// entry G(p, (p+d) mod NP).  Every unordered pair is covered (the d = NP/2
+// entries twice, with bit-identical values), the work is balanced, and a lane
+// only needs the basis values of the next NP/2 poles on the ring, which it
+// receives from its neighbours by DPP quad permutes.  Padded poles get tau = 0,
+// so their loss column is exactly zero and they drop out.
+
+#include "common.hpp"
+#include "fit_eval.hpp"
+
+namespace dfit {
+
+template <int N, int SP> struct Shape {
+  static_assert(SP == 1 || SP == 2 || SP == 4, "pole split must be 1, 2 or 4");
+  static constexpr int NB = (N + SP - 1) / SP;               // poles owned per lane
+  static constexpr int NP = NB * SP;                         // padded ring size
+  static constexpr int D = (SP == 1) ? 0 : NP / 2;           // ring half width
+  static constexpr int NV = (SP == 1) ? N : NB + D;          // basis values seen by a lane
+  static constexpr int NG = (SP == 1) ? N * (N + 1) / 2 : NB * (D + 1);  // Gram accumulators
+  static constexpr int NT = N * (N + 1) / 2;                 // packed triangle
+  static constexpr int LDS_DOUBLES = (SP == 1) ? 0 : N * (N + 1) / 2 + 6 * N;  // per candidate
+};
+
+constexpr __host__ __device__ int tri(int n, int i, int j) { return i * n - (i * (i - 1)) / 2 + (j - i); }
+
+// value of block t (owned by lane (q + t) mod SP) of a lane's ring view
+template <int SP> __device__ __forceinline__ double ring_fetch(double v, int t) {
+  if constexpr (SP == 2) {
+    return dpp_quad<QP_SWAP1>(v);
+  } else {
+    return t == 1 ? dpp_quad<QP_ROT1>(v) : dpp_quad<QP_SWAP2>(v);
+  }
+}
+
+// sum over the SP lanes of a candidate (bit-identical in all of them)
+template <int SP> __device__ __forceinline__ double group_sum(double v) {
+  if constexpr (SP == 1) {
+    return v;
+  } else if constexpr (SP == 2) {
+    return v + dpp_quad<QP_SWAP1>(v);
+  } else {
+    v = v + dpp_quad<QP_SWAP1>(v);
+    return v + dpp_quad<QP_SWAP2>(v);
+  }
+}
+
+// sum over the SF frequency lanes of a candidate (xor butterfly)
+__device__ __forceinline__ double freq_sum(double v, int sp, int s_lanes) {
+  for (int m = sp; m < s_lanes; m <<= 1) v += __shfl_xor(v, m, WAVE);
+  return v;
+}
+
+// Double-double accumulation (Knuth's TwoSum, FMA-based TwoProd; Ogita, Rump
+// and Oishi 2005): acc (hi, lo) += a * b with the product and the sum errors
+// kept, about 2u^2 relative to the terms instead of u.
+__device__ __forceinline__ void dd_fma_acc(double &hi, double &lo, double a, double b) {
+  const double p = a * b;
+  const double pe = __builtin_fma(a, b, -p);
+  const double s = hi + p;
+  const double bv = s - hi;
+  const double se = (hi - (s - bv)) + (p - bv);
+  hi = s;
+  lo = lo + (se + pe);
+}
+
+// xor-butterfly of a double-double over the SF frequency lanes; TwoSum's
+// error term does not depend on the operand order, so all lanes end with the
+// same bits
+__device__ __forceinline__ double freq_sum_dd(double hi, double lo, int sp, int s_lanes) {
+  for (int m = sp; m < s_lanes; m <<= 1) {
+    const double oh = __shfl_xor(hi, m, WAVE), ol = __shfl_xor(lo, m, WAVE);
+    const double s = hi + oh;
+    const double bv = s - hi;
+    const double se = (hi - (s - bv)) + (oh - bv);
+    hi = s;
+    lo = (lo + ol) + se;
+  }
+  return hi + lo;
+}
+
+// --------------------------------------------------------------------------
+// Dense solve helpers on a packed upper triangle held in registers (SP == 1)
+// or in LDS (SP > 1).  A = U^T U, U upper, diagonal stored as reciprocals in uinv.
+// --------------------------------------------------------------------------
+template <int N, class MAT>
+__device__ __forceinline__ bool equilibrate_factor(MAT &A, double *invd, double *uinv, double damping,
+                                                   double tol) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double g = A[tri(N, i, i)];
+    ok = ok && (g > 0.0) && (g < INFINITY);
+    invd[i] = 1.0 / sqrt(g);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = i + 1; j < N; ++j) A[tri(N, i, j)] = A[tri(N, i, j)] * invd[i] * invd[j];
+    A[tri(N, i, i)] = 1.0 + damping;
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double s = A[tri(N, j, j)];
+#pragma unroll
+    for (int l = 0; l < j; ++l) s = __builtin_fma(-A[tri(N, l, j)], A[tri(N, l, j)], s);
+    ok = ok && (s > tol);
+    double u = sqrt(s);
+    double ui = 1.0 / u;
+    uinv[j] = ui;
+    A[tri(N, j, j)] = u;
+#pragma unroll
+    for (int k = j + 1; k < N; ++k) {
+      double t = A[tri(N, j, k)];
+#pragma unroll
+      for (int l = 0; l < j; ++l) t = __builtin_fma(-A[tri(N, l, j)], A[tri(N, l, k)], t);
+      A[tri(N, j, k)] = t * ui;
+    }
+  }
+  return ok;
+}
+
+// x <- A^-1 x with A = U^T U (x overwritten)
+template <int N, class MAT, class VEC>
+__device__ __forceinline__ void chol_solve(const MAT &A, const double *uinv, VEC &x) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double s = x[i];
+#pragma unroll
+    for (int l = 0; l < i; ++l) s = __builtin_fma(-A[tri(N, l, i)], x[l], s);
+    x[i] = s * uinv[i];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double s = x[i];
+#pragma unroll
+    for (int l = i + 1; l < N; ++l) s = __builtin_fma(-A[tri(N, i, l)], x[l], s);
+    x[i] = s * uinv[i];
+  }
+}
+
+// The same factorisation and solves for a matrix in LDS (SP > 1): plain
+// loops, so that the compiler does not pull the whole matrix into registers.
+// Every lane of a candidate runs them on that candidate's region.
+__device__ __noinline__ bool lds_equilibrate_factor(int n, double *A, double *invd, double *uinv, double damping,
+                                                    double tol) {
+  bool ok = true;
+  for (int i = 0; i < n; ++i) {
+    const double g = A[tri(n, i, i)];
+    ok = ok && (g > 0.0) && (g < INFINITY);
+    invd[i] = 1.0 / sqrt(g);
+  }
+  for (int i = 0; i < n; ++i) {
+    const int row = tri(n, i, i);
+    for (int j = i + 1; j < n; ++j) A[row + (j - i)] = A[row + (j - i)] * invd[i] * invd[j];
+    A[row] = 1.0 + damping;
+  }
+  for (int j = 0; j < n; ++j) {
+    double s = A[tri(n, j, j)];
+    for (int l = 0; l < j; ++l) {
+      const double u = A[tri(n, l, j)];
+      s = __builtin_fma(-u, u, s);
+    }
+    ok = ok && (s > tol);
+    const double u = sqrt(s);
+    const double ui = 1.0 / u;
+    uinv[j] = ui;
+    A[tri(n, j, j)] = u;
+    for (int k = j + 1; k < n; ++k) {
+      double t = A[tri(n, j, k)];
+      for (int l = 0; l < j; ++l) t = __builtin_fma(-A[tri(n, l, j)], A[tri(n, l, k)], t);
+      A[tri(n, j, k)] = t * ui;
+    }
+  }
+  return ok;
+}
+
+__device__ __noinline__ void lds_chol_solve(int n, const double *A, const double *uinv, double *x) {
+  for (int i = 0; i < n; ++i) {
+    double s = x[i];
+    for (int l = 0; l < i; ++l) s = __builtin_fma(-A[tri(n, l, i)], x[l], s);
+    x[i] = s * uinv[i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = x[i];
+    const int row = tri(n, i, i);
+    for (int l = i + 1; l < n; ++l) s = __builtin_fma(-A[row + (l - i)], x[l], s);
+    x[i] = s * uinv[i];
+  }
+}
+
+// per-candidate LDS region of the SP > 1 path: packed triangle, then six
+// vectors of N (scaling, reciprocal pivots, rhs, column sums, two work vectors)
+template <int N> struct LdsLayout {
+  static constexpr int NT = N * (N + 1) / 2;
+  static constexpr int DOUBLES = NT + 6 * N;
+  double *A, *invd, *uinv, *vb, *vS, *vz, *vw;
+  __device__ __forceinline__ explicit LdsLayout(double *base)
+      : A(base), invd(base + NT), uinv(base + NT + N), vb(base + NT + 2 * N), vS(base + NT + 3 * N),
+        vz(base + NT + 4 * N), vw(base + NT + 5 * N) {}
+};
+
+// --------------------------------------------------------------------------
+// The kernel.  GRAD adds the adjoint (grad w.r.t. log10 tau, and per-candidate
+// records for the target gradient).
+// --------------------------------------------------------------------------
+// target waves per SIMD: bounds the register budget of each instantiation
+template <int N, int SP> constexpr int waves_per_simd() { return (SP == 1 && N <= 6) ? 3 : 2; }
+
+template <int N, int SP, bool GRAD>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_simd<N, SP>())))
+void fit_kernel(const FitArgs a) {
+  using S = Shape<N, SP>;
+  constexpr int NB = S::NB, NV = S::NV, NG = S::NG, D = S::D;
+  extern __shared__ double lds_all[];
+
+  const int lane = threadIdx.x;
+  const int SF = a.freq_split;
+  const int SL = SP * SF;            // lanes per candidate
+  const int grp = lane / SL;         // candidate slot in the wave
+  const int sub = lane - grp * SL;
+  const int q = sub % SP;            // pole block
+  const int fl = sub / SP;           // frequency lane
+  const int64_t slot = (int64_t)blockIdx.x * a.cand_per_wave + grp;
+  const int32_t cand = a.lane_cand[slot];
+  const bool active = cand >= 0;
+  const int32_t mat = active ? a.lane_mat[slot] : 0;
+  const int64_t c = active ? cand : 0;
+
+  int64_t f0 = 0, F = 0;
+  if (active) {
+    f0 = a.f_off[mat];
+    F = a.f_off[mat + 1] - f0;
+  }
+  const double *om = a.omega + f0;
+  const double *epr = a.eps_re + f0;
+  const double *epi = a.eps_im + f0;
+  const double damping = a.damping;
+  const bool flip = !(a.flags & FLAG_NO_SIGN_FLIP);
+
+  // ---- relaxation times of the owned poles
+  double tau[NB], th[NB];
+  bool bad = false;
+#pragma unroll
+  for (int cI = 0; cI < NB; ++cI) {
+    const int p = q * NB + cI;
+    th[cI] = 0.0;
+    tau[cI] = 0.0;
+    if (p < N && active) {
+      const double t = a.theta[c * a.ld + p];
+      th[cI] = t;
+      bad = bad || !(fabs(t) <= THETA_LIMIT);
+      tau[cI] = exp10(t);
+    }
+  }
+
+  // ---- pass 1: Gram, right-hand side, column sums of R, sum of eps'
+  double G[NG], bv[NB], Sv[NB];
+#pragma unroll
+  for (int e = 0; e < NG; ++e) G[e] = 0.0;
+#pragma unroll
+  for (int cI = 0; cI < NB; ++cI) {
+    bv[cI] = 0.0;
+    Sv[cI] = 0.0;
+  }
+  double sum_er = 0.0;
+  {
+    int64_t k = fl;
+    double w_n = 0, er_n = 0, ei_n = 0;
+    if (k < F) {
+      w_n = om[k];
+      er_n = epr[k];
+      ei_n = epi[k];
+    }
+    for (; k < F; k += SF) {
+      const double w = w_n, er = er_n, ei = ei_n;
+      const int64_t kn = k + SF;
+      if (kn < F) {
+        w_n = om[kn];
+        er_n = epr[kn];
+        ei_n = epi[kn];
+      }
+      double Iv[NV];
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) {
+        const double x = w * tau[cI];
+        const double R = rcp_nr(__builtin_fma(x, x, 1.0));
+        const double I = x * R;
+        Sv[cI] += R;
+        bv[cI] = __builtin_fma(I, ei, bv[cI]);
+        Iv[cI] = I;
+      }
+      if constexpr (SP > 1) {
+#pragma unroll
+        for (int v = NB; v < NV; ++v) Iv[v] = ring_fetch<SP>(Iv[v % NB], v / NB);
+#pragma unroll
+        for (int cI = 0; cI < NB; ++cI)
+#pragma unroll
+          for (int d = 0; d <= D; ++d) G[cI * (D + 1) + d] = __builtin_fma(Iv[cI], Iv[cI + d], G[cI * (D + 1) + d]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int j = i; j < N; ++j) G[tri(N, i, j)] = __builtin_fma(Iv[i], Iv[j], G[tri(N, i, j)]);
+      }
+      sum_er += er;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NG; ++e) G[e] = freq_sum(G[e], SP, SL);
+#pragma unroll
+  for (int cI = 0; cI < NB; ++cI) {
+    bv[cI] = freq_sum(bv[cI], SP, SL);
+    Sv[cI] = freq_sum(Sv[cI], SP, SL);
+    bad = bad || !(fabs(bv[cI]) < INFINITY);
+  }
+  sum_er = freq_sum(sum_er, SP, SL);
+  bad = bad || !(fabs(sum_er) < INFINITY);
+  bad = group_sum<SP>(bad ? 1.0 : 0.0) != 0.0;
+
+  // ---- DLS solve (equilibrated, damped Cholesky)
+  const double tol = 8.0 * (double)(F > N ? F : N) * 0x1.0p-53;
+  double zt[NB], zc[NB], invd_own[NB];
+  bool ok;
+  double *L = nullptr;
+  double uinv_r[SP == 1 ? N : 1], invd_r[SP == 1 ? N : 1];
+  if constexpr (SP == 1) {
+    ok = equilibrate_factor<N>(G, invd_r, uinv_r, damping, tol);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      zt[i] = bv[i] * invd_r[i];
+      invd_own[i] = invd_r[i];
+    }
+    chol_solve<N>(G, uinv_r, zt);
+  } else {
+    // assemble the packed triangle in LDS (all lanes of a candidate write the same values)
+    L = lds_all + (int64_t)grp * S::LDS_DOUBLES;
+    const LdsLayout<N> lay(L);
+    double *A = lay.A, *invd = lay.invd, *uinv = lay.uinv, *vb = lay.vb, *vS = lay.vS, *vz = lay.vz;
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) {
+      const int p1 = q * NB + cI;
+#pragma unroll
+      for (int d = 0; d <= D; ++d) {
+        int p2 = p1 + d;
+        if (p2 >= S::NP) p2 -= S::NP;
+        if (p1 < N && p2 < N) {
+          const int i = p1 < p2 ? p1 : p2, j = p1 < p2 ? p2 : p1;
+          A[tri(N, i, j)] = G[cI * (D + 1) + d];
+        }
+      }
+      if (p1 < N) {
+        vb[p1] = bv[cI];
+        vS[p1] = Sv[cI];
+      }
+    }
+    __syncthreads();
+    ok = lds_equilibrate_factor(N, A, invd, uinv, damping, tol);
+    for (int i = 0; i < N; ++i) vz[i] = vb[i] * invd[i];
+    lds_chol_solve(N, A, uinv, vz);
+    __syncthreads();
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) {
+      const int p = q * NB + cI;
+      zt[cI] = p < N ? vz[p] : 0.0;
+      invd_own[cI] = p < N ? invd[p] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int cI = 0; cI < NB; ++cI) zc[cI] = zt[cI] * invd_own[cI];
+
+  // ---- pass 2: corrected semi-normal equations, g = I^T (eps'' - I z).
+  // The residual is nearly orthogonal to the columns of I, so g is a sum with
+  // heavy cancellation; it is accumulated in double-double (residual refinement
+  // with the residual products in extra precision).
+  double gv[NB], gl[NB];
+#pragma unroll
+  for (int cI = 0; cI < NB; ++cI) {
+    gv[cI] = 0.0;
+    gl[cI] = 0.0;
+  }
+  {
+    int64_t k = fl;
+    double w_n = 0, ei_n = 0;
+    if (k < F) {
+      w_n = om[k];
+      ei_n = epi[k];
+    }
+    for (; k < F; k += SF) {
+      const double w = w_n, ei = ei_n;
+      const int64_t kn = k + SF;
+      if (kn < F) {
+        w_n = om[kn];
+        ei_n = epi[kn];
+      }
+      double Iv[NB];
+      double part = 0.0;
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) {
+        const double x = w * tau[cI];
+        const double R = rcp_nr(__builtin_fma(x, x, 1.0));
+        Iv[cI] = x * R;
+        part = __builtin_fma(Iv[cI], zc[cI], part);
+      }
+      const double r = ei - group_sum<SP>(part);
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) dd_fma_acc(gv[cI], gl[cI], Iv[cI], r);
+    }
+  }
+#pragma unroll
+  for (int cI = 0; cI < NB; ++cI) gv[cI] = freq_sum_dd(gv[cI], gl[cI], SP, SL);
+
+  // correction: zt += A^-1 (D^-1 g - damping zt)
+  if constexpr (SP == 1) {
+    double dz[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) dz[i] = __builtin_fma(gv[i], invd_r[i], -damping * zt[i]);
+    chol_solve<N>(G, uinv_r, dz);
+#pragma unroll
+    for (int i = 0; i < N; ++i) zt[i] += dz[i];
+  } else {
+    const LdsLayout<N> lay(L);
+    double *A = lay.A, *uinv = lay.uinv, *vw = lay.vw;
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) {
+      const int p = q * NB + cI;
+      if (p < N) vw[p] = __builtin_fma(gv[cI], invd_own[cI], -damping * zt[cI]);
+    }
+    __syncthreads();
+    lds_chol_solve(N, A, uinv, vw);
+    __syncthreads();
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) {
+      const int p = q * NB + cI;
+      zt[cI] += p < N ? vw[p] : 0.0;
+    }
+  }
+  double wv_[NB];
+  double ws_part = 0.0;
+#pragma unroll
+  for (int cI = 0; cI < NB; ++cI) {
+    zc[cI] = zt[cI] * invd_own[cI];
+    wv_[cI] = flip ? fabs(zc[cI]) : zc[cI];
+    ws_part = __builtin_fma(wv_[cI], Sv[cI], ws_part);
+  }
+  const double einf = (F > 0) ? (sum_er - group_sum<SP>(ws_part)) / (double)F : 0.0;
+
+  // ---- pass 3: residuals and cost (+ g_w for the adjoint)
+  double cost = 0.0;
+  double gw[GRAD ? NB : 1];
+#pragma unroll
+  for (int cI = 0; cI < (GRAD ? NB : 1); ++cI) gw[cI] = 0.0;
+  {
+    int64_t k = fl;
+    double w_n = 0, er_n = 0, ei_n = 0;
+    if (k < F) {
+      w_n = om[k];
+      er_n = epr[k];
+      ei_n = epi[k];
+    }
+    for (; k < F; k += SF) {
+      const double w = w_n, er = er_n, ei = ei_n;
+      const int64_t kn = k + SF;
+      if (kn < F) {
+        w_n = om[kn];
+        er_n = epr[kn];
+        ei_n = epi[kn];
+      }
+      double Rv[NB], Iv[NB];
+      double pr = 0.0, pi = 0.0;
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) {
+        const double x = w * tau[cI];
+        Rv[cI] = rcp_nr(__builtin_fma(x, x, 1.0));
+        Iv[cI] = x * Rv[cI];
+        pr = __builtin_fma(wv_[cI], Rv[cI], pr);
+        pi = __builtin_fma(wv_[cI], Iv[cI], pi);
+      }
+      const double rr = (er - einf) - group_sum<SP>(pr);
+      const double ri = ei - group_sum<SP>(pi);
+      cost = __builtin_fma(rr, rr, cost);
+      cost = __builtin_fma(ri, ri, cost);
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int cI = 0; cI < NB; ++cI) gw[cI] = __builtin_fma(Rv[cI], rr, __builtin_fma(Iv[cI], ri, gw[cI]));
+      }
+    }
+  }
+  cost = freq_sum(cost, SP, SL);
+
+  const bool sing = !ok;
+  const int st = bad ? ST_BADINPUT : (sing ? ST_SINGULAR : ST_OK);
+  const bool writer = active && fl == 0;
+  double gc = 1.0;
+  if (writer && q == 0) {
+    a.cost[c] = st == ST_OK ? cost : (st == ST_SINGULAR ? INFINITY : NAN);
+    if (a.eps_inf) a.eps_inf[c] = st == ST_OK ? einf : NAN;
+    if (a.status) a.status[c] = (int8_t)st;
+  }
+  if (writer && a.weights) {
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) {
+      const int p = q * NB + cI;
+      if (p < N) a.weights[c * a.ld + p] = st == ST_OK ? wv_[cI] : NAN;
+    }
+  }
+  if constexpr (!GRAD) {
+    return;
+  } else {
+    // ---- adjoint: mu = M^-1 (s o g_w), M = D A D
+    if (a.grad_cost) gc = active ? a.grad_cost[c] : 0.0;
+    double mt[NB], mu[NB];
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) {
+      gw[cI] = -2.0 * freq_sum(gw[cI], SP, SL);
+      const double s = (flip && zc[cI] < 0.0) ? -1.0 : 1.0;
+      mt[cI] = s * gw[cI] * invd_own[cI];
+    }
+    if constexpr (SP == 1) {
+      chol_solve<N>(G, uinv_r, mt);
+    } else {
+      const LdsLayout<N> lay(L);
+      double *A = lay.A, *uinv = lay.uinv, *vw = lay.vw;
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) {
+        const int p = q * NB + cI;
+        if (p < N) vw[p] = mt[cI];
+      }
+      __syncthreads();
+      lds_chol_solve(N, A, uinv, vw);
+      __syncthreads();
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) {
+        const int p = q * NB + cI;
+        mt[cI] = p < N ? vw[p] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) mu[cI] = mt[cI] * invd_own[cI];
+
+    // ---- pass 4: basis derivatives against the residuals
+    double T1[NB], T2[NB], T3[NB], T4[NB];
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) T1[cI] = T2[cI] = T3[cI] = T4[cI] = 0.0;
+    {
+      int64_t k = fl;
+      double w_n = 0, er_n = 0, ei_n = 0;
+      if (k < F) {
+        w_n = om[k];
+        er_n = epr[k];
+        ei_n = epi[k];
+      }
+      for (; k < F; k += SF) {
+        const double w = w_n, er = er_n, ei = ei_n;
+        const int64_t kn = k + SF;
+        if (kn < F) {
+          w_n = om[kn];
+          er_n = epr[kn];
+          ei_n = epi[kn];
+        }
+        double xv[NB], Rv[NB], Iv[NB];
+        double pr = 0.0, pi = 0.0, pz = 0.0, pm = 0.0;
+#pragma unroll
+        for (int cI = 0; cI < NB; ++cI) {
+          xv[cI] = w * tau[cI];
+          Rv[cI] = rcp_nr(__builtin_fma(xv[cI], xv[cI], 1.0));
+          Iv[cI] = xv[cI] * Rv[cI];
+          pr = __builtin_fma(wv_[cI], Rv[cI], pr);
+          pi = __builtin_fma(wv_[cI], Iv[cI], pi);
+          pz = __builtin_fma(zc[cI], Iv[cI], pz);
+          pm = __builtin_fma(mu[cI], Iv[cI], pm);
+        }
+        const double rr = (er - einf) - group_sum<SP>(pr);
+        const double ri = ei - group_sum<SP>(pi);
+        const double qz = ei - group_sum<SP>(pz);
+        const double qm = group_sum<SP>(pm);
+#pragma unroll
+        for (int cI = 0; cI < NB; ++cI) {
+          const double x = xv[cI], R = Rv[cI];
+          const double R2 = R * R;
+          const double dR = -2.0 * LN10 * (x * x) * R2;
+          const double dI = LN10 * x * R2 * (1.0 - x * x);
+          T1[cI] = __builtin_fma(dR, rr, __builtin_fma(dI, ri, T1[cI]));
+          T2[cI] = __builtin_fma(dI, qz, T2[cI]);
+          T3[cI] = __builtin_fma(dI, qm, T3[cI]);
+          T4[cI] = __builtin_fma(dI, Iv[cI], T4[cI]);
+        }
+      }
+    }
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) {
+      T1[cI] = freq_sum(T1[cI], SP, SL);
+      T2[cI] = freq_sum(T2[cI], SP, SL);
+      T3[cI] = freq_sum(T3[cI], SP, SL);
+      T4[cI] = freq_sum(T4[cI], SP, SL);
+    }
+    if (writer) {
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) {
+        const int p = q * NB + cI;
+        if (p >= N) continue;
+        double g = -2.0 * wv_[cI] * T1[cI] + mu[cI] * T2[cI] - zc[cI] * T3[cI] -
+                   2.0 * damping * mu[cI] * zc[cI] * T4[cI];
+        if (a.grad_theta) a.grad_theta[c * a.ld + p] = st == ST_OK ? gc * g : NAN;
+        // per-candidate record for the target gradient: [w | z | mu | eps_inf, gc]
+        if (a.record) {
+          double *rec = a.record + c * a.rec_ld;
+          rec[p] = wv_[cI];
+          rec[N + p] = zc[cI];
+          rec[2 * N + p] = mu[cI];
+          if (p == 0) {
+            rec[3 * N] = einf;
+            rec[3 * N + 1] = st == ST_OK ? gc : 0.0;
+          }
+        }
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Target gradient: for each material and frequency point, the sum over its
+// candidates (in index order) of gc * (2 r'_k) and gc * (2 r''_k + (I mu)_k),
+// recomputed from the per-candidate records of the adjoint kernel.
+// --------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void target_grad_kernel(const TargetGradArgs a, int32_t n_mats) {
+  for (int32_t mi = blockIdx.y; mi < n_mats; mi += gridDim.y) {
+  const int32_t m = a.mat_list[mi];
+  const int64_t f0 = a.f_off[m], F = a.f_off[m + 1] - f0;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= F) continue;
+  const double w = a.omega[f0 + k], er = a.eps_re[f0 + k], ei = a.eps_im[f0 + k];
+  double sr = 0.0, si = 0.0;
+  for (int64_t c = a.cand_off[m]; c < a.cand_off[m + 1]; ++c) {
+    const double *rec = a.record + c * a.rec_ld;
+    const double gc = rec[3 * N + 1];
+    if (gc == 0.0) continue;
+    double pr = 0.0, pi = 0.0, pm = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const double x = w * exp10(a.theta[c * a.ld + i]);
+      const double R = rcp_nr(__builtin_fma(x, x, 1.0));
+      const double I = x * R;
+      pr = __builtin_fma(rec[i], R, pr);
+      pi = __builtin_fma(rec[i], I, pi);
+      pm = __builtin_fma(rec[2 * N + i], I, pm);
+    }
+    const double rr = (er - rec[3 * N]) - pr;
+    const double ri = ei - pi;
+    sr = __builtin_fma(gc, 2.0 * rr, sr);
+    si = __builtin_fma(gc, __builtin_fma(2.0, ri, pm), si);
+  }
+  a.grad_re[f0 + k] = sr;
+  a.grad_im[f0 + k] = si;
+  }
+}
+
+// --------------------------------------------------------------------------
+// dispatch tables
+// --------------------------------------------------------------------------
+constexpr int pole_split_for(int n) { return n <= 8 ? 1 : (n <= 12 ? 2 : 4); }
+
+template <int N> int lds_bytes_per_cand() { return Shape<N, pole_split_for(N)>::LDS_DOUBLES * 8; }
+
+template <int N> hipError_t launch_fit_n(const FitArgs &a, int64_t n_tiles, bool grad, hipStream_t s) {
+  constexpr int SP = pole_split_for(N);
+  const size_t lds = (size_t)Shape<N, SP>::LDS_DOUBLES * 8 * a.cand_per_wave;
+  if (grad)
+    hipLaunchKernelGGL((fit_kernel<N, SP, true>), dim3((unsigned)n_tiles), dim3(64), lds, s, a);
+  else
+    hipLaunchKernelGGL((fit_kernel<N, SP, false>), dim3((unsigned)n_tiles), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int N> hipError_t launch_target_n(const TargetGradArgs &a, int64_t max_f, int32_t n_mats, hipStream_t s) {
+  dim3 grid((unsigned)((max_f + 255) / 256), (unsigned)(n_mats < 65535 ? n_mats : 65535));
+  hipLaunchKernelGGL((target_grad_kernel<N>), grid, dim3(256), 0, s, a, n_mats);
+  return hipGetLastError();
+}
+
+template <int... Ns> struct Table {
+  static int pole_split(int n) {
+    int r = 0;
+    ((n == Ns ? (r = pole_split_for(Ns)) : 0), ...);
+    return r;
+  }
+  static int lds(int n) {
+    int r = 0;
+    ((n == Ns ? (r = lds_bytes_per_cand<Ns>()) : 0), ...);
+    return r;
+  }
+  static hipError_t fit(int n, const FitArgs &a, int64_t tiles, bool grad, hipStream_t s) {
+    hipError_t e = hipErrorInvalidValue;
+    ((n == Ns ? (e = launch_fit_n<Ns>(a, tiles, grad, s)) : hipSuccess), ...);
+    return e;
+  }
+  static hipError_t target(int n, const TargetGradArgs &a, int64_t max_f, int32_t n_mats, hipStream_t s) {
+    hipError_t e = hipErrorInvalidValue;
+    ((n == Ns ? (e = launch_target_n<Ns>(a, max_f, n_mats, s)) : hipSuccess), ...);
+    return e;
+  }
+};
+using AllN = Table<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24>;
+
+int pole_split(int n) { return AllN::pole_split(n); }
+int lds_bytes_per_candidate(int n) { return AllN::lds(n); }
+hipError_t launch_fit(int n, const FitArgs &a, int64_t n_tiles, bool grad, hipStream_t s) {
+  return AllN::fit(n, a, n_tiles, grad, s);
+}
+hipError_t launch_target_grad(int n, const TargetGradArgs &a, int64_t max_f, int32_t n_mats, hipStream_t s) {
+  return AllN::target(n, a, max_f, n_mats, s);
+}
+
+}  // namespace dfit

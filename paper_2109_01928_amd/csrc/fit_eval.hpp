@@ -1,0 +1,112 @@
+// Internal interface between the C ABI layer and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dfit {
+
+// Arguments of the cost / adjoint kernel (one work tile per 64-lane block).
+struct FitArgs {
+  const int64_t *f_off;
+  const double *omega, *eps_re, *eps_im;
+  const double *theta;
+  int64_t ld;
+  double damping;
+  uint32_t flags;
+  int32_t freq_split;     // SF: lanes per candidate along the frequency axis
+  int32_t cand_per_wave;  // 64 / (SP * SF)
+  const int32_t *lane_cand;  // [tiles * cand_per_wave] candidate index or -1
+  const int32_t *lane_mat;   // [tiles * cand_per_wave] material of that candidate
+  double *cost, *weights, *eps_inf;
+  int8_t *status;
+  // adjoint
+  const double *grad_cost;
+  double *grad_theta;
+  double *record;  // [n_cand][rec_ld] per-candidate w | z | mu | eps_inf, gc (or NULL)
+  int64_t rec_ld;
+};
+
+struct TargetGradArgs {
+  const int64_t *f_off, *cand_off;
+  const double *omega, *eps_re, *eps_im, *theta;
+  int64_t ld;
+  const double *record;
+  int64_t rec_ld;
+  const int32_t *mat_list;  // materials with this pole count
+  double *grad_re, *grad_im;
+};
+
+int pole_split(int n_poles);
+int lds_bytes_per_candidate(int n_poles);
+hipError_t launch_fit(int n_poles, const FitArgs &a, int64_t n_tiles, bool grad, hipStream_t s);
+hipError_t launch_target_grad(int n_poles, const TargetGradArgs &a, int64_t max_f, int32_t n_mats,
+                              hipStream_t s);
+
+// other kernels
+struct MaterialArgs {
+  int32_t M;
+  const int8_t *kind;
+  const double *params;
+  const int64_t *f_off;
+  int64_t n_freq;
+  const double *omega;
+  uint64_t noise_seed;
+  double *eps_re, *eps_im, *jac;
+};
+hipError_t launch_material(const MaterialArgs &a, hipStream_t s);
+hipError_t launch_material_vjp(int32_t M, const int64_t *f_off, const double *jac, const double *g_re,
+                               const double *g_im, double *gp, hipStream_t s);
+
+hipError_t launch_basis(const double *omega, int64_t F, const double *theta, int64_t ld, int64_t n_cand, int32_t N,
+                        double *re, double *im, hipStream_t s);
+
+struct PsoArgs {
+  int32_t M;
+  const int64_t *cand_off;
+  const int32_t *n_poles;
+  int64_t ld;
+  const double *lb, *ub;
+  double inertia, c1, c2;
+  uint64_t seed;
+  int32_t t, move;
+  const double *cost;
+  double *x, *v, *pbest_x, *pbest_cost, *gbest_x, *gbest_cost;
+  int64_t *gbest_idx;
+  double *history;
+  int64_t hist_ld;
+};
+hipError_t launch_pso_init(const PsoArgs &a, int64_t n_cand, hipStream_t s);
+hipError_t launch_pso_step(const PsoArgs &a, hipStream_t s);
+
+struct LbfgsArgs {
+  int32_t M;
+  const int32_t *n_poles;
+  int64_t ld;
+  int32_t mem, max_trials;
+  double c1;
+  const double *lb, *ub;  // [M] search box
+  double *theta;       // [M][ld] current point
+  double *cost;        // [M] cost at theta
+  double *grad;        // [M][ld] gradient at theta
+  double *S, *Y;       // [M][mem][ld] history (ring)
+  double *rho;         // [M][mem]
+  int32_t *hist_n, *hist_head;  // [M]
+  double *dir;         // [M][ld]
+  double *gd;          // [M] g.d of the chosen direction
+  double *trial_theta; // [M*max_trials][ld]
+  const double *trial_cost;  // [M*max_trials]
+  const int8_t *trial_status;
+  double *new_theta;   // [M][ld] accepted point
+  double *acc_cost;    // [M] cost of the accepted trial
+  int32_t *accepted;   // [M]
+  const double *new_cost, *new_grad;  // cost / gradient at new_theta
+  const int8_t *new_status;
+  double *cost_hist;   // [M][steps+1] or NULL
+  int32_t step, steps;
+};
+hipError_t launch_lbfgs_direction(const LbfgsArgs &a, hipStream_t s);
+hipError_t launch_lbfgs_select(const LbfgsArgs &a, hipStream_t s);
+hipError_t launch_lbfgs_update(const LbfgsArgs &a, hipStream_t s);
+
+}  // namespace dfit

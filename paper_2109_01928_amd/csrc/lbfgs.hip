@@ -1,0 +1,172 @@
+// Gradient polish of each material's best candidate: L-BFGS (Liu & Nocedal
+// 1989) with the two-loop recursion (Nocedal & Wright, Algorithm 7.4) and
+// Armijo backtracking alpha = 1, 1/2, 1/4, ... inside the search box: each
+// trial point is projected onto [lb, ub] and the sufficient-decrease test uses
+// the projected displacement p, C(trial) <= C + c1 g.p.  The trial points of
+// one step are all evaluated in one batched cost launch, and the accepted step
+// is the first trial (largest alpha) that passes, which is what a sequential
+// halving search returns.  One thread per material.
+
+#include "common.hpp"
+#include "fit_eval.hpp"
+
+namespace dfit {
+
+__global__ __launch_bounds__(256) void lbfgs_direction_kernel(const LbfgsArgs a) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.M) return;
+  const int N = a.n_poles[m];
+  const int64_t ld = a.ld;
+  const double *g = a.grad + (int64_t)m * ld;
+  double *d = a.dir + (int64_t)m * ld;
+  const double C = a.cost[m];
+  if (a.cost_hist) a.cost_hist[(int64_t)m * (a.steps + 1) + a.step] = C;
+  bool skip = !(fabs(C) < INFINITY);
+  for (int i = 0; i < N; ++i) skip = skip || !(fabs(g[i]) < INFINITY);
+  double gd = 0.0;
+  if (!skip) {
+    const int mem = a.mem;
+    int n = a.hist_n[m];
+    const int head = a.hist_head[m];
+    double q[DFIT_MAX_POLES], alpha[DFIT_MAX_MEM];
+    for (int i = 0; i < N; ++i) q[i] = g[i];
+    // newest to oldest
+    for (int j = n - 1; j >= 0; --j) {
+      const int slot = (head - n + j + mem) % mem;
+      const double *s = a.S + ((int64_t)m * mem + slot) * ld;
+      const double *y = a.Y + ((int64_t)m * mem + slot) * ld;
+      double t = 0.0;
+      for (int i = 0; i < N; ++i) t += s[i] * q[i];
+      alpha[j] = a.rho[(int64_t)m * mem + slot] * t;
+      for (int i = 0; i < N; ++i) q[i] -= alpha[j] * y[i];
+    }
+    double gamma = 1.0;
+    if (n > 0) {
+      const int slot = (head - 1 + mem) % mem;
+      const double *s = a.S + ((int64_t)m * mem + slot) * ld;
+      const double *y = a.Y + ((int64_t)m * mem + slot) * ld;
+      double sy = 0.0, yy = 0.0;
+      for (int i = 0; i < N; ++i) {
+        sy += s[i] * y[i];
+        yy += y[i] * y[i];
+      }
+      gamma = sy / yy;
+    }
+    for (int i = 0; i < N; ++i) q[i] *= gamma;
+    for (int j = 0; j < n; ++j) {
+      const int slot = (head - n + j + mem) % mem;
+      const double *s = a.S + ((int64_t)m * mem + slot) * ld;
+      const double *y = a.Y + ((int64_t)m * mem + slot) * ld;
+      double t = 0.0;
+      for (int i = 0; i < N; ++i) t += y[i] * q[i];
+      const double b = a.rho[(int64_t)m * mem + slot] * t;
+      for (int i = 0; i < N; ++i) q[i] += (alpha[j] - b) * s[i];
+    }
+    for (int i = 0; i < N; ++i) {
+      d[i] = -q[i];
+      gd += g[i] * d[i];
+    }
+    if (n == 0 || !(gd < 0.0)) {
+      // steepest descent, largest component at most one decade
+      a.hist_n[m] = 0;
+      double gmax = 0.0;
+      for (int i = 0; i < N; ++i) gmax = fmax(gmax, fabs(g[i]));
+      if (!(gmax > 0.0)) {
+        skip = true;
+      } else {
+        const double sc = fmin(1.0, 1.0 / gmax);
+        gd = 0.0;
+        for (int i = 0; i < N; ++i) {
+          d[i] = -g[i] * sc;
+          gd += g[i] * d[i];
+        }
+      }
+    }
+  }
+  a.gd[m] = skip ? NAN : gd;
+  const double *th = a.theta + (int64_t)m * ld;
+  const double lo = a.lb[m], hi = a.ub[m];
+  double alpha_t = 1.0;
+  for (int t = 0; t < a.max_trials; ++t) {
+    double *tt = a.trial_theta + ((int64_t)m * a.max_trials + t) * ld;
+    for (int i = 0; i < N; ++i) {
+      const double v = th[i] + alpha_t * d[i];
+      tt[i] = skip ? th[i] : (v < lo ? lo : (v > hi ? hi : v));
+    }
+    alpha_t *= 0.5;
+  }
+}
+
+__global__ __launch_bounds__(256) void lbfgs_select_kernel(const LbfgsArgs a) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.M) return;
+  const int N = a.n_poles[m];
+  const double gd = a.gd[m];
+  const double C = a.cost[m];
+  int pick = -1;
+  const double *g = a.grad + (int64_t)m * a.ld;
+  const double *th = a.theta + (int64_t)m * a.ld;
+  if (gd == gd) {  // not skipped
+    for (int t = 0; t < a.max_trials; ++t) {
+      const int64_t r = (int64_t)m * a.max_trials + t;
+      const double *tt = a.trial_theta + r * a.ld;
+      double gp = 0.0;
+      for (int i = 0; i < N; ++i) gp += g[i] * (tt[i] - th[i]);
+      if (a.trial_status[r] == ST_OK && a.trial_cost[r] <= C + a.c1 * gp) {
+        pick = t;
+        break;
+      }
+    }
+  }
+  a.accepted[m] = pick >= 0 ? 1 : 0;
+  a.acc_cost[m] = pick >= 0 ? a.trial_cost[(int64_t)m * a.max_trials + pick] : C;
+  const double *src = pick >= 0 ? a.trial_theta + ((int64_t)m * a.max_trials + pick) * a.ld : a.theta + (int64_t)m * a.ld;
+  for (int i = 0; i < N; ++i) a.new_theta[(int64_t)m * a.ld + i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void lbfgs_update_kernel(const LbfgsArgs a) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.M) return;
+  const int N = a.n_poles[m];
+  const int64_t ld = a.ld;
+  if (a.accepted[m]) {
+    const int mem = a.mem;
+    const int head = a.hist_head[m];
+    double *s = a.S + ((int64_t)m * mem + head) * ld;
+    double *y = a.Y + ((int64_t)m * mem + head) * ld;
+    double sy = 0.0;
+    for (int i = 0; i < N; ++i) {
+      s[i] = a.new_theta[m * ld + i] - a.theta[m * ld + i];
+      y[i] = a.new_grad[m * ld + i] - a.grad[m * ld + i];
+      sy += s[i] * y[i];
+    }
+    if (sy > 1e-300) {
+      a.rho[(int64_t)m * mem + head] = 1.0 / sy;
+      a.hist_head[m] = (head + 1) % mem;
+      a.hist_n[m] = a.hist_n[m] < mem ? a.hist_n[m] + 1 : mem;
+    }
+    for (int i = 0; i < N; ++i) {
+      a.theta[m * ld + i] = a.new_theta[m * ld + i];
+      a.grad[m * ld + i] = a.new_grad[m * ld + i];
+    }
+    a.cost[m] = a.acc_cost[m];  // the evaluation the acceptance test used
+  }
+  if (a.cost_hist && a.step == a.steps - 1) a.cost_hist[(int64_t)m * (a.steps + 1) + a.steps] = a.cost[m];
+}
+
+static dim3 grid_for(int32_t M) { return dim3((unsigned)((M + 255) / 256)); }
+
+hipError_t launch_lbfgs_direction(const LbfgsArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(lbfgs_direction_kernel, grid_for(a.M), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_lbfgs_select(const LbfgsArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(lbfgs_select_kernel, grid_for(a.M), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_lbfgs_update(const LbfgsArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(lbfgs_update_kernel, grid_for(a.M), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace dfit

@@ -1,0 +1,122 @@
+"""Shared helpers for the GPU parity tests: build the same seeded batch for the
+oracle (CPU) and for the library (GPU), and the comparison rules."""
+import numpy as np
+
+import workloads as W
+
+COST_RTOL = 1e-10      # cost relative error vs the FP64 oracle
+WEIGHT_RTOL = 1e-8     # weights / eps_inf: max |diff| / max |ref| per candidate
+
+
+def targets_oracle(orc, wl):
+    return orc.material_eval(wl.kind, wl.params, wl.f_off, wl.omega, noise_seed=wl.noise_seed)
+
+
+def cost_floor(wl, er, ei):
+    """Scale below which a cost counts as zero: 1e-12 * sum(eps'^2 + eps''^2) of
+    the candidate's material (exact-recovery cases have cost ~ 0)."""
+    per_m = np.array([np.sum(er[wl.f_off[m]:wl.f_off[m + 1]] ** 2 + ei[wl.f_off[m]:wl.f_off[m + 1]] ** 2)
+                      for m in range(wl.M)])
+    P = np.diff(wl.cand_off)
+    return 1e-12 * np.repeat(per_m, P)
+
+
+def cost_rel_err(c, ref, floor):
+    c = np.asarray(c)
+    ref = np.asarray(ref)
+    fin = np.isfinite(ref)
+    out = np.zeros_like(ref)
+    out[fin] = np.abs(c[fin] - ref[fin]) / np.maximum(np.abs(ref[fin]), floor[fin])
+    # non-finite references must be reproduced exactly (inf stays inf, NaN stays NaN)
+    bad = ~fin & ~((np.isnan(ref) & np.isnan(c)) | (ref == c))
+    out[bad] = np.inf
+    return out
+
+
+def attributed_cost_err(orc, ob, theta, c_gpu, floor, damping, flags, rel64, stats=None):
+    """Cost error after attribution.  A candidate whose error against the FP64
+    oracle exceeds COST_RTOL is judged against the 80-bit (long double)
+    instance of the same oracle, the more accurate reference.  If it still
+    exceeds COST_RTOL there, the candidate is ill-conditioned beyond what any
+    FP64 evaluation can resolve (near-duplicate relaxation times); it passes
+    when the GPU is at least as close to the 80-bit result as the FP64 oracle
+    is (its error is reported as 0 after that check, and counted in stats).
+    Returns (errors, number of candidates judged against the 80-bit oracle)."""
+    over = rel64 > COST_RTOL
+    if stats is not None:
+        stats.update(n=len(rel64), oracle_limited=0, fp64_limited=0, max_rel_80=0.0)
+    if not over.any():
+        return rel64, 0
+    c80 = orc.fit_eval(ob, theta, damping=damping, flags=flags, precision=80)[0]
+    rel80 = cost_rel_err(c_gpu, c80, floor)
+    c64 = np.asarray(ob_cost64(orc, ob, theta, damping, flags))
+    own = cost_rel_err(c64, c80, floor)                 # the FP64 oracle's own error
+    out = rel64.copy()
+    out[over] = rel80[over]
+    limited = over & (rel80 > COST_RTOL) & (rel80 <= own)
+    if stats is not None:
+        stats.update(oracle_limited=int((over & (rel80 <= COST_RTOL)).sum()), fp64_limited=int(limited.sum()),
+                     max_rel_80=float(rel80[over].max()))
+    out[limited] = 0.0
+    return out, int(over.sum())
+
+
+def ob_cost64(orc, ob, theta, damping, flags):
+    return orc.fit_eval(ob, theta, damping=damping, flags=flags)[0]
+
+
+def weight_rel_err(w, ref, n_poles_per_cand):
+    err = np.zeros(len(ref))
+    for i, (a, r, n) in enumerate(zip(w, ref, n_poles_per_cand)):
+        a, r = a[:n], r[:n]
+        if not np.all(np.isfinite(r)):
+            err[i] = 0.0 if np.array_equal(np.isnan(a), np.isnan(r)) else np.inf
+            continue
+        err[i] = np.max(np.abs(a - r)) / max(np.max(np.abs(r)), 1e-300)
+    return err
+
+
+def poles_per_cand(wl):
+    return np.repeat(wl.n_poles, np.diff(wl.cand_off))
+
+
+def small_uniform(M, F, N, P, seed, fmin=1e6, fmax=1e10, kinds=None):
+    kind, params = W.draw_mixed(M, seed, fmin, fmax, kinds=kinds)
+    lb, ub = W.tau_bounds(fmin, fmax)
+    om = W.log_grid(fmin, fmax, F)
+    return W.Workload(f"test M{M} F{F} N{N} P{P}", kind, params, W.offsets([F] * M), np.tile(om, M),
+                      np.full(M, N, np.int32), W.offsets([P] * M), np.full(M, lb), np.full(M, ub), 1, seed=seed)
+
+
+def small_ragged(M, seed, Fr=(20, 700), Nr=(1, 24), Pr=(0, 150)):
+    kind, params = W.draw_mixed(M, seed, 1e6, 1e10)
+    g = W.rng(seed, 9)
+    Fm = g.integers(Fr[0], Fr[1] + 1, size=M)
+    Nm = g.integers(Nr[0], Nr[1] + 1, size=M).astype(np.int32)
+    Pm = g.integers(Pr[0], Pr[1] + 1, size=M)
+    lb, ub = W.tau_bounds(1e6, 1e10)
+    om = np.concatenate([W.log_grid(1e6, 1e10, int(f)) for f in Fm])
+    return W.Workload(f"ragged M{M}", kind, params, W.offsets(Fm), om, Nm, W.offsets(Pm), np.full(M, lb),
+                      np.full(M, ub), 1, seed=seed)
+
+
+def attributed_weight_err(orc, ob, theta, w_gpu, e_gpu, ok, npc, damping, flags, w64, e64):
+    """Weight and eps_inf errors after the same attribution as the cost: a
+    candidate over WEIGHT_RTOL against the FP64 oracle is judged against the
+    80-bit instance.  Returns (weight errors, eps_inf errors, n oracle-limited)."""
+    werr = weight_rel_err(w_gpu[ok], w64[ok], npc[ok])
+    eerr = np.abs(e_gpu[ok] - e64[ok]) / np.maximum(np.abs(e64[ok]), 1e-300)
+    over = (werr > WEIGHT_RTOL) | (eerr > WEIGHT_RTOL)
+    if not over.any():
+        return werr, eerr, 0
+    _, w80, e80, _ = orc.fit_eval(ob, theta, damping=damping, flags=flags, precision=80)
+    w80g = weight_rel_err(w_gpu[ok][over], w80[ok][over], npc[ok][over])
+    e80g = (np.abs(e_gpu[ok] - e80[ok]) / np.maximum(np.abs(e80[ok]), 1e-300))[over]
+    # FP64-limited: the GPU is at least as close to the 80-bit result as the FP64 oracle
+    w_own = weight_rel_err(w64[ok][over], w80[ok][over], npc[ok][over])
+    e_own = (np.abs(e64[ok] - e80[ok]) / np.maximum(np.abs(e80[ok]), 1e-300))[over]
+    w80g[(w80g > WEIGHT_RTOL) & (w80g <= w_own)] = 0.0
+    e80g[(e80g > WEIGHT_RTOL) & (e80g <= e_own)] = 0.0
+    werr[over] = w80g
+    eerr[over] = e80g
+    return werr, eerr, int(over.sum())

@@ -1,0 +1,173 @@
+"""GPU parity of the HIP library against the FP64 oracle, called through the C
+ABI (via the thin binding).  Same seeded inputs on both sides; targets are
+computed by the oracle and uploaded, so the cost kernels see identical data."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from _helpers import (COST_RTOL, WEIGHT_RTOL, attributed_cost_err, attributed_weight_err, cost_floor, cost_rel_err,
+                      poles_per_cand, small_ragged, small_uniform, targets_oracle)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    import paper_2109_01928_amd as D
+
+    assert torch.cuda.is_available()
+    D.lib()
+    return D
+
+
+def _gpu_batch(D, wl, er, ei):
+    import torch
+    return D.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, torch.tensor(er, device="cuda"),
+                   torch.tensor(ei, device="cuda"))
+
+
+def _check_eval(D, orc, wl, theta, damping=1e-8, flags=0, split=None, tag=""):
+    import torch
+    er, ei = targets_oracle(orc, wl)
+    ob = orc.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, er, ei)
+    oc, ow, oe, ost = orc.fit_eval(ob, theta, damping=damping, flags=flags)
+    b = _gpu_batch(D, wl, er, ei)
+    plan = D.Plan(b)
+    if split:
+        plan.set_freq_split(split)
+    th = torch.tensor(theta, device="cuda")
+    c, w, e, st = D.fit_eval(plan, b, th, damping=damping, flags=flags)
+    torch.cuda.synchronize()
+    c, w, e, st = (t.cpu().numpy() for t in (c, w, e, st))
+    print(f"[{tag}] {wl.name} split={split} plan={plan.info()}", flush=True)
+    np.testing.assert_array_equal(st, ost)
+    floor = cost_floor(wl, er, ei)
+    rel, n_lim = attributed_cost_err(orc, ob, theta, c, floor, damping, flags, cost_rel_err(c, oc, floor))
+    worst = int(np.argmax(rel))
+    print(f"[{tag}] max cost rel err {rel.max():.3e}; oracle-limited candidates: {n_lim} of {len(c)}", flush=True)
+    assert rel.max() <= COST_RTOL, f"cost rel err {rel.max():.3e} at candidate {worst}"
+    ok = ost == 0
+    werr, eerr, n_wlim = attributed_weight_err(orc, ob, theta, w, e, ok, poles_per_cand(wl), damping, flags, ow, oe)
+    print(f"[{tag}] max weight rel err {werr.max(initial=0):.3e}, eps_inf {eerr.max(initial=0):.3e}; "
+          f"oracle-limited: {n_wlim}", flush=True)
+    assert werr.max(initial=0) <= WEIGHT_RTOL, f"weight rel err {werr.max():.3e}"
+    assert eerr.max(initial=0) <= WEIGHT_RTOL, f"eps_inf rel err {eerr.max():.3e}"
+    return rel.max(), werr.max(initial=0)
+
+
+# ---------------------------------------------------------------------------
+def test_material_targets_match_oracle(D, orc):
+    import torch
+    for wl in (small_uniform(40, 333, 5, 1, seed=4), small_ragged(30, seed=2), W.tables(M=16, F=257, N=20, P=1)):
+        er, ei = targets_oracle(orc, wl)
+        b = D.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, np.zeros_like(er), np.zeros_like(er))
+        ger, gei = D.material_eval(wl.kind, wl.params, b, noise_seed=wl.noise_seed)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(ger.cpu().numpy(), er, rtol=2e-13, atol=1e-13)
+        np.testing.assert_allclose(gei.cpu().numpy(), ei, rtol=2e-13, atol=1e-13)
+    # Jacobian of the HN family
+    wl = small_uniform(24, 101, 5, 1, seed=8, kinds=[W.KIND_HN, W.KIND_CC, W.KIND_CD])
+    oer, oei, oJ = orc.material_eval(wl.kind, wl.params, wl.f_off, wl.omega, jac=True)
+    b = D.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, oer, oei)
+    ger, gei, gJ = D.material_eval(wl.kind, wl.params, b, jac=True)
+    gJ = gJ.cpu().numpy()
+    scale = np.abs(oJ).max(axis=(0, 2))                       # per parameter column
+    assert np.max(np.abs(gJ - oJ).max(axis=(0, 2)) / scale) < 1e-12
+
+
+def test_basis_matches_oracle(D, orc):
+    import torch
+    om = W.log_grid(1e5, 1e11, 777)
+    theta = np.array([[-12.5, -11.0, -9.3, -7.7, -6.2], [-10.0, -10.0, -8.0, -7.0, -9.9]])
+    re, im = D.basis(torch.tensor(om, device="cuda"), torch.tensor(theta, device="cuda"), 5)
+    for c in range(2):
+        r0, i0 = orc.basis(om, theta[c])
+        np.testing.assert_allclose(re[c].cpu().numpy(), r0, rtol=1e-15, atol=0)
+        np.testing.assert_allclose(im[c].cpu().numpy(), i0, rtol=1e-15, atol=0)
+
+
+def test_listing2_on_gpu(D, orc):
+    import torch
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "listing2.json")))
+    m = g["material"]
+    om = W.log_grid(1e7, 1e11, 100)
+    p = np.zeros((1, 16))
+    p[0, :5] = [m["eps_inf"], m["d_eps"], m["tau0"], m["alpha"], m["beta"]]
+    b = D.Batch([0, 100], [0, 1], [5], om, np.zeros(100), np.zeros(100))
+    er, ei = D.material_eval([W.KIND_HN], p, b)
+    b = b.with_targets(er, ei)
+    th = torch.tensor(np.log10(g["printed_tau"])[None], device="cuda")
+    for damping in (0.0, 1e-8):
+        c, w, e, st = D.fit_eval(D.Plan(b), b, th, damping=damping)
+        assert st.item() == 0
+        np.testing.assert_array_equal(np.round(w.cpu().numpy()[0], 4), g["printed_d_eps"])
+        assert round(e.item(), 4) == g["printed_eps_inf"]
+
+
+# cost parity at the shapes of the benchmark workloads (reduced counts), every
+# pole-count branch and every frequency split
+@pytest.mark.parametrize("F,N,P,M,fmin,fmax", [
+    (50, 5, 40, 1, 1e5, 1e10),        # single HN workload shape
+    (1000, 8, 64, 6, 1e6, 1e10),      # mixed batch shape (bench workload)
+    (2000, 12, 32, 4, 1e5, 1e11),     # differentiation workload shape
+    (4096, 20, 16, 2, 1e5, 1e11),     # tables workload shape
+])
+def test_cost_parity_config_shapes(D, orc, F, N, P, M, fmin, fmax):
+    wl = small_uniform(M, F, N, P, seed=F + N, fmin=fmin, fmax=fmax)
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=N)
+    r, wr = _check_eval(D, orc, wl, theta, tag="shape")
+    print(f"F={F} N={N}: max cost rel err {r:.2e}, weights {wr:.2e}")
+
+
+@pytest.mark.parametrize("N", list(range(1, 25)))
+def test_cost_parity_every_pole_count(D, orc, N):
+    wl = small_uniform(3, 173, N, 70, seed=100 + N)   # 70 candidates: ragged last tile
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=N)
+    for split in (None, 1, 4, 64 // {1: 1, 2: 2, 4: 4}[1 if N <= 8 else (2 if N <= 12 else 4)]):
+        _check_eval(D, orc, wl, theta, split=split, tag=f"N{N}")
+
+
+def test_cost_parity_ragged_batch(D, orc):
+    wl = small_ragged(60, seed=7)
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=3)
+    _check_eval(D, orc, wl, theta, tag="ragged")
+    _check_eval(D, orc, wl, theta, split=8, tag="ragged")
+
+
+def test_edge_cases_and_status(D, orc):
+    wl = small_uniform(2, 64, 4, 8, seed=5)
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=1)
+    theta[1, 2] = np.nan          # BADINPUT
+    theta[2, 0] = 70.0            # |log10 tau| > 64
+    theta[3, 1] = theta[3, 0]     # duplicate tau: singular without damping
+    theta[4, :] = [-11.0, -10.0, -9.0, -8.0]
+    _check_eval(D, orc, wl, theta, damping=1e-8, tag="edge")
+    wl2 = small_uniform(2, 64, 4, 8, seed=5)
+    th2 = theta.copy()
+    th2[[0, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15]] = [-11.5, -10.0, -8.5, -7.2]   # well conditioned
+    _check_eval(D, orc, wl2, th2, damping=0.0, tag="edge-undamped")
+    _check_eval(D, orc, wl, theta, damping=1e-8, flags=1, tag="edge-noflip")
+    # a single frequency point, a single pole
+    wl3 = small_uniform(3, 1, 1, 5, seed=2)
+    th3 = W.draw_theta(wl3.cand_off, wl3.n_poles, wl3.lb, wl3.ub, 1, seed=2)
+    _check_eval(D, orc, wl3, th3, tag="F1N1")
+
+
+def test_empty_materials_and_determinism(D, orc):
+    import torch
+    wl = small_ragged(25, seed=11, Pr=(0, 3))
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=5)
+    _check_eval(D, orc, wl, theta, tag="empty")
+    wl = small_uniform(4, 500, 10, 64, seed=3)
+    er, ei = targets_oracle(orc, wl)
+    b = _gpu_batch(D, wl, er, ei)
+    plan = D.Plan(b)
+    th = torch.tensor(W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=2), device="cuda")
+    c1 = D.fit_eval(plan, b, th)[0].clone()
+    c2 = D.fit_eval(plan, b, th)[0].clone()
+    assert torch.equal(c1, c2)

@@ -117,7 +117,7 @@ def test_pso_finds_single_pole_global_minimum(orc):
     sw = orc.pso_run(b, [-12.0], [-7.0], 30, seed=0)
     assert sw.gbest_cost[0] <= cmin * (1 + 1e-6)
     # polishing from there keeps it at the grid minimum with a vanishing gradient
-    th, hist = orc.lbfgs(orc.Batch([0, 200], [0, 1], [1], om, er, ei), sw.gbest_x, steps=10)
+    th, hist = orc.lbfgs(orc.Batch([0, 200], [0, 1], [1], om, er, ei), sw.gbest_x, -12.0, -7.0, steps=10)
     assert hist[0, -1] <= cmin
     _, g, _, _, _ = orc.fit_grad(orc.Batch([0, 200], [0, 1], [1], om, er, ei), th)
     assert abs(g[0, 0]) < 1e-6 * hist[0, -1]
@@ -129,8 +129,23 @@ def test_lbfgs_monotone_and_improves(orc):
     b = orc.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, er, ei)
     sw = orc.pso_run(b, wl.lb, wl.ub, wl.iters, seed=5)
     bm = orc.Batch(wl.f_off, np.arange(wl.M + 1), wl.n_poles, wl.omega, er, ei)
-    th, hist = orc.lbfgs(bm, sw.gbest_x, steps=30)
+    th, hist = orc.lbfgs(bm, sw.gbest_x, wl.lb, wl.ub, steps=30)
     assert np.all(np.diff(hist, axis=1) <= 0)
+    assert np.all(th >= wl.lb[0]) and np.all(th <= wl.ub[0])
     assert np.all(hist[:, -1] < 0.9 * hist[:, 0])
     c = orc.fit_eval(bm, th)[0]
     np.testing.assert_array_equal(c, hist[:, -1])
+
+
+def test_lbfgs_stays_in_box_from_a_corner(orc):
+    # a swarm best on the corner of the box (many poles at the bound): the
+    # polish must stay inside the box and never increase the cost
+    om = W.log_grid(1e6, 1e10, 400)
+    params = np.zeros((1, 16))
+    params[0, :5] = [3.0, 40.0, 3e-9, 0.5, 0.6]
+    er, ei = orc.material_eval([W.KIND_HN], params, [0, 400], om)
+    th0 = np.array([[-12.0, -7.0, -12.0, -12.0, -12.0, -12.0, -12.0, -12.0]])
+    b = orc.Batch([0, 400], [0, 1], [8], om, er, ei)
+    th, hist = orc.lbfgs(b, th0, -12.0, -7.0, steps=40)
+    assert np.all(th >= -12.0) and np.all(th <= -7.0)
+    assert np.all(np.diff(hist[0]) <= 0) and hist[0, -1] < hist[0, 0]
