@@ -55,6 +55,10 @@ def main():
     ap.add_argument("--polish-steps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-eval", type=int, default=0,
+                    help="profiling: run this many forward launches of the swarm batch and exit")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="profiling: time a device-to-device copy of this many bytes (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the fit shards by material with no communication, "
@@ -68,6 +72,14 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 5}), flush=True)
+        return
     wl = W.mixed_uniform(M=args.materials, F=1000, N=8, P=256, iters=args.iters, seed=0)
     M, P, N, F = wl.M, wl.P, 8, 1000
     T_TRIALS, MEM = 30, 10
@@ -84,6 +96,17 @@ def main():
     sw = D.Swarm.empty(P, M, wl.ld, args.iters + 1, dev)
     out = (torch.empty(P, dtype=torch.float64, device=dev), None, None, torch.empty(P, dtype=torch.int8, device=dev))
     stream = torch.cuda.current_stream()
+
+    if args.only_eval:
+        er, ei = D.material_eval(kind_t, params_t, b)
+        bb = b.with_targets(er, ei)
+        theta = torch.tensor(W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=77), device=dev)
+        for _ in range(args.only_eval):
+            D.fit_eval(plan, bb, theta, want_weights=False, out=out)
+        torch.cuda.synchronize()
+        print(json.dumps({"launches": args.only_eval, "evals_per_launch": P, "flops_per_eval": algorithmic_flops(F, N),
+                          "alg_bytes_per_eval": algorithmic_bytes(F, N, 256)}), flush=True)
+        return
 
     def one_step(events=None):
         er, ei = D.material_eval(kind_t, params_t, b)

@@ -53,7 +53,7 @@ enum {
 /* per-candidate status */
 enum {
   DEBYE_ST_OK = 0,
-  DEBYE_ST_BADINPUT = 1, /* non-finite log10(tau), |log10 tau| > 64, or non-finite
+  DEBYE_ST_BADINPUT = 1, /* non-finite log10(tau), |log10 tau| > 30, or non-finite
                             omega / eps' / eps'' of the material: cost = NaN */
   DEBYE_ST_SINGULAR = 2  /* the scaled damped normal matrix is numerically singular
                             (only reachable with damping ~ 0, e.g. duplicate
@@ -96,7 +96,7 @@ typedef struct debye_batch {
   const int64_t *f_off;    /* [M+1] device */
   const int64_t *cand_off; /* [M+1] device */
   const int32_t *n_poles;  /* [M]   device */
-  const double *omega;     /* [n_freq] angular frequency 2 pi f (rad/s), > 0 */
+  const double *omega;     /* [n_freq] angular frequency 2 pi f (rad/s), 0 < omega < 1e45 */
   const double *eps_re;    /* [n_freq] eps'  */
   const double *eps_im;    /* [n_freq] eps'' (loss, >= 0 for passive media) */
 } debye_batch;

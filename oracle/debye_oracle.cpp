@@ -56,8 +56,9 @@ using cd = std::complex<double>;
 enum { ST_OK = 0, ST_BADINPUT = 1, ST_SINGULAR = 2 };
 enum { FLAG_NO_SIGN_FLIP = 1u };
 
-// Largest |log10 tau| accepted; beyond it a candidate is reported BADINPUT.
-constexpr double THETA_LIMIT = 64.0;
+// Largest |log10 tau| accepted (relaxation times 1e-30 .. 1e30 s); beyond it
+// a candidate is reported BADINPUT.
+constexpr double THETA_LIMIT = 30.0;
 constexpr double LN10 = 2.302585092994045684017991454684364208;
 
 // ---------------------------------------------------------------------------

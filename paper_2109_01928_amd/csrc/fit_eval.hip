@@ -6,8 +6,8 @@
 //   weights: damped least squares on the loss part with Marquardt scaling,
 //     (D^-1 G D^-1 + damping Id) zt = D^-1 b,  G = I^T I, b = I^T eps'', D = diag(G)^1/2,
 //     z = D^-1 zt, solved by Cholesky plus one corrected-semi-normal-equations
-//     step (a residual pass over the frequencies, I^T r accumulated in
-//     double-double) because log-spaced Debye columns are nearly collinear;
+//     step (a residual pass over the frequencies, I^T r accumulated with
+//     compensation) because log-spaced Debye columns are nearly collinear;
 //   flip: w = |z| (penalty for negative weights);
 //   eps_inf = (sum_k eps'_k - sum_i w_i S_i) / F,  S_i = sum_k R_ki;
 //   cost = sum_k (eps'_k - eps_inf - (R w)_k)^2 + (eps''_k - (I w)_k)^2.
@@ -75,17 +75,15 @@ __device__ __forceinline__ double freq_sum(double v, int sp, int s_lanes) {
   return v;
 }
 
-// Double-double accumulation (Knuth's TwoSum, FMA-based TwoProd; Ogita, Rump
-// and Oishi 2005): acc (hi, lo) += a * b with the product and the sum errors
-// kept, about 2u^2 relative to the terms instead of u.
-__device__ __forceinline__ void dd_fma_acc(double &hi, double &lo, double a, double b) {
-  const double p = a * b;
-  const double pe = __builtin_fma(a, b, -p);
-  const double s = hi + p;
-  const double bv = s - hi;
-  const double se = (hi - (s - bv)) + (p - bv);
-  hi = s;
-  lo = lo + (se + pe);
+// Compensated accumulation sum += a * b (Kahan's summation with the running
+// correction c folded into the product by a fused multiply-add): the error of
+// a length-F sum stays at a few units of roundoff of the terms' magnitude
+// instead of growing with F.  The true sum is sum - c.
+__device__ __forceinline__ void kahan_fma_acc(double &sum, double &c, double a, double b) {
+  const double y = __builtin_fma(a, b, -c);
+  const double t = sum + y;
+  c = (t - sum) - y;
+  sum = t;
 }
 
 // xor-butterfly of a double-double over the SF frequency lanes; TwoSum's
@@ -101,6 +99,34 @@ __device__ __forceinline__ double freq_sum_dd(double hi, double lo, int sp, int 
     lo = (lo + ol) + se;
   }
   return hi + lo;
+}
+
+// --------------------------------------------------------------------------
+// Debye basis of the owned poles at one frequency: R = 1/(1+x^2), I = x R.
+// Two poles share one reciprocal: r = 1/(d0 d1), R0 = d1 r, R1 = d0 r (within
+// a few ulp; the hardware reciprocal costs four fused multiply-adds).  With
+// |log10 tau| <= 30 (larger values are rejected as bad input) and w < 1e45
+// rad/s, x < 1e75 and the product d0 d1 < 1e301 cannot overflow.
+// Padded poles have tau = 0: x = 0, R = 1, I = 0.
+// --------------------------------------------------------------------------
+template <int NB>
+__device__ __forceinline__ void basis_point(double w, const double *tau, double *R, double *I) {
+#pragma unroll
+  for (int c = 0; c + 1 < NB; c += 2) {
+    const double x0 = w * tau[c], x1 = w * tau[c + 1];
+    const double d0 = __builtin_fma(x0, x0, 1.0), d1 = __builtin_fma(x1, x1, 1.0);
+    const double r = rcp_nr(d0 * d1);
+    const double r0 = d1 * r, r1 = d0 * r;
+    R[c] = r0;
+    R[c + 1] = r1;
+    I[c] = x0 * r0;
+    I[c + 1] = x1 * r1;
+  }
+  if constexpr (NB & 1) {
+    const double x = w * tau[NB - 1];
+    R[NB - 1] = rcp_nr(__builtin_fma(x, x, 1.0));
+    I[NB - 1] = x * R[NB - 1];
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -245,7 +271,14 @@ void fit_kernel(const FitArgs a) {
   const int sub = lane - grp * SL;
   const int q = sub % SP;            // pole block
   const int fl = sub / SP;           // frequency lane
-  const int64_t slot = (int64_t)blockIdx.x * a.cand_per_wave + grp;
+  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+  // block b runs on XCD b % 8; giving each XCD a contiguous range of tiles
+  // keeps the tiles of one material (they are contiguous in the work list) on
+  // one L2.  The grid is rounded up to a multiple of 8; surplus blocks exit.
+  const int64_t tiles_per_xcd = (a.n_tiles + 7) / 8;
+  const int64_t tile = (int64_t)(blockIdx.x & 7) * tiles_per_xcd + (blockIdx.x >> 3);
+  if (tile >= a.n_tiles) return;
+  const int64_t slot = tile * a.cand_per_wave + grp;
   const int32_t cand = a.lane_cand[slot];
   const bool active = cand >= 0;
   const int32_t mat = active ? a.lane_mat[slot] : 0;
@@ -298,21 +331,16 @@ void fit_kernel(const FitArgs a) {
     }
     for (; k < F; k += SF) {
       const double w = w_n, er = er_n, ei = ei_n;
-      const int64_t kn = k + SF;
-      if (kn < F) {
-        w_n = om[kn];
-        er_n = epr[kn];
-        ei_n = epi[kn];
-      }
-      double Iv[NV];
+      const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
+      w_n = om[kn];
+      er_n = epr[kn];
+      ei_n = epi[kn];
+      double Iv[NV], Rv[NB];
+      basis_point<NB>(w, tau, Rv, Iv);
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
-        const double x = w * tau[cI];
-        const double R = rcp_nr(__builtin_fma(x, x, 1.0));
-        const double I = x * R;
-        Sv[cI] += R;
-        bv[cI] = __builtin_fma(I, ei, bv[cI]);
-        Iv[cI] = I;
+        Sv[cI] += Rv[cI];
+        bv[cI] = __builtin_fma(Iv[cI], ei, bv[cI]);
       }
       if constexpr (SP > 1) {
 #pragma unroll
@@ -395,8 +423,8 @@ void fit_kernel(const FitArgs a) {
 
   // ---- pass 2: corrected semi-normal equations, g = I^T (eps'' - I z).
   // The residual is nearly orthogonal to the columns of I, so g is a sum with
-  // heavy cancellation; it is accumulated in double-double (residual refinement
-  // with the residual products in extra precision).
+  // heavy cancellation; it is accumulated with compensation (residual
+  // refinement with the residual products summed in extra precision).
   double gv[NB], gl[NB];
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) {
@@ -412,27 +440,21 @@ void fit_kernel(const FitArgs a) {
     }
     for (; k < F; k += SF) {
       const double w = w_n, ei = ei_n;
-      const int64_t kn = k + SF;
-      if (kn < F) {
-        w_n = om[kn];
-        ei_n = epi[kn];
-      }
-      double Iv[NB];
+      const int64_t kn = (k + SF < F) ? k + SF : k;
+      w_n = om[kn];
+      ei_n = epi[kn];
+      double Iv[NB], Rv[NB];
+      basis_point<NB>(w, tau, Rv, Iv);
       double part = 0.0;
 #pragma unroll
-      for (int cI = 0; cI < NB; ++cI) {
-        const double x = w * tau[cI];
-        const double R = rcp_nr(__builtin_fma(x, x, 1.0));
-        Iv[cI] = x * R;
-        part = __builtin_fma(Iv[cI], zc[cI], part);
-      }
+      for (int cI = 0; cI < NB; ++cI) part = __builtin_fma(Iv[cI], zc[cI], part);
       const double r = ei - group_sum<SP>(part);
 #pragma unroll
-      for (int cI = 0; cI < NB; ++cI) dd_fma_acc(gv[cI], gl[cI], Iv[cI], r);
+      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], Iv[cI], r);
     }
   }
 #pragma unroll
-  for (int cI = 0; cI < NB; ++cI) gv[cI] = freq_sum_dd(gv[cI], gl[cI], SP, SL);
+  for (int cI = 0; cI < NB; ++cI) gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL);
 
   // correction: zt += A^-1 (D^-1 g - damping zt)
   if constexpr (SP == 1) {
@@ -484,19 +506,15 @@ void fit_kernel(const FitArgs a) {
     }
     for (; k < F; k += SF) {
       const double w = w_n, er = er_n, ei = ei_n;
-      const int64_t kn = k + SF;
-      if (kn < F) {
-        w_n = om[kn];
-        er_n = epr[kn];
-        ei_n = epi[kn];
-      }
+      const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
+      w_n = om[kn];
+      er_n = epr[kn];
+      ei_n = epi[kn];
       double Rv[NB], Iv[NB];
+      basis_point<NB>(w, tau, Rv, Iv);
       double pr = 0.0, pi = 0.0;
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
-        const double x = w * tau[cI];
-        Rv[cI] = rcp_nr(__builtin_fma(x, x, 1.0));
-        Iv[cI] = x * Rv[cI];
         pr = __builtin_fma(wv_[cI], Rv[cI], pr);
         pi = __builtin_fma(wv_[cI], Iv[cI], pi);
       }
@@ -576,19 +594,16 @@ void fit_kernel(const FitArgs a) {
       }
       for (; k < F; k += SF) {
         const double w = w_n, er = er_n, ei = ei_n;
-        const int64_t kn = k + SF;
-        if (kn < F) {
-          w_n = om[kn];
-          er_n = epr[kn];
-          ei_n = epi[kn];
-        }
+        const int64_t kn = (k + SF < F) ? k + SF : k;
+        w_n = om[kn];
+        er_n = epr[kn];
+        ei_n = epi[kn];
         double xv[NB], Rv[NB], Iv[NB];
+        basis_point<NB>(w, tau, Rv, Iv);
         double pr = 0.0, pi = 0.0, pz = 0.0, pm = 0.0;
 #pragma unroll
         for (int cI = 0; cI < NB; ++cI) {
           xv[cI] = w * tau[cI];
-          Rv[cI] = rcp_nr(__builtin_fma(xv[cI], xv[cI], 1.0));
-          Iv[cI] = xv[cI] * Rv[cI];
           pr = __builtin_fma(wv_[cI], Rv[cI], pr);
           pi = __builtin_fma(wv_[cI], Iv[cI], pi);
           pz = __builtin_fma(zc[cI], Iv[cI], pz);
@@ -690,10 +705,13 @@ template <int N> int lds_bytes_per_cand() { return Shape<N, pole_split_for(N)>::
 template <int N> hipError_t launch_fit_n(const FitArgs &a, int64_t n_tiles, bool grad, hipStream_t s) {
   constexpr int SP = pole_split_for(N);
   const size_t lds = (size_t)Shape<N, SP>::LDS_DOUBLES * 8 * a.cand_per_wave;
+  FitArgs b = a;
+  b.n_tiles = n_tiles;
+  const unsigned blocks = (unsigned)(((n_tiles + 7) / 8) * 8);
   if (grad)
-    hipLaunchKernelGGL((fit_kernel<N, SP, true>), dim3((unsigned)n_tiles), dim3(64), lds, s, a);
+    hipLaunchKernelGGL((fit_kernel<N, SP, true>), dim3(blocks), dim3(64), lds, s, b);
   else
-    hipLaunchKernelGGL((fit_kernel<N, SP, false>), dim3((unsigned)n_tiles), dim3(64), lds, s, a);
+    hipLaunchKernelGGL((fit_kernel<N, SP, false>), dim3(blocks), dim3(64), lds, s, b);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ struct FitArgs {
   uint32_t flags;
   int32_t freq_split;     // SF: lanes per candidate along the frequency axis
   int32_t cand_per_wave;  // 64 / (SP * SF)
+  int64_t n_tiles;        // work tiles (one per wavefront)
   const int32_t *lane_cand;  // [tiles * cand_per_wave] candidate index or -1
   const int32_t *lane_mat;   // [tiles * cand_per_wave] material of that candidate
   double *cost, *weights, *eps_inf;

@@ -143,7 +143,7 @@ def test_edge_cases_and_status(D, orc):
     wl = small_uniform(2, 64, 4, 8, seed=5)
     theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=1)
     theta[1, 2] = np.nan          # BADINPUT
-    theta[2, 0] = 70.0            # |log10 tau| > 64
+    theta[2, 0] = 70.0            # |log10 tau| > 30: rejected
     theta[3, 1] = theta[3, 0]     # duplicate tau: singular without damping
     theta[4, :] = [-11.0, -10.0, -9.0, -8.0]
     _check_eval(D, orc, wl, theta, damping=1e-8, tag="edge")
