@@ -45,6 +45,13 @@ def algorithmic_bytes(F, N, P_per_mat):
     return 8 * N + 8 + 24 * F / P_per_mat
 
 
+def kernel_source_hash():
+    import hashlib
+    src = b"".join(open(os.path.join(ROOT, "paper_2109_01928_amd", "csrc", f), "rb").read()
+                   for f in ("fit_eval.hip", "common.hpp", "fit_eval.hpp"))
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,15 +177,14 @@ def main():
     torch.cuda.synchronize()
     adj_rate = P * reps / (g0.elapsed_time(g1) * 1e-3)
 
-    # traffic measured by rocprofv3 counters for this kernel (see profiles/);
-    # null until a counter run of the current kernel is recorded there
+    # HBM bytes per launch measured by rocprofv3 counters (profiles/); used only
+    # while the kernel source is the one the counters were taken on
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "fit_eval_N8_mixed_traffic.json")
     if os.path.exists(tfile):
-        try:
-            traffic = json.load(open(tfile)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+        rec = json.load(open(tfile))
+        if rec.get("source_sha256_16") == kernel_source_hash():
+            traffic = rec.get("bytes_per_launch")
 
     line = {
         "metric": "Debye-fit cost evals/s (fwd, fwd+adjoint), rel err <=1e-10 vs FP64 oracle",
