@@ -57,9 +57,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--materials", type=int, default=1024)
-    ap.add_argument("--iters", type=int, default=200)
-    ap.add_argument("--polish-steps", type=int, default=50)
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "single", "ragged", "hncc", "tables"],
+                    help="mixed (default): 1024 mixed materials, F=1000, N=8, 256x200; single: one HN, F=50, N=5, "
+                         "40x50; ragged: 4096 materials of uneven F/N/swarm size; hncc: 1024 HN/CC, F=2000, N=12; "
+                         "tables: 65536 HN-sum tables, F=4096, N=20, 128 particles")
+    ap.add_argument("--materials", type=int, default=0, help="override the workload's material count")
+    ap.add_argument("--iters", type=int, default=-1, help="override the workload's swarm iterations")
+    ap.add_argument("--polish-steps", type=int, default=-1)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-eval", type=int, default=0,
@@ -87,8 +91,15 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 5}), flush=True)
         return
-    wl = W.mixed_uniform(M=args.materials, F=1000, N=8, P=256, iters=args.iters, seed=0)
-    M, P, N, F = wl.M, wl.P, 8, 1000
+    wl = make_workload(W, args)
+    args.iters = wl.iters
+    if args.polish_steps < 0:
+        args.polish_steps = wl.polish_steps
+    M, P = wl.M, wl.P
+    uniform = len(set(np.diff(wl.f_off))) == 1 and len(set(wl.n_poles)) == 1
+    N = int(wl.n_poles.max())
+    F = int(np.max(np.diff(wl.f_off)))
+    P_per = int(np.max(np.diff(wl.cand_off)))
     T_TRIALS, MEM = 30, 10
 
     # static inputs resident in HBM before timing
@@ -101,6 +112,8 @@ def main():
     ub = torch.tensor(wl.ub, device=dev)
     plan = D.Plan(b)
     sw = D.Swarm.empty(P, M, wl.ld, args.iters + 1, dev)
+    work_per_eval = float(np.sum(np.diff(wl.cand_off) * np.array(
+        [algorithmic_flops(int(f), int(n)) for f, n in zip(np.diff(wl.f_off), wl.n_poles)])))  # per swarm launch
     out = (torch.empty(P, dtype=torch.float64, device=dev), None, None, torch.empty(P, dtype=torch.int8, device=dev))
     stream = torch.cuda.current_stream()
 
@@ -156,12 +169,23 @@ def main():
     evals_step = evals_swarm + evals_polish
     value = evals_step * args.steps / dt
 
-    # dominant kernel: the N = 8 cost evaluation, timed on its stream
+    # dominant kernel: the swarm's cost evaluation, timed on its stream
     durs = np.array([a.elapsed_time(c) for a, c in events]) * 1e-3
     avg = float(durs.mean())
-    wb = algorithmic_flops(F, N)
-    achieved = wb * P / avg
+    wb = work_per_eval / P
+    achieved = work_per_eval / avg
     fwd_rate = P / avg
+
+    # the same swarm fit replayed from a captured HIP graph vs eager launches
+    bbx = b.with_targets(er, ei)
+    t_sw = {}
+    for mode in (False, True):
+        D.pso_run(plan, bbx, lb, ub, sw, args.iters, wl.inertia, wl.c1, wl.c2, wl.seed, use_graph=mode)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        D.pso_run(plan, bbx, lb, ub, sw, args.iters, wl.inertia, wl.c1, wl.c2, wl.seed, use_graph=mode)
+        torch.cuda.synchronize()
+        t_sw["graph" if mode else "eager"] = 1e3 * (time.perf_counter() - t1)
 
     # forward + adjoint kernel rate on the final swarm positions
     bb = b.with_targets(er, ei)
@@ -181,7 +205,7 @@ def main():
     # while the kernel source is the one the counters were taken on
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "fit_eval_N8_mixed_traffic.json")
-    if os.path.exists(tfile):
+    if args.workload == "mixed" and os.path.exists(tfile):
         rec = json.load(open(tfile))
         if rec.get("source_sha256_16") == kernel_source_hash():
             traffic = rec.get("bytes_per_launch")
@@ -199,16 +223,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded materials; no dataset in the paper)",
-        "config": {"workload": f"mixed materials M{M} F{F} N{N} P256 I{args.iters} + L-BFGS polish "
-                               f"{args.polish_steps} steps x {T_TRIALS} trials",
-                   "materials": M, "freq_points": F, "poles": N, "particles": 256, "iterations": args.iters,
+        "config": {"workload": f"{wl.name} + L-BFGS polish {args.polish_steps} steps x {T_TRIALS} trials",
+                   "materials": M, "freq_points": F if uniform else "ragged", "poles": N if uniform else "ragged",
+                   "particles": P_per if uniform else "ragged", "iterations": args.iters,
                    "evals_per_step": evals_step},
         "fwd_kernel_evals_per_s": fwd_rate,
         "fwd_adjoint_kernel_evals_per_s": adj_rate,
+        "swarm_fit_ms": {"eager": t_sw["eager"], "graph": t_sw["graph"]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
-                     "kernel": "fit_kernel<8,1,false>", "avg_launch_s": avg,
-                     "flops_per_eval": wb, "evals_per_launch": P},
+                     "kernel": f"fit_kernel<{N},{1 if N <= 8 else (2 if N <= 12 else 4)},false>" if uniform
+                     else "fit_kernel (all pole-count buckets of one evaluation)",
+                     "avg_launch_s": avg, "flops_per_eval": wb, "evals_per_launch": P},
     }
     if hist is not None:
         h = hist.cpu().numpy()
@@ -218,62 +244,92 @@ def main():
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"], line["parity_sample"] = cpu_leg(D, W, wl, bb, plan, args.cpu_seconds)
+        # counted evaluations: only those within the parity tolerance (sampled rate)
+        ps = line["parity_sample"]
+        line["value_raw"] = value
+        line["value"] = value * ps["within_1e-10"] / ps["candidates"]
     print(json.dumps(line), flush=True)
 
 
+def make_workload(W, args):
+    if args.workload == "mixed":
+        wl = W.mixed_uniform(M=args.materials or 1024, iters=args.iters if args.iters >= 0 else 200)
+    elif args.workload == "single":
+        wl = W.single_hn()
+    elif args.workload == "ragged":
+        wl = W.mixed_ragged(M=args.materials or 4096, iters=args.iters if args.iters >= 0 else 300)
+    elif args.workload == "hncc":
+        wl = W.hn_cc(M=args.materials or 1024, iters=args.iters if args.iters >= 0 else 200)
+    else:
+        wl = W.tables(M=args.materials or 65536, iters=args.iters if args.iters >= 0 else 400)
+    if args.iters >= 0:
+        wl.iters = args.iters
+    return wl
+
+
 def cpu_leg(D, W, wl, bb, plan, seconds):
-    """Oracle on the host cores (bounded sample) and a parity check of the
-    same sample on the GPU."""
+    """Oracle on the host cores (bounded sample of whole materials, in order,
+    until `seconds` of oracle time) and a parity check of the same sample on
+    the GPU: cost within 1e-10 of the FP64 oracle, or of its 80-bit instance
+    where the FP64 oracle is the less accurate side."""
     import torch
 
     import oracle
 
     er = bb.eps_re.cpu().numpy()
     ei = bb.eps_im.cpu().numpy()
-    # GPU targets vs oracle targets (row a1), then identical targets for the cost
-    oer, oei = oracle.material_eval(wl.kind, wl.params, wl.f_off, wl.omega)
+    # GPU targets vs oracle targets (target synthesis), then identical targets for the cost
+    oer, oei = oracle.material_eval(wl.kind, wl.params, wl.f_off, wl.omega, noise_seed=wl.noise_seed)
     tgt_err = float(max(np.max(np.abs(er - oer) / np.maximum(np.abs(oer), 1e-300)),
                         np.max(np.abs(ei - oei) / np.maximum(np.abs(oei), 1e-300))))
-    ob = oracle.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, oer, oei)
     theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=77)
     nthreads = oracle.num_threads()
-    # bounded sample: whole materials (256 candidates each) until `seconds` of oracle time
-    chunk = 16
-    done_m, t_cpu = 0, 0.0
-    costs = []
-    while t_cpu < seconds and done_m < wl.M:
-        ms = list(range(done_m, min(done_m + chunk, wl.M)))
-        sub = oracle.Batch(wl.f_off[ms[0]:ms[-1] + 2] - wl.f_off[ms[0]], wl.cand_off[ms[0]:ms[-1] + 2] - wl.cand_off[ms[0]],
-                           wl.n_poles[ms], wl.omega[wl.f_off[ms[0]]:wl.f_off[ms[-1] + 1]],
-                           oer[wl.f_off[ms[0]]:wl.f_off[ms[-1] + 1]], oei[wl.f_off[ms[0]]:wl.f_off[ms[-1] + 1]])
-        th = theta[wl.cand_off[ms[0]]:wl.cand_off[ms[-1] + 1]]
+
+    def sub_batch(m0, m1):
+        f0, f1 = wl.f_off[m0], wl.f_off[m1]
+        return oracle.Batch(wl.f_off[m0:m1 + 1] - f0, wl.cand_off[m0:m1 + 1] - wl.cand_off[m0], wl.n_poles[m0:m1],
+                            wl.omega[f0:f1], oer[f0:f1], oei[f0:f1])
+
+    def one_cand(m):
+        f0, f1 = wl.f_off[m], wl.f_off[m + 1]
+        return oracle.Batch([0, f1 - f0], [0, 1], wl.n_poles[m:m + 1], wl.omega[f0:f1], oer[f0:f1], oei[f0:f1])
+
+    # timed sample: whole materials in order; after the last material the
+    # candidates are drawn again with the next seed, until `seconds`
+    done_m, t_cpu, costs, n_timed, draw = 0, 0.0, [], 0, 0
+    while t_cpu < seconds:
+        m1 = min(done_m + 16, wl.M)
+        th_all = theta if draw == 0 else W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=77 + draw)
+        th = th_all[wl.cand_off[done_m]:wl.cand_off[m1]]
         t = time.perf_counter()
-        c = oracle.fit_eval(sub, th, nthreads=nthreads)[0]
+        c = oracle.fit_eval(sub_batch(done_m, m1), th, nthreads=nthreads)[0]
         t_cpu += time.perf_counter() - t
-        costs.append(c)
-        done_m = ms[-1] + 1
+        n_timed += len(c)
+        if draw == 0:
+            costs.append(c)
+        done_m = m1
+        if done_m == wl.M:
+            done_m, draw = 0, draw + 1
+    n_draws = draw + (1 if done_m else 0)
     c64 = np.concatenate(costs)
     n = len(c64)
-    # parity of the same sample on the GPU (oracle targets uploaded)
+    done_m = int(np.searchsorted(wl.cand_off, n))
     gb = bb.with_targets(torch.tensor(oer, device="cuda"), torch.tensor(oei, device="cuda"))
     cg = D.fit_eval(plan, gb, torch.tensor(theta, device="cuda"), want_weights=False)[0].cpu().numpy()[:n]
-    floor = np.repeat([1e-12 * np.sum(oer[wl.f_off[m]:wl.f_off[m + 1]] ** 2 + oei[wl.f_off[m]:wl.f_off[m + 1]] ** 2)
-                       for m in range(done_m)], 256)
+    per_m = np.array([np.sum(oer[wl.f_off[m]:wl.f_off[m + 1]] ** 2 + oei[wl.f_off[m]:wl.f_off[m + 1]] ** 2)
+                      for m in range(done_m)])
+    floor = 1e-12 * np.repeat(per_m, np.diff(wl.cand_off[:done_m + 1]))
     rel = np.abs(cg - c64) / np.maximum(c64, floor)
-    over = rel > 1e-10
-    n_lim = int(over.sum())
-    if n_lim:
-        idx = np.nonzero(over)[0]
-        for c in idx:  # judged against the 80-bit oracle instance
-            m = c // 256
-            one = oracle.Batch([0, 1000], [0, 1], [8], wl.omega[wl.f_off[m]:wl.f_off[m + 1]],
-                               oer[wl.f_off[m]:wl.f_off[m + 1]], oei[wl.f_off[m]:wl.f_off[m + 1]])
-            c80 = oracle.fit_eval(one, theta[c:c + 1], precision=80)[0][0]
-            rel[c] = abs(cg[c] - c80) / max(c80, floor[c])
-    cpu = {"value": n / t_cpu, "unit": "evals/s", "cores": nthreads, "kind": "oracle",
-           "sample": f"{n} candidates ({done_m} materials x 256) of the same workload, uniform log10 tau, "
-                     f"Householder-QR FP64 oracle, {t_cpu:.1f} s"}
-    parity = {"candidates": n, "max_cost_rel_err": float(rel.max()), "oracle_limited": n_lim,
+    over = np.nonzero(rel > 1e-10)[0]
+    mat_of = np.searchsorted(wl.cand_off, np.arange(n), side="right") - 1
+    for c in over:  # judged against the 80-bit oracle instance
+        c80 = oracle.fit_eval(one_cand(mat_of[c]), theta[c:c + 1], precision=80)[0][0]
+        rel[c] = abs(cg[c] - c80) / max(c80, floor[c])
+    cpu = {"value": n_timed / t_cpu, "unit": "evals/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"{n_timed} candidate evaluations of the same workload (whole materials in order, "
+                     f"uniform log10 tau, {n_draws} draw(s)), Householder-QR FP64 oracle, "
+                     f"{t_cpu:.1f} s"}
+    parity = {"candidates": n, "max_cost_rel_err": float(rel.max()), "oracle_limited": int(len(over)),
               "within_1e-10": int((rel <= 1e-10).sum()), "target_max_rel_err": tgt_err}
     return cpu, parity
 

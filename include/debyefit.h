@@ -226,6 +226,32 @@ int debye_pso_step(const debye_batch *b, int64_t ld, const double *lb, const dou
                    double *history, int64_t hist_ld, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * A whole swarm fit: pso_init, cost evaluation, then `iters` x (pso_step with
+ * move, cost evaluation), then a bests-only pso_step; P*(iters+1) evaluations
+ * per material.  With use_graph != 0 one iteration (step -> evaluation ->
+ * iteration-counter increment) is captured once as a HIP graph (kept in the
+ * plan and reused while the arguments are unchanged) and replayed `iters`
+ * times on a stream owned by the plan, ordered after and before `stream` by
+ * events; results are bit-identical to use_graph = 0.  history needs
+ * hist_ld >= iters + 1.  Calls with one plan must not overlap.
+ * ------------------------------------------------------------------------ */
+typedef struct debye_swarm {
+  double *x, *v, *pbest_x;          /* [n_cand][ld] */
+  double *pbest_cost;               /* [n_cand] */
+  double *gbest_x;                  /* [M][ld] */
+  double *gbest_cost;               /* [M] */
+  int64_t *gbest_idx;               /* [M] */
+  double *history;                  /* [M][hist_ld] or NULL */
+  int64_t hist_ld;
+  double *cost;                     /* [n_cand] cost of the current positions (workspace/output) */
+  int8_t *status;                   /* [n_cand] or NULL */
+} debye_swarm;
+
+int debye_pso_run(const debye_plan *plan, const debye_batch *b, int64_t ld, const double *lb, const double *ub,
+                  debye_pso_params p, int32_t iters, double damping, uint32_t flags, const debye_swarm *swarm,
+                  int32_t use_graph, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Gradient polish: L-BFGS (Liu & Nocedal 1989; two-loop recursion, memory
  * `mem`), Armijo backtracking alpha = 1, 1/2, ... (max_trials, constant c1),
  * on one candidate per material, theta [M][ld] in place, inside the search box

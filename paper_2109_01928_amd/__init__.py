@@ -33,7 +33,7 @@ DEFAULT_DAMPING = 1e-8
 EXPORTED = ["debye_plan_create", "debye_plan_destroy", "debye_plan_set_freq_split", "debye_plan_info",
             "debye_last_error", "debye_version", "debye_basis", "debye_fit_eval", "debye_fit_eval_grad",
             "debye_material_eval", "debye_material_vjp", "debye_pso_init", "debye_pso_step",
-            "debye_lbfgs_polish"]
+            "debye_pso_run", "debye_lbfgs_polish"]
 
 
 class DebyeError(RuntimeError):
@@ -50,6 +50,12 @@ class _CBatch(C.Structure):
 
 class _CPso(C.Structure):
     _fields_ = [("inertia", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("seed", C.c_uint64)]
+
+
+class _CSwarm(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("v", C.c_void_p), ("pbest_x", C.c_void_p), ("pbest_cost", C.c_void_p),
+                ("gbest_x", C.c_void_p), ("gbest_cost", C.c_void_p), ("gbest_idx", C.c_void_p),
+                ("history", C.c_void_p), ("hist_ld", C.c_int64), ("cost", C.c_void_p), ("status", C.c_void_p)]
 
 
 class _CLbfgs(C.Structure):
@@ -83,6 +89,8 @@ def lib():
     L.debye_pso_init.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CPso, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.debye_pso_step.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CPso, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp,
                                  _vp, _vp, _vp, i64, _vp]
+    L.debye_pso_run.argtypes = [_vp, C.POINTER(_CBatch), i64, _vp, _vp, _CPso, i32, dbl, u32, C.POINTER(_CSwarm), i32,
+                                _vp]
     L.debye_lbfgs_polish.argtypes = [C.POINTER(_CBatch), _vp, _vp, _vp, i64, _vp, _vp, dbl, u32, _CLbfgs, _vp, _vp]
     _lib = L
     return L
@@ -269,6 +277,20 @@ def pso_step(b: Batch, lb, ub, sw: Swarm, t, move, cost, inertia=0.7, c1=1.5, c2
     _check(lib().debye_pso_step(C.byref(cb), sw.x.shape[1], _ptr(lb), _ptr(ub), p, int(t), int(move), _ptr(cost),
                                 _ptr(sw.x), _ptr(sw.v), _ptr(sw.pbest_x), _ptr(sw.pbest_cost), _ptr(sw.gbest_x),
                                 _ptr(sw.gbest_cost), _ptr(sw.gbest_idx), _ptr(h), sw.history.shape[1], _stream()))
+
+
+def pso_run(plan: Plan, b: Batch, lb, ub, sw: Swarm, iters, inertia=0.7, c1=1.5, c2=1.5, seed=0,
+            damping=DEFAULT_DAMPING, flags=0, use_graph=True, cost=None, status=None):
+    """A whole swarm fit (debye_pso_run); returns the cost of the final positions."""
+    cost = torch.empty(b.P, dtype=torch.float64, device=sw.x.device) if cost is None else cost
+    cs = _CSwarm(sw.x.data_ptr(), sw.v.data_ptr(), sw.pbest_x.data_ptr(), sw.pbest_cost.data_ptr(),
+                 sw.gbest_x.data_ptr(), sw.gbest_cost.data_ptr(), sw.gbest_idx.data_ptr(), sw.history.data_ptr(),
+                 sw.history.shape[1], cost.data_ptr(), None if status is None else status.data_ptr())
+    cb = b.cstruct()
+    _check(lib().debye_pso_run(plan.handle, C.byref(cb), sw.x.shape[1], _ptr(lb), _ptr(ub),
+                               _CPso(inertia, c1, c2, seed), int(iters), float(damping), flags, C.byref(cs),
+                               1 if use_graph else 0, _stream()))
+    return cost
 
 
 def lbfgs_polish(b1: Batch, theta, lb, ub, steps=50, mem=10, max_trials=30, c1=1e-4, damping=DEFAULT_DAMPING,

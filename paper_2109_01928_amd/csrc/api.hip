@@ -53,7 +53,18 @@ struct Bucket {
   int32_t *d_lane_cand = nullptr, *d_lane_mat = nullptr, *d_mats = nullptr;
 };
 
+// a captured swarm iteration (step -> cost evaluation -> counter tick) and the
+// arguments it was captured with
+struct SwarmGraph {
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  int32_t *counter = nullptr;
+  std::vector<unsigned char> key;
+};
+
 struct debye_plan {
+  SwarmGraph graph;
   int32_t M = 0, max_poles = 0;
   int64_t n_freq = 0, n_cand = 0;
   std::vector<int64_t> f_off, cand_off;
@@ -237,6 +248,12 @@ int debye_plan_create(const debye_batch *shape, const int64_t *f_off_host, const
 
 int debye_plan_destroy(debye_plan *p) {
   if (!p) return DEBYE_OK;
+  if (p->graph.stream) (void)hipStreamSynchronize(p->graph.stream);
+  if (p->graph.exec) (void)hipGraphExecDestroy(p->graph.exec);
+  if (p->graph.ev_in) (void)hipEventDestroy(p->graph.ev_in);
+  if (p->graph.ev_out) (void)hipEventDestroy(p->graph.ev_out);
+  if (p->graph.stream) (void)hipStreamDestroy(p->graph.stream);
+  if (p->graph.counter) (void)hipFree(p->graph.counter);
   for (auto &b : p->buckets) free_bucket(b);
   if (p->d_record) (void)hipFree(p->d_record);
   delete p;
@@ -439,6 +456,120 @@ int debye_pso_step(const debye_batch *b, int64_t ld, const double *lb, const dou
   a.history = history;
   a.hist_ld = hist_ld;
   CHECK_HIP(dfit::launch_pso_step(a, stream), "debye_pso_step launch");
+  return DEBYE_OK;
+}
+
+static dfit::PsoArgs pso_args(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_pso_params p,
+                               int32_t t, int32_t move, const debye_swarm *sw) {
+  dfit::PsoArgs a{};
+  a.M = b->n_mat;
+  a.cand_off = b->cand_off;
+  a.n_poles = b->n_poles;
+  a.ld = ld;
+  a.lb = lb;
+  a.ub = ub;
+  a.inertia = p.inertia;
+  a.c1 = p.c1;
+  a.c2 = p.c2;
+  a.seed = p.seed;
+  a.t = t;
+  a.move = move;
+  a.cost = sw->cost;
+  a.x = sw->x;
+  a.v = sw->v;
+  a.pbest_x = sw->pbest_x;
+  a.pbest_cost = sw->pbest_cost;
+  a.gbest_x = sw->gbest_x;
+  a.gbest_cost = sw->gbest_cost;
+  a.gbest_idx = sw->gbest_idx;
+  a.history = sw->history;
+  a.hist_ld = sw->hist_ld;
+  return a;
+}
+
+int debye_pso_run(const debye_plan *pc, const debye_batch *b, int64_t ld, const double *lb, const double *ub,
+                  debye_pso_params p, int32_t iters, double damping, uint32_t flags, const debye_swarm *sw,
+                  int32_t use_graph, hipStream_t stream) {
+  int rc = check_plan_batch(pc, b, ld);
+  if (rc) return rc;
+  if ((rc = check_damping(damping, flags))) return rc;
+  if ((rc = pso_check(b, ld, lb, ub, p))) return rc;
+  if (!sw || !sw->x || !sw->v || !sw->pbest_x || !sw->pbest_cost || !sw->gbest_x || !sw->gbest_cost ||
+      !sw->gbest_idx || !sw->cost)
+    return fail(DEBYE_EINVAL, "NULL swarm pointer");
+  if (iters < 0) return fail(DEBYE_ERANGE, "iters must be >= 0");
+  if (sw->history && sw->hist_ld < (int64_t)iters + 1) return fail(DEBYE_ERANGE, "hist_ld must be >= iters + 1");
+  debye_plan *plan = const_cast<debye_plan *>(pc);
+  SwarmGraph &g = plan->graph;
+  hipStream_t s = stream;
+  if (use_graph) {
+    if (!g.stream) {
+      CHECK_HIP(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking), "graph stream");
+      CHECK_HIP(hipEventCreateWithFlags(&g.ev_in, hipEventDisableTiming), "graph event");
+      CHECK_HIP(hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming), "graph event");
+      if (hipMalloc(&g.counter, sizeof(int32_t)) != hipSuccess) return fail(DEBYE_ENOMEM, "graph counter");
+    }
+    CHECK_HIP(hipEventRecord(g.ev_in, stream), "event");
+    CHECK_HIP(hipStreamWaitEvent(g.stream, g.ev_in, 0), "event wait");
+    s = g.stream;
+  }
+  dfit::PsoArgs a0 = pso_args(b, ld, lb, ub, p, 0, 0, sw);
+  CHECK_HIP(dfit::launch_pso_init(a0, b->n_cand, s), "swarm init");
+  if ((rc = debye_fit_eval(plan, b, sw->x, ld, damping, flags, sw->cost, nullptr, nullptr, sw->status, s))) return rc;
+  if (!use_graph) {
+    for (int32_t t = 1; t <= iters; ++t) {
+      CHECK_HIP(dfit::launch_pso_step(pso_args(b, ld, lb, ub, p, t, 1, sw), s), "swarm step");
+      if ((rc = debye_fit_eval(plan, b, sw->x, ld, damping, flags, sw->cost, nullptr, nullptr, sw->status, s)))
+        return rc;
+    }
+  } else if (iters > 0) {
+    // key: every argument the captured nodes depend on
+    std::vector<unsigned char> key;
+    auto put = [&](const void *q, size_t n) {
+      const unsigned char *c = (const unsigned char *)q;
+      key.insert(key.end(), c, c + n);
+    };
+    put(b, sizeof *b);
+    put(&ld, sizeof ld);
+    put(&lb, sizeof lb);
+    put(&ub, sizeof ub);
+    put(&p, sizeof p);
+    put(&damping, sizeof damping);
+    put(&flags, sizeof flags);
+    put(sw, sizeof *sw);
+    if (!g.exec || g.key != key) {
+      if (g.exec) {
+        (void)hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+      }
+      hipGraph_t graph = nullptr;
+      CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+      dfit::PsoArgs a = pso_args(b, ld, lb, ub, p, 0, 1, sw);
+      a.t_dev = g.counter;
+      hipError_t e1 = dfit::launch_pso_step(a, s);
+      int rc2 = debye_fit_eval(plan, b, sw->x, ld, damping, flags, sw->cost, nullptr, nullptr, sw->status, s);
+      hipError_t e2 = dfit::launch_tick(g.counter, s);
+      hipError_t e3 = hipStreamEndCapture(s, &graph);
+      if (e1 != hipSuccess || rc2 || e2 != hipSuccess || e3 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc2 ? rc2 : hip_fail(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3), "swarm graph capture");
+      }
+      hipError_t e4 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e4 != hipSuccess) {
+        g.exec = nullptr;
+        return hip_fail(e4, "swarm graph instantiate");
+      }
+      g.key = key;
+    }
+    CHECK_HIP(dfit::launch_set_counter(g.counter, 1, s), "counter");
+    for (int32_t t = 1; t <= iters; ++t) CHECK_HIP(hipGraphLaunch(g.exec, s), "swarm graph launch");
+  }
+  CHECK_HIP(dfit::launch_pso_step(pso_args(b, ld, lb, ub, p, iters + 1, 0, sw), s), "final bests");
+  if (use_graph) {
+    CHECK_HIP(hipEventRecord(g.ev_out, s), "event");
+    CHECK_HIP(hipStreamWaitEvent(stream, g.ev_out, 0), "event wait");
+  }
   return DEBYE_OK;
 }
 

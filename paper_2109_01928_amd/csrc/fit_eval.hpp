@@ -71,6 +71,7 @@ struct PsoArgs {
   double inertia, c1, c2;
   uint64_t seed;
   int32_t t, move;
+  const int32_t *t_dev;  // if set, the iteration number is read from device memory
   const double *cost;
   double *x, *v, *pbest_x, *pbest_cost, *gbest_x, *gbest_cost;
   int64_t *gbest_idx;
@@ -79,6 +80,8 @@ struct PsoArgs {
 };
 hipError_t launch_pso_init(const PsoArgs &a, int64_t n_cand, hipStream_t s);
 hipError_t launch_pso_step(const PsoArgs &a, hipStream_t s);
+hipError_t launch_set_counter(int32_t *c, int32_t value, hipStream_t s);
+hipError_t launch_tick(int32_t *c, hipStream_t s);
 
 struct LbfgsArgs {
   int32_t M;

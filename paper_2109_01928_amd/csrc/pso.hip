@@ -56,6 +56,7 @@ __global__ __launch_bounds__(256) void pso_step_kernel(const PsoArgs a) {
   __shared__ int s_take;
   const int m = blockIdx.x;
   const int tid = threadIdx.x;
+  const int32_t t = a.t_dev ? *a.t_dev : a.t;
   const int64_t c0 = a.cand_off[m];
   const int64_t P = a.cand_off[m + 1] - c0;
   const int N = a.n_poles[m];
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(256) void pso_step_kernel(const PsoArgs a) {
       a.gbest_cost[m] = s_val[0];
       a.gbest_idx[m] = best;
     }
-    if (a.history) a.history[(int64_t)m * a.hist_ld + (a.t - 1)] = a.gbest_cost[m];
+    if (a.history) a.history[(int64_t)m * a.hist_ld + (t - 1)] = a.gbest_cost[m];
   }
   __syncthreads();
   if (s_take) {
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(256) void pso_step_kernel(const PsoArgs a) {
     const int64_t p = e / N;
     const int d = (int)(e - p * N);
     const int64_t c = c0 + p;
-    const U64x4 r = philox4x64((uint64_t)d, (uint64_t)p, (uint64_t)a.t, STREAM_PSO_STEP, a.seed, (uint64_t)m);
+    const U64x4 r = philox4x64((uint64_t)d, (uint64_t)p, (uint64_t)t, STREAM_PSO_STEP, a.seed, (uint64_t)m);
     const double r1 = unit53(r.w[0]), r2 = unit53(r.w[1]);
     const double xi = a.x[c * ld + d];
     double vel = __dmul_rn(a.inertia, a.v[c * ld + d]);
@@ -138,6 +139,20 @@ __global__ __launch_bounds__(256) void pso_step_kernel(const PsoArgs a) {
 
 hipError_t launch_pso_step(const PsoArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(pso_step_kernel, dim3((unsigned)a.M), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// iteration counter of a replayed swarm graph (a kernel, so that graphs hold
+// no memset nodes)
+__global__ void set_counter_kernel(int32_t *c, int32_t v) { *c = v; }
+__global__ void tick_kernel(int32_t *c) { *c = *c + 1; }
+
+hipError_t launch_set_counter(int32_t *c, int32_t value, hipStream_t s) {
+  hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(1), 0, s, c, value);
+  return hipGetLastError();
+}
+hipError_t launch_tick(int32_t *c, hipStream_t s) {
+  hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, s, c);
   return hipGetLastError();
 }
 
