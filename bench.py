@@ -47,8 +47,9 @@ def algorithmic_bytes(F, N, P_per_mat):
 
 def kernel_source_hash():
     import hashlib
+    # the cost kernel's own source: its file and the device helpers it includes
     src = b"".join(open(os.path.join(ROOT, "paper_2109_01928_amd", "csrc", f), "rb").read()
-                   for f in ("fit_eval.hip", "common.hpp", "fit_eval.hpp"))
+                   for f in ("fit_eval.hip", "common.hpp"))
     return hashlib.sha256(src).hexdigest()[:16]
 
 
