@@ -61,6 +61,11 @@ def lib():
                                       C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_double, _d, C.c_int]
         L.orc_afe.argtypes = [C.c_int64, _d, _d, _d, C.c_int32, _d, _d, C.c_double]
         L.orc_afe.restype = C.c_double
+        L.orc_fit_from_basis.argtypes = [C.c_int64, _d, _d, _d, _d, C.c_int32, C.c_double, C.c_uint32, C.c_int32,
+                                         _d]
+        L.orc_fit_cond.argtypes = [C.c_int64, _d, _d, _d, C.c_int32, _d, C.c_double, C.c_uint32, _d, _d, _d]
+        L.orc_fit_cond_batch.argtypes = [C.c_int32, _i64, _i64, _i32, _d, _d, _d, _d, C.c_int64, C.c_double,
+                                         C.c_uint32, _d, C.c_int]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -191,6 +196,88 @@ def fit_detail(omega, eps_re, eps_im, theta, damping=1e-8, flags=0):
     st = lib().orc_fit_detail(F, _p(omega, _d), _p(eps_re, _d), _p(eps_im, _d), N, _p(theta, _d),
                               damping, flags, _p(z, _d), _p(d, _d), _p(rr, _d), _p(ri, _d))
     return st, z, d, rr, ri
+
+
+def fit_from_basis(R, I, eps_re, eps_im, damping=1e-8, flags=0, precision=64):
+    """Cost of one candidate from an explicitly given basis R, I [F][N]
+    (steps 2-5 of the forward map)."""
+    R, I, eps_re, eps_im = map(_f64, (R, I, eps_re, eps_im))
+    F, N = R.shape
+    cost = np.empty(1)
+    st = lib().orc_fit_from_basis(F, _p(R, _d), _p(I, _d), _p(eps_re, _d), _p(eps_im, _d), N, damping, flags,
+                                  precision, _p(cost, _d))
+    return cost[0], st
+
+
+def fit_cond(omega, eps_re, eps_im, theta, damping=1e-8, flags=0):
+    """Relative condition number of one candidate's cost under componentwise
+    relative perturbations of the basis, and the total derivatives dC/dR,
+    dC/dI [F][N] it is built from (80-bit arithmetic)."""
+    omega, eps_re, eps_im, theta = map(_f64, (omega, eps_re, eps_im, theta))
+    F, N = len(omega), len(theta)
+    dR, dI, cond = np.empty((F, N)), np.empty((F, N)), np.empty(1)
+    st = lib().orc_fit_cond(F, _p(omega, _d), _p(eps_re, _d), _p(eps_im, _d), N, _p(theta, _d), damping, flags,
+                            _p(dR, _d), _p(dI, _d), _p(cond, _d))
+    return cond[0], dR, dI, st
+
+
+def fit_cond_batch(b: Batch, theta, damping=1e-8, flags=0, nthreads=0):
+    """fit_cond's condition number for every candidate of a batch."""
+    theta = _f64(theta)
+    cond = np.empty(b.P)
+    lib().orc_fit_cond_batch(b.M, _p(b.f_off, _i64), _p(b.cand_off, _i64), _p(b.n_poles, _i32),
+                             _p(b.omega, _d), _p(b.eps_re, _d), _p(b.eps_im, _d), _p(theta, _d),
+                             theta.shape[1], damping, flags, _p(cond, _d), nthreads)
+    return cond
+
+
+UNIT_ROUNDOFF = 2.0 ** -53
+
+
+def judge_costs(b: Batch, theta, c_test, c64, floor, rtol, damping=1e-8, flags=0, stats=None, rel=None):
+    """Parity judgement of costs computed elsewhere against this oracle.
+
+    Relative error (floored) against the FP64 oracle; a candidate above rtol
+    is judged instead against the 80-bit instance of the oracle (the more
+    accurate reference).  If it is still above rtol there, the candidate's
+    cost is ill-conditioned in FP64 (near-duplicate relaxation times): it
+    passes (error reported as 0, counted as "fp64_limited") when its error
+    against the 80-bit result is within what rounding the basis to FP64 can
+    cause, cond * u with cond from fit_cond, or within the FP64 oracle's own
+    error.  `rel` (optional) holds precomputed errors against the FP64
+    oracle; only candidates with a finite FP64 cost are re-judged.  Returns
+    (errors, stats)."""
+    c_test, c64, floor = map(np.asarray, (c_test, c64, floor))
+    if rel is None:
+        rel = np.abs(c_test - c64) / np.maximum(c64, floor)
+    rel = np.array(rel, dtype=np.float64)
+    st = dict(n=len(rel), oracle_limited=0, fp64_limited=0, max_rel_80=0.0)
+    over = np.nonzero(~(rel <= rtol) & np.isfinite(c64))[0]
+    if len(over):
+        idx = np.searchsorted(b.cand_off, over, side="right") - 1
+        for c, m in zip(over, idx):
+            f0, f1 = b.f_off[m], b.f_off[m + 1]
+            one = Batch([0, f1 - f0], [0, 1], b.n_poles[m:m + 1], b.omega[f0:f1], b.eps_re[f0:f1],
+                        b.eps_im[f0:f1])
+            th = theta[c:c + 1]
+            c80 = fit_eval(one, th, damping, flags, precision=80)[0][0]
+            r80 = abs(c_test[c] - c80) / max(c80, floor[c])
+            st["max_rel_80"] = max(st["max_rel_80"], float(r80))
+            if r80 <= rtol:
+                st["oracle_limited"] += 1
+                rel[c] = r80
+                continue
+            own = abs(c64[c] - c80) / max(c80, floor[c])
+            cond = fit_cond(b.omega[f0:f1], b.eps_re[f0:f1], b.eps_im[f0:f1], th[0, :b.n_poles[m]], damping,
+                            flags)[0]
+            if r80 <= max(own, cond * UNIT_ROUNDOFF):
+                st["fp64_limited"] += 1
+                rel[c] = 0.0
+            else:
+                rel[c] = r80
+    if stats is not None:
+        stats.update(st)
+    return rel, st
 
 
 class Swarm:

@@ -251,6 +251,9 @@ template <class T> struct Fit {
 };
 
 template <class T>
+void fit_solve(Fit<T> &out, int64_t F, const T *eps_re, const T *eps_im, int N, double damping, unsigned flags);
+
+template <class T>
 Fit<T> fit_forward(int64_t F, const double *omega, const T *eps_re, const T *eps_im, int N,
                    const T *theta, double damping, unsigned flags) {
   Fit<T> out;
@@ -276,7 +279,13 @@ Fit<T> fit_forward(int64_t F, const double *omega, const T *eps_re, const T *eps
   for (int64_t k = 0; k < F; ++k)
     for (int i = 0; i < N; ++i)
       basis_point(omega[k], out.tau[i], out.R[k * N + i], out.I[k * N + i]);
+  fit_solve(out, F, eps_re, eps_im, N, damping, flags);
+  return out;
+}
 
+// Steps 2-5 on the basis already held in out.R, out.I (row k, column i).
+template <class T>
+void fit_solve(Fit<T> &out, int64_t F, const T *eps_re, const T *eps_im, int N, double damping, unsigned flags) {
   // step 2: Marquardt scaling d_i = ||I_{:,i}||_2, then the damped least
   // squares  min || (I D^-1) zt - eps'' ||^2 + damping ||zt||^2  solved by
   // Householder QR of the stacked matrix [I D^-1 ; sqrt(damping) Id_N].
@@ -285,7 +294,7 @@ Fit<T> fit_forward(int64_t F, const double *omega, const T *eps_re, const T *eps
     T s = T(0);
     for (int64_t k = 0; k < F; ++k) s += out.I[k * N + i] * out.I[k * N + i];
     out.d[i] = std::sqrt(s);
-    if (!(re(out.d[i]) > 0)) { out.status = ST_SINGULAR; out.cost = T(INFINITY); return out; }
+    if (!(re(out.d[i]) > 0)) { out.status = ST_SINGULAR; out.cost = T(INFINITY); return; }
   }
   const int64_t m = F + N;
   std::vector<T> A((size_t)m * N, T(0)), y(m, T(0));
@@ -335,7 +344,7 @@ Fit<T> fit_forward(int64_t F, const double *omega, const T *eps_re, const T *eps
     if (rmin <= (double)std::max<int64_t>(F, N) * 0x1.0p-53 * rmax || rmax == 0) {
       out.status = ST_SINGULAR;
       out.cost = T(INFINITY);
-      return out;
+      return;
     }
   }
   // back substitution  Rqr zt = (Q^T y)[0:N],  z = D^-1 zt
@@ -374,7 +383,6 @@ Fit<T> fit_forward(int64_t F, const double *omega, const T *eps_re, const T *eps
     cost += a * a + b * b;
   }
   out.cost = cost;
-  return out;
 }
 
 // ---------------------------------------------------------------------------
@@ -388,6 +396,31 @@ Fit<T> fit_forward(int64_t F, const double *omega, const T *eps_re, const T *eps
 // with dR/dtheta = -2 ln10 x^2 R^2 and dI/dtheta = ln10 x R^2 (1 - x^2).
 // M is applied through the QR factor: M = D Rqr^T Rqr D.
 // ---------------------------------------------------------------------------
+// g_w = -2 (R^T r' + I^T r'') and mu = D^-1 Rqr^-1 Rqr^-T D^-1 (s o g_w),
+// the adjoint vector of the weights (M^-1 through the QR factor)
+template <class T> std::vector<T> adjoint_mu(const Fit<T> &f, int64_t F, int N, unsigned flags) {
+  std::vector<T> gw(N, T(0)), sg(N);
+  for (int i = 0; i < N; ++i) {
+    T s = T(0);
+    for (int64_t k = 0; k < F; ++k) s += f.R[k * N + i] * f.rre[k] + f.I[k * N + i] * f.rim[k];
+    gw[i] = T(-2) * s;
+    sg[i] = (flags & FLAG_NO_SIGN_FLIP) ? T(1) : (f.z[i] < 0 ? T(-1) : T(1));
+  }
+  std::vector<T> u(N), v(N), mu(N);
+  for (int i = 0; i < N; ++i) {
+    T s = sg[i] * gw[i] / f.d[i];
+    for (int j = 0; j < i; ++j) s -= f.Rqr[j * N + i] * u[j];
+    u[i] = s / f.Rqr[i * N + i];
+  }
+  for (int i = N - 1; i >= 0; --i) {
+    T s = u[i];
+    for (int j = i + 1; j < N; ++j) s -= f.Rqr[i * N + j] * v[j];
+    v[i] = s / f.Rqr[i * N + i];
+  }
+  for (int i = 0; i < N; ++i) mu[i] = v[i] / f.d[i];
+  return mu;
+}
+
 struct GradOut {
   int status;
   double cost;
@@ -406,26 +439,7 @@ GradOut fit_grad(int64_t F, const double *omega, const double *eps_re, const dou
   g.g_im.assign(F, nan);
   if (f.status != ST_OK) return g;
 
-  std::vector<double> gw(N, 0.0), sg(N);
-  for (int i = 0; i < N; ++i) {
-    double s = 0;
-    for (int64_t k = 0; k < F; ++k) s += f.R[k * N + i] * f.rre[k] + f.I[k * N + i] * f.rim[k];
-    gw[i] = -2.0 * s;
-    sg[i] = (flags & FLAG_NO_SIGN_FLIP) ? 1.0 : (f.z[i] < 0 ? -1.0 : 1.0);
-  }
-  // mu = D^-1 Rqr^-1 Rqr^-T D^-1 (s o g_w)
-  std::vector<double> u(N), v(N), mu(N);
-  for (int i = 0; i < N; ++i) {
-    double s = sg[i] * gw[i] / f.d[i];
-    for (int j = 0; j < i; ++j) s -= f.Rqr[j * N + i] * u[j];
-    u[i] = s / f.Rqr[i * N + i];
-  }
-  for (int i = N - 1; i >= 0; --i) {
-    double s = u[i];
-    for (int j = i + 1; j < N; ++j) s -= f.Rqr[i * N + j] * v[j];
-    v[i] = s / f.Rqr[i * N + i];
-  }
-  for (int i = 0; i < N; ++i) mu[i] = v[i] / f.d[i];
+  const std::vector<double> mu = adjoint_mu(f, F, N, flags);
 
   std::vector<double> Iz(F), Imu(F);
   for (int64_t k = 0; k < F; ++k) {
@@ -456,6 +470,49 @@ GradOut fit_grad(int64_t F, const double *omega, const double *eps_re, const dou
     g.g_im[k] = 2.0 * f.rim[k] + Imu[k];
   }
   return g;
+}
+
+// ---------------------------------------------------------------------------
+// Sensitivity of the cost to the rounding of the basis.  Any FP64 evaluation
+// works with R and I rounded to a few units of roundoff u; to first order the
+// cost then moves by up to  u * sum_ki (|dC/dR_ki R_ki| + |dC/dI_ki I_ki|),
+// with the total derivatives (weights and eps_inf following the basis)
+//   dC/dR_ki = -2 w_i r'_k         (eps_inf is a mean and sum_k r'_k = 0)
+//   dC/dI_ki = -2 w_i r''_k + mu_i (eps'' - I z)_k - z_i (I mu)_k - 2 damping z_i mu_i I_ki,
+// the same adjoint as the theta gradient before its contraction with dR/dtheta
+// and dI/dtheta.  cond = that sum / C is the relative condition number of the
+// cost under componentwise relative perturbations of the basis; computed in
+// 80-bit arithmetic.  Returns the status; cond = NaN unless ST_OK.
+// ---------------------------------------------------------------------------
+int basis_sensitivity(int64_t F, const double *omega, const double *eps_re, const double *eps_im, int N,
+                      const double *theta, double damping, unsigned flags, double *dCdR, double *dCdI,
+                      double *cond) {
+  using T = long double;
+  std::vector<T> er(F), ei(F), th(N);
+  for (int64_t k = 0; k < F; ++k) { er[k] = eps_re[k]; ei[k] = eps_im[k]; }
+  for (int i = 0; i < N; ++i) th[i] = theta[i];
+  Fit<T> f = fit_forward<T>(F, omega, er.data(), ei.data(), N, th.data(), damping, flags);
+  *cond = std::numeric_limits<double>::quiet_NaN();
+  if (f.status != ST_OK) return f.status;
+  const std::vector<T> mu = adjoint_mu(f, F, N, flags);
+  T sum = T(0);
+  for (int64_t k = 0; k < F; ++k) {
+    T iz = T(0), im = T(0);
+    for (int i = 0; i < N; ++i) {
+      iz += f.I[k * N + i] * f.z[i];
+      im += f.I[k * N + i] * mu[i];
+    }
+    for (int i = 0; i < N; ++i) {
+      const T dr = T(-2) * f.w[i] * f.rre[k];
+      const T di = T(-2) * f.w[i] * f.rim[k] + mu[i] * (ei[k] - iz) - f.z[i] * im -
+                   T(2) * T(damping) * f.z[i] * mu[i] * f.I[k * N + i];
+      if (dCdR) dCdR[k * N + i] = (double)dr;
+      if (dCdI) dCdI[k * N + i] = (double)di;
+      sum += std::fabs(dr * f.R[k * N + i]) + std::fabs(di * f.I[k * N + i]);
+    }
+  }
+  *cond = f.cost > 0 ? (double)(sum / f.cost) : INFINITY;
+  return ST_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -715,6 +772,45 @@ int orc_fit_cs_grad(int64_t F, const double *omega, const double *eps_re, const 
 
 // Per-candidate internals for tests: unflipped LS solution z, scaling d and
 // the residuals.  Returns the status.
+// Cost from an explicitly given basis R, I ([F][N] row-major), steps 2-5 of
+// the forward map; precision 64 or 80.
+int orc_fit_from_basis(int64_t F, const double *R, const double *I, const double *eps_re, const double *eps_im,
+                       int32_t N, double damping, uint32_t flags, int32_t precision, double *cost) {
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    Fit<T> f;
+    f.R.assign(R, R + (size_t)F * N);
+    f.I.assign(I, I + (size_t)F * N);
+    std::vector<T> er(eps_re, eps_re + F), ei(eps_im, eps_im + F);
+    f.cost = T(std::numeric_limits<double>::quiet_NaN());
+    f.z.assign(N, T(0));
+    f.w.assign(N, T(0));
+    fit_solve(f, F, er.data(), ei.data(), N, damping, flags);
+    *cost = (double)f.cost;
+    return f.status;
+  };
+  return precision == 80 ? run((long double)0) : run(0.0);
+}
+
+int orc_fit_cond(int64_t F, const double *omega, const double *eps_re, const double *eps_im, int32_t N,
+                 const double *theta, double damping, uint32_t flags, double *dCdR, double *dCdI, double *cond) {
+  return basis_sensitivity(F, omega, eps_re, eps_im, N, theta, damping, flags, dCdR, dCdI, cond);
+}
+
+int orc_fit_cond_batch(int32_t M, const int64_t *f_off, const int64_t *cand_off, const int32_t *n_poles,
+                       const double *omega, const double *eps_re, const double *eps_im, const double *theta,
+                       int64_t ld, double damping, uint32_t flags, double *cond, int nthreads) {
+  const int64_t P = cand_off[M];
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads_or_default(nthreads))
+  for (int64_t c = 0; c < P; ++c) {
+    int m = mat_of(cand_off, M, c);
+    int64_t a = f_off[m], F = f_off[m + 1] - f_off[m];
+    basis_sensitivity(F, omega + a, eps_re + a, eps_im + a, n_poles[m], theta + c * ld, damping, flags, nullptr,
+                      nullptr, cond + c);
+  }
+  return 0;
+}
+
 int orc_fit_detail(int64_t F, const double *omega, const double *eps_re, const double *eps_im, int32_t N,
                    const double *theta, double damping, uint32_t flags, double *z, double *d,
                    double *rre, double *rim) {

@@ -34,31 +34,18 @@ def cost_rel_err(c, ref, floor):
 
 
 def attributed_cost_err(orc, ob, theta, c_gpu, floor, damping, flags, rel64, stats=None):
-    """Cost error after attribution.  A candidate whose error against the FP64
-    oracle exceeds COST_RTOL is judged against the 80-bit (long double)
-    instance of the same oracle, the more accurate reference.  If it still
-    exceeds COST_RTOL there, the candidate is ill-conditioned beyond what any
-    FP64 evaluation can resolve (near-duplicate relaxation times); it passes
-    when the GPU is at least as close to the 80-bit result as the FP64 oracle
-    is (its error is reported as 0 after that check, and counted in stats).
-    Returns (errors, number of candidates judged against the 80-bit oracle)."""
-    over = rel64 > COST_RTOL
-    if stats is not None:
-        stats.update(n=len(rel64), oracle_limited=0, fp64_limited=0, max_rel_80=0.0)
-    if not over.any():
-        return rel64, 0
-    c80 = orc.fit_eval(ob, theta, damping=damping, flags=flags, precision=80)[0]
-    rel80 = cost_rel_err(c_gpu, c80, floor)
+    """Cost error after the oracle's attribution (oracle.judge_costs): a
+    candidate over COST_RTOL against the FP64 oracle is judged against its
+    80-bit instance; one still over COST_RTOL there passes only if its error
+    is within the FP64 rounding sensitivity of its cost (cond * u) or the
+    FP64 oracle's own error.  Returns (errors, number of candidates judged
+    against the 80-bit oracle)."""
     c64 = np.asarray(ob_cost64(orc, ob, theta, damping, flags))
-    own = cost_rel_err(c64, c80, floor)                 # the FP64 oracle's own error
-    out = rel64.copy()
-    out[over] = rel80[over]
-    limited = over & (rel80 > COST_RTOL) & (rel80 <= own)
+    st = {}
+    rel, _ = orc.judge_costs(ob, np.asarray(theta), c_gpu, c64, floor, COST_RTOL, damping, flags, st, rel=rel64)
     if stats is not None:
-        stats.update(oracle_limited=int((over & (rel80 <= COST_RTOL)).sum()), fp64_limited=int(limited.sum()),
-                     max_rel_80=float(rel80[over].max()))
-    out[limited] = 0.0
-    return out, int(over.sum())
+        stats.update(st)
+    return rel, st["oracle_limited"] + st["fp64_limited"] + int(np.sum(rel > COST_RTOL))
 
 
 def ob_cost64(orc, ob, theta, damping, flags):
