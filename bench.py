@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--polish-steps", type=int, default=-1)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default frequency splits")
+    ap.add_argument("--freq-split", type=int, default=0,
+                    help="fixed frequency split for every pole count (implies --no-autotune)")
     ap.add_argument("--only-eval", type=int, default=0,
                     help="profiling: run this many forward launches of the swarm batch and exit")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -112,6 +115,15 @@ def main():
     lb = torch.tensor(wl.lb, device=dev)
     ub = torch.tensor(wl.ub, device=dev)
     plan = D.Plan(b)
+    if args.freq_split:
+        plan.set_freq_split(args.freq_split)
+    elif not args.no_autotune:
+        # schedule tuned once on the workload's own targets and a uniform draw of
+        # candidates (set-up, outside the timed region)
+        er0, ei0 = D.material_eval(kind_t, params_t, b, noise_seed=wl.noise_seed)
+        th0 = torch.tensor(W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=5), device=dev)
+        plan.autotune(b.with_targets(er0, ei0), th0, reps=2)
+        del er0, ei0, th0
     sw = D.Swarm.empty(P, M, wl.ld, args.iters + 1, dev)
     work_per_eval = float(np.sum(np.diff(wl.cand_off) * np.array(
         [algorithmic_flops(int(f), int(n)) for f, n in zip(np.diff(wl.f_off), wl.n_poles)])))  # per swarm launch
@@ -231,6 +243,7 @@ def main():
         "fwd_kernel_evals_per_s": fwd_rate,
         "fwd_adjoint_kernel_evals_per_s": adj_rate,
         "swarm_fit_ms": {"eager": t_sw["eager"], "graph": t_sw["graph"]},
+        "schedule": {f"N{i['n_poles']}": f"{i['pole_split']}x{i['freq_split']} lanes" for i in plan.info()},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
                      "kernel": f"fit_kernel<{N},{1 if N <= 8 else (2 if N <= 12 else 4)},false>" if uniform

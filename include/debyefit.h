@@ -105,7 +105,12 @@ typedef struct debye_batch {
  * pole count, lanes per candidate, work lists sorted by cost (longest first),
  * and workspace.  Build it once per shape from HOST copies of the offsets;
  * reuse it for every call on batches of that shape (e.g. every iteration of
- * an optimiser).  `flags` is reserved (0). */
+ * an optimiser).  `flags` is reserved (0).
+ * With more than one pole count the buckets of an evaluation are forked from
+ * the caller's stream onto up to four streams owned by the plan and joined
+ * back before the call's work is complete on the caller's stream (under
+ * stream capture they become parallel graph branches).  A plan is therefore
+ * not to be used from two host threads at once. */
 typedef struct debye_plan debye_plan;
 
 int debye_plan_create(const debye_batch *shape, const int64_t *f_off_host, const int64_t *cand_off_host,
@@ -116,6 +121,18 @@ int debye_plan_destroy(debye_plan *plan);
  * frequency axis, a power of two; 0 restores the automatic choice) for pole
  * count n_poles (0 = all). Used by the autotuner and the tests. */
 int debye_plan_set_freq_split(debye_plan *plan, int32_t n_poles, int32_t split);
+
+/* Autotune the schedule on real data: for every pole-count bucket without an
+ * override, time `reps` launches (1..100) of the cost kernel at each frequency
+ * split (1, 2, 4, ... up to 64 / pole split, while spectra keep at least 8
+ * points per lane) with HIP events on `stream`, and keep the fastest.  The
+ * arguments are those of debye_fit_eval (log10_tau: a representative set of
+ * candidates, e.g. the initial swarm).  Synchronises `stream`; allocates and
+ * frees a temporary cost buffer, so it is a set-up call, not for capture.
+ * The choice stays in the plan (debye_plan_info reports it); an override set
+ * by debye_plan_set_freq_split takes precedence. */
+int debye_plan_autotune(debye_plan *plan, const debye_batch *b, const double *log10_tau, int64_t ld,
+                        double damping, uint32_t flags, int32_t reps, hipStream_t stream);
 
 /* Schedule introspection: with i < 0 returns the number of pole-count buckets;
  * otherwise fills the pole count, pole split, frequency split and number of

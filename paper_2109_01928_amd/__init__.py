@@ -30,7 +30,8 @@ MAX_POLES = 24
 PARAM_STRIDE = 16
 DEFAULT_DAMPING = 1e-8
 
-EXPORTED = ["debye_plan_create", "debye_plan_destroy", "debye_plan_set_freq_split", "debye_plan_info",
+EXPORTED = ["debye_plan_create", "debye_plan_destroy", "debye_plan_set_freq_split", "debye_plan_autotune",
+            "debye_plan_info",
             "debye_last_error", "debye_version", "debye_basis", "debye_fit_eval", "debye_fit_eval_grad",
             "debye_material_eval", "debye_material_vjp", "debye_pso_init", "debye_pso_step",
             "debye_pso_run", "debye_lbfgs_polish"]
@@ -81,6 +82,7 @@ def lib():
     L.debye_plan_destroy.argtypes = [_vp]
     L.debye_plan_set_freq_split.argtypes = [_vp, i32, i32]
     L.debye_plan_info.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
+    L.debye_plan_autotune.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, i32, _vp]
     L.debye_basis.argtypes = [_vp, i64, _vp, i64, i64, i32, _vp, _vp, _vp]
     L.debye_fit_eval.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, _vp, _vp, _vp, _vp, _vp]
     L.debye_fit_eval_grad.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -159,6 +161,14 @@ class Plan:
 
     def set_freq_split(self, split, n_poles=0):
         _check(lib().debye_plan_set_freq_split(self.handle, n_poles, split))
+
+    def autotune(self, b: "Batch", theta, damping=1e-8, flags=0, reps=3):
+        """Time each bucket's frequency splits on (b, theta) and keep the fastest
+        (debye_plan_autotune; synchronises the current stream)."""
+        assert theta.dtype == torch.float64 and theta.is_contiguous() and theta.dim() == 2 and theta.shape[0] == b.P
+        cb = b.cstruct()
+        _check(lib().debye_plan_autotune(self.handle, C.byref(cb), _ptr(theta), theta.shape[1], damping, flags, reps,
+                                         _stream()))
 
     def info(self):
         L = lib()

@@ -42,13 +42,19 @@ int hip_fail(hipError_t e, const char *what) {
 // Lanes per wave that the schedule tries to keep busy: the GPU has 256 CUs x 4
 // SIMDs; at two waves per SIMD a batch needs about 2048 waves to fill it.
 constexpr int64_t TARGET_WAVES = 2048;
-constexpr int MAX_LDS_PER_BLOCK = 64 * 1024;
+// LDS budget of one single-wave block: a CU has 160 KiB, and two waves per SIMD
+// (eight per CU) need at most 20 KiB each
+constexpr int LDS_PER_WAVE = 20 * 1024;
+// concurrent streams over which the pole-count buckets of one evaluation are
+// spread (one hardware queue each)
+constexpr int MAX_SIDE_STREAMS = 4;
 
 }  // namespace
 
 struct Bucket {
   int32_t N = 0, SP = 1, SF = 1, cpw = 64;
   int64_t n_cands = 0, n_tiles = 0, max_f = 0, work = 0;
+  double flops = 0;          // algorithmic FP64 work of one evaluation of the bucket
   std::vector<int32_t> mats;
   int32_t *d_lane_cand = nullptr, *d_lane_mat = nullptr, *d_mats = nullptr;
 };
@@ -71,8 +77,14 @@ struct debye_plan {
   std::vector<int32_t> n_poles;
   std::vector<Bucket> buckets;
   std::map<int32_t, int32_t> sf_override;  // N (0 = all) -> frequency split
+  std::map<int32_t, int32_t> sf_tuned;     // N -> split measured fastest by debye_plan_autotune
   double *d_record = nullptr;
   int64_t rec_ld = 0;
+  // fork/join of the buckets over side streams: bucket i runs on side[lane_of[i]]
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev_join;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<int> stream_of;
 };
 
 namespace {
@@ -89,14 +101,17 @@ int pick_split(const debye_plan &p, const Bucket &b) {
   if (it == p.sf_override.end()) it = p.sf_override.find(0);
   const int max_sf = 64 / b.SP;
   if (it != p.sf_override.end() && it->second > 0) return std::min(it->second, max_sf);
+  auto tuned = p.sf_tuned.find(b.N);
+  if (tuned != p.sf_tuned.end()) return std::min(tuned->second, max_sf);
   // smallest power of two that gives TARGET_WAVES waves, without splitting
   // short spectra below 16 points per lane
   const int64_t avg_f = b.n_cands ? b.work / (b.n_cands * b.N) : 1;
   int sf = 1;
   while (sf < max_sf && (b.n_cands * b.SP * sf + 63) / 64 < TARGET_WAVES && avg_f / (2 * sf) >= 16) sf *= 2;
-  // the SP > 1 path keeps each candidate's normal matrix in LDS
+  // the SP > 1 path keeps each candidate's normal matrix in LDS: fewer
+  // candidates per wave until two waves per SIMD fit
   const int lds = dfit::lds_bytes_per_candidate(b.N);
-  while (lds > 0 && sf < max_sf && (64 / (b.SP * sf)) * lds > MAX_LDS_PER_BLOCK) sf *= 2;
+  while (lds > 0 && sf < max_sf && (64 / (b.SP * sf)) * lds > LDS_PER_WAVE) sf *= 2;
   return sf;
 }
 
@@ -179,6 +194,33 @@ dfit::FitArgs fit_args(const debye_plan *p, const Bucket &bk, const debye_batch 
   return a;
 }
 
+// Enqueue launch(bucket, stream) for every non-empty bucket.  With several
+// buckets they fork from `stream` onto the plan's side streams and join back,
+// so different pole counts overlap on the GPU; under stream capture the fork
+// and join become parallel branches of the graph.
+template <class LAUNCH> int for_buckets(const debye_plan *p, hipStream_t stream, LAUNCH &&launch) {
+  if (p->side.empty()) {
+    for (const Bucket &bk : p->buckets)
+      if (bk.n_tiles) {
+        int rc = launch(bk, stream);
+        if (rc) return rc;
+      }
+    return DEBYE_OK;
+  }
+  const int n_side = (int)p->side.size();
+  CHECK_HIP(hipEventRecord(p->ev_fork, stream), "fork event");
+  for (int j = 0; j < n_side; ++j) CHECK_HIP(hipStreamWaitEvent(p->side[j], p->ev_fork, 0), "fork wait");
+  int rc = DEBYE_OK;
+  for (size_t i = 0; i < p->buckets.size() && rc == DEBYE_OK; ++i)
+    if (p->buckets[i].n_tiles) rc = launch(p->buckets[i], p->side[p->stream_of[i]]);
+  // join every side stream, also after a failed launch, so no capture is left open
+  for (int j = 0; j < n_side; ++j) {
+    CHECK_HIP(hipEventRecord(p->ev_join[j], p->side[j]), "join event");
+    CHECK_HIP(hipStreamWaitEvent(stream, p->ev_join[j], 0), "join wait");
+  }
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -231,15 +273,37 @@ int debye_plan_create(const debye_batch *shape, const int64_t *f_off_host, const
     const int64_t F = f_off_host[m + 1] - f_off_host[m];
     b.max_f = std::max(b.max_f, F);
     b.work += P * F * b.N;
+    b.flops += (double)P * ((double)F * (b.N * b.N + 13.0 * b.N + 5.0) + b.N * b.N * (b.N / 3.0 + 2.0));
   }
   for (auto &kv : by_n) p->buckets.push_back(std::move(kv.second));
   // largest work first
-  std::stable_sort(p->buckets.begin(), p->buckets.end(), [](const Bucket &x, const Bucket &y) { return x.work > y.work; });
+  std::stable_sort(p->buckets.begin(), p->buckets.end(), [](const Bucket &x, const Bucket &y) { return x.flops > y.flops; });
   for (auto &b : p->buckets) {
     rc = build_tiles(*p, b);
     if (rc) {
       debye_plan_destroy(p);
       return rc;
+    }
+  }
+  // several pole counts: the buckets run concurrently on side streams, each
+  // bucket (largest first) on the stream with the least work so far
+  const int n_side = std::min<int>(MAX_SIDE_STREAMS, (int)p->buckets.size());
+  if (n_side > 1) {
+    p->side.assign(n_side, nullptr);
+    p->ev_join.assign(n_side, nullptr);
+    bool ok = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int j = 0; j < n_side && ok; ++j)
+      ok = hipStreamCreateWithFlags(&p->side[j], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&p->ev_join[j], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      debye_plan_destroy(p);
+      return fail(DEBYE_EHIP, "plan: stream or event creation failed");
+    }
+    std::vector<double> load(n_side, 0.0);
+    for (const Bucket &b : p->buckets) {
+      const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      p->stream_of.push_back(j);
+      load[j] += b.flops;
     }
   }
   *out = p;
@@ -254,8 +318,15 @@ int debye_plan_destroy(debye_plan *p) {
   if (p->graph.ev_out) (void)hipEventDestroy(p->graph.ev_out);
   if (p->graph.stream) (void)hipStreamDestroy(p->graph.stream);
   if (p->graph.counter) (void)hipFree(p->graph.counter);
+  for (hipStream_t st : p->side)
+    if (st) (void)hipStreamSynchronize(st);
   for (auto &b : p->buckets) free_bucket(b);
   if (p->d_record) (void)hipFree(p->d_record);
+  for (hipStream_t st : p->side)
+    if (st) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : p->ev_join)
+    if (ev) (void)hipEventDestroy(ev);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   delete p;
   return DEBYE_OK;
 }
@@ -270,6 +341,56 @@ int debye_plan_set_freq_split(debye_plan *p, int32_t n_poles, int32_t split) {
     if (rc) return rc;
   }
   return DEBYE_OK;
+}
+
+int debye_plan_autotune(debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld, double damping,
+                        uint32_t flags, int32_t reps, hipStream_t stream) {
+  int rc = check_plan_batch(p, b, ld);
+  if (rc) return rc;
+  if ((rc = check_damping(damping, flags))) return rc;
+  if (!log10_tau) return fail(DEBYE_EINVAL, "log10_tau is NULL");
+  if (reps < 1 || reps > 100) return fail(DEBYE_ERANGE, "reps must be in 1..100");
+  double *cost = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&](int r) {
+    (void)hipStreamSynchronize(stream);
+    if (cost) (void)hipFree(cost);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return r;
+  };
+  if (hipMalloc(&cost, (size_t)std::max<int64_t>(p->n_cand, 1) * 8) != hipSuccess)
+    return cleanup(fail(DEBYE_ENOMEM, "autotune: cost buffer allocation failed"));
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return cleanup(fail(DEBYE_EHIP, "autotune: event creation failed"));
+  for (Bucket &bk : p->buckets) {
+    if (!bk.n_cands || p->sf_override.count(bk.N) || p->sf_override.count(0)) continue;
+    const int64_t avg_f = bk.work / (bk.n_cands * bk.N);
+    int best_sf = 1;
+    float best_ms = INFINITY;
+    for (int sf = 1; sf <= 64 / bk.SP; sf *= 2) {
+      if (sf > 1 && avg_f / sf < 8) break;
+      p->sf_tuned[bk.N] = sf;
+      if ((rc = build_tiles(*p, bk))) return cleanup(rc);
+      dfit::FitArgs a = fit_args(p, bk, b, log10_tau, ld, damping, flags);
+      a.cost = cost;
+      hipError_t e = dfit::launch_fit(bk.N, a, bk.n_tiles, false, stream);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = dfit::launch_fit(bk.N, a, bk.n_tiles, false, stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) return cleanup(hip_fail(e, "autotune launch"));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_sf = sf;
+      }
+    }
+    p->sf_tuned[bk.N] = best_sf;
+    if ((rc = build_tiles(*p, bk))) return cleanup(rc);
+  }
+  return cleanup(DEBYE_OK);
 }
 
 int debye_plan_info(const debye_plan *p, int32_t i, int32_t *n_poles, int32_t *pole_split, int32_t *freq_split,
@@ -301,16 +422,15 @@ int debye_fit_eval(const debye_plan *p, const debye_batch *b, const double *log1
   if (rc) return rc;
   if ((rc = check_damping(damping, flags))) return rc;
   if (!log10_tau || !cost) return fail(DEBYE_EINVAL, "log10_tau and cost must not be NULL");
-  for (const Bucket &bk : p->buckets) {
-    if (!bk.n_tiles) continue;
+  return for_buckets(p, stream, [&](const Bucket &bk, hipStream_t s) -> int {
     dfit::FitArgs a = fit_args(p, bk, b, log10_tau, ld, damping, flags);
     a.cost = cost;
     a.weights = weights;
     a.eps_inf = eps_inf;
     a.status = status;
-    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, false, stream), "debye_fit_eval launch");
-  }
-  return DEBYE_OK;
+    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, false, s), "debye_fit_eval launch");
+    return DEBYE_OK;
+  });
 }
 
 int debye_fit_eval_grad(const debye_plan *pc, const debye_batch *b, const double *log10_tau, int64_t ld,
@@ -332,8 +452,13 @@ int debye_fit_eval_grad(const debye_plan *pc, const debye_batch *b, const double
       return fail(DEBYE_ENOMEM, "adjoint workspace allocation failed");
     }
   }
-  for (const Bucket &bk : p->buckets) {
-    if (!bk.n_tiles) continue;
+  if (targets) {
+    // materials without candidates get zero target gradients (a fill kernel,
+    // not a memset, so that the call can be captured into a graph)
+    CHECK_HIP(dfit::launch_fill(grad_eps_re, p->n_freq, 0.0, stream), "fill");
+    CHECK_HIP(dfit::launch_fill(grad_eps_im, p->n_freq, 0.0, stream), "fill");
+  }
+  rc = for_buckets(p, stream, [&](const Bucket &bk, hipStream_t s) -> int {
     dfit::FitArgs a = fit_args(p, bk, b, log10_tau, ld, damping, flags);
     a.cost = cost;
     a.status = status;
@@ -341,14 +466,9 @@ int debye_fit_eval_grad(const debye_plan *pc, const debye_batch *b, const double
     a.grad_theta = grad_log10_tau;
     a.record = targets ? p->d_record : nullptr;
     a.rec_ld = p->rec_ld;
-    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, true, stream), "debye_fit_eval_grad launch");
-  }
-  if (targets) {
-    // materials without candidates get zero target gradients
-    CHECK_HIP(hipMemsetAsync(grad_eps_re, 0, (size_t)p->n_freq * 8, stream), "memset");
-    CHECK_HIP(hipMemsetAsync(grad_eps_im, 0, (size_t)p->n_freq * 8, stream), "memset");
-    for (const Bucket &bk : p->buckets) {
-      if (!bk.n_tiles) continue;
+    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, true, s), "debye_fit_eval_grad launch");
+    if (!targets) return DEBYE_OK;
+    {
       dfit::TargetGradArgs t{};
       t.f_off = b->f_off;
       t.cand_off = b->cand_off;
@@ -362,10 +482,12 @@ int debye_fit_eval_grad(const debye_plan *pc, const debye_batch *b, const double
       t.mat_list = bk.d_mats;
       t.grad_re = grad_eps_re;
       t.grad_im = grad_eps_im;
-      CHECK_HIP(dfit::launch_target_grad(bk.N, t, bk.max_f, (int32_t)bk.mats.size(), stream), "target gradient launch");
+      // the bucket's materials only: disjoint from the other buckets' points
+      CHECK_HIP(dfit::launch_target_grad(bk.N, t, bk.max_f, (int32_t)bk.mats.size(), s), "target gradient launch");
     }
-  }
-  return DEBYE_OK;
+    return DEBYE_OK;
+  });
+  return rc;
 }
 
 int debye_material_eval(int32_t M, const int8_t *kind, const double *params, const int64_t *f_off, int64_t n_freq,

@@ -28,9 +28,11 @@ __device__ __forceinline__ double rcp_nr(double d) {
 
 // Cross-lane move of a double inside a quad (DPP quad_perm; CTRL encodes the
 // source lane of each of the four lanes, two bits per lane).
+// Every source lane of a quad permutation is valid, so the move needs no
+// "old" value (bound_ctrl set) and compiles to two bare v_mov_b32_dpp.
 template <int CTRL> __device__ __forceinline__ double dpp_quad(double v) {
-  int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, 0xF, 0xF, false);
-  int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, 0xF, 0xF, false);
+  int lo = __builtin_amdgcn_mov_dpp((int)__double2loint(v), CTRL, 0xF, 0xF, true);
+  int hi = __builtin_amdgcn_mov_dpp((int)__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 constexpr int QP_SWAP1 = 0xB1;  // [1,0,3,2]: lane ^ 1

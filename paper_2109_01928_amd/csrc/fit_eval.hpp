@@ -81,6 +81,8 @@ struct PsoArgs {
 hipError_t launch_pso_init(const PsoArgs &a, int64_t n_cand, hipStream_t s);
 hipError_t launch_pso_step(const PsoArgs &a, hipStream_t s);
 hipError_t launch_set_counter(int32_t *c, int32_t value, hipStream_t s);
+// p[0..n) = v (a kernel, so that it can sit in a captured graph)
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_tick(int32_t *c, hipStream_t s);
 
 struct LbfgsArgs {

@@ -5,6 +5,8 @@
 // velocity update is rounded separately (no fused multiply-add) and evaluated
 // in a fixed order, so a swarm is bit-reproducible from its seed.
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "fit_eval.hpp"
 
@@ -151,6 +153,17 @@ hipError_t launch_set_counter(int32_t *c, int32_t value, hipStream_t s) {
   hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(1), 0, s, c, value);
   return hipGetLastError();
 }
+__global__ __launch_bounds__(256) void fill_kernel(double *p, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_tick(int32_t *c, hipStream_t s) {
   hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, s, c);
   return hipGetLastError();

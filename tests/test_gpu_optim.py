@@ -135,6 +135,38 @@ def test_adjoint_matches_oracle(D, orc, N, F, flags, damping):
             assert np.max(np.abs(a[s:e] - o[s:e])) <= 1e-6 * np.max(np.abs(o[s:e]))
 
 
+def test_adjoint_ragged_matches_oracle(D, orc):
+    """Several pole counts at once (their buckets run on concurrent streams),
+    with the target gradients summed per material."""
+    import torch
+    wl = small_ragged(18, seed=31, Fr=(40, 300), Nr=(1, 24), Pr=(0, 40))
+    er, ei = targets_oracle(orc, wl)
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=8)
+    gc = np.linspace(0.5, 2.0, wl.P)
+    ob = orc.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, er, ei)
+    oc, og, ogr, ogi, ost = orc.fit_grad(ob, theta, grad_cost=gc)
+    b = _batch(D, wl, er, ei)
+    plan = D.Plan(b)
+    c, g, gr, gi, st = D.fit_eval_grad(plan, b, _t(theta), grad_cost=_t(gc), targets=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(st.cpu().numpy(), ost)
+    rel = cost_rel_err(c.cpu().numpy(), oc, cost_floor(wl, er, ei))
+    rel, _ = attributed_cost_err(orc, ob, theta, c.cpu().numpy(), cost_floor(wl, er, ei), 1e-8, 0, rel)
+    assert rel.max() <= COST_RTOL
+    g = g.cpu().numpy()
+    for cI in range(wl.P):
+        m = int(np.searchsorted(wl.cand_off, cI, side="right") - 1)
+        n = wl.n_poles[m]
+        assert np.max(np.abs(g[cI, :n] - og[cI, :n])) <= 1e-6 * np.max(np.abs(og[cI, :n])), cI
+    for a, o in ((gr.cpu().numpy(), ogr), (gi.cpu().numpy(), ogi)):
+        for m in range(wl.M):
+            s, e = wl.f_off[m], wl.f_off[m + 1]
+            if wl.cand_off[m + 1] == wl.cand_off[m]:
+                assert np.all(a[s:e] == 0.0)
+            else:
+                assert np.max(np.abs(a[s:e] - o[s:e])) <= 1e-6 * np.max(np.abs(o[s:e])), m
+
+
 def test_adjoint_matches_central_differences_on_gpu(D, orc):
     import torch
     wl = small_uniform(1, 2000, 12, 1, seed=4, fmin=1e5, fmax=1e11, kinds=[W.KIND_HN])

@@ -38,9 +38,11 @@ def _check_eval(D, orc, wl, theta, damping=1e-8, flags=0, split=None, tag=""):
     oc, ow, oe, ost = orc.fit_eval(ob, theta, damping=damping, flags=flags)
     b = _gpu_batch(D, wl, er, ei)
     plan = D.Plan(b)
-    if split:
-        plan.set_freq_split(split)
     th = torch.tensor(theta, device="cuda")
+    if split == "tune":
+        plan.autotune(b, th, damping=damping, flags=flags, reps=1)
+    elif split:
+        plan.set_freq_split(split)
     c, w, e, st = D.fit_eval(plan, b, th, damping=damping, flags=flags)
     torch.cuda.synchronize()
     c, w, e, st = (t.cpu().numpy() for t in (c, w, e, st))
@@ -137,6 +139,7 @@ def test_cost_parity_ragged_batch(D, orc):
     theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=3)
     _check_eval(D, orc, wl, theta, tag="ragged")
     _check_eval(D, orc, wl, theta, split=8, tag="ragged")
+    _check_eval(D, orc, wl, theta, split="tune", tag="ragged-autotuned")
 
 
 def test_edge_cases_and_status(D, orc):
