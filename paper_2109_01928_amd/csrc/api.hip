@@ -54,6 +54,7 @@ constexpr int MAX_SIDE_STREAMS = 4;
 struct Bucket {
   int32_t N = 0, SP = 1, SF = 1, cpw = 64;
   int64_t n_cands = 0, n_tiles = 0, max_f = 0, work = 0;
+  int64_t xcd_off[9] = {};   // tiles of XCD x: xcd_off[x] .. xcd_off[x+1]-1
   double flops = 0;          // algorithmic FP64 work of one evaluation of the bucket
   std::vector<int32_t> mats;
   int32_t *d_lane_cand = nullptr, *d_lane_mat = nullptr, *d_mats = nullptr;
@@ -115,25 +116,55 @@ int pick_split(const debye_plan &p, const Bucket &b) {
   return sf;
 }
 
+// Work tiles of a bucket and their split over the 8 XCDs.  Work items are
+// runs of one material's candidates (a material with more than 1/32 of the
+// bucket's tiles is cut into pieces, so that a few big swarms still spread
+// over the chip); the items, longest tiles first, go one by one to the XCD
+// with the least estimated work (LPT), which keeps a material's spectra in
+// one L2 and finishes the XCDs together.  Each XCD's candidates are packed
+// into tiles in that order (a tile may span two materials of the same XCD).
 int build_tiles(debye_plan &p, Bucket &b) {
   free_bucket(b);
   b.SF = pick_split(p, b);
   b.cpw = 64 / (b.SP * b.SF);
-  // longest spectra first, candidates of a material kept together
-  std::vector<int32_t> order = b.mats;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    return (p.f_off[x + 1] - p.f_off[x]) > (p.f_off[y + 1] - p.f_off[y]);
-  });
-  std::vector<int32_t> lc, lm;
-  lc.reserve(b.n_cands + b.cpw);
-  for (int32_t m : order)
-    for (int64_t c = p.cand_off[m]; c < p.cand_off[m + 1]; ++c) {
-      lc.push_back((int32_t)c);
-      lm.push_back(m);
+  struct Item {
+    int32_t m;
+    int64_t c0, c1;   // candidates [c0, c1)
+    double tile_t;    // estimated duration of one tile: points per lane plus the solve
+  };
+  int64_t total_tiles = 0;
+  for (int32_t m : b.mats) total_tiles += (p.cand_off[m + 1] - p.cand_off[m] + b.cpw - 1) / b.cpw;
+  const int64_t max_item = std::max<int64_t>(1, total_tiles / 32) * b.cpw;  // candidates
+  std::vector<Item> items;
+  for (int32_t m : b.mats) {
+    const int64_t F = p.f_off[m + 1] - p.f_off[m];
+    const double t = (double)((F + b.SF - 1) / b.SF) + 0.05 * b.N * b.N;
+    for (int64_t c = p.cand_off[m]; c < p.cand_off[m + 1]; c += max_item)
+      items.push_back({m, c, std::min(c + max_item, p.cand_off[m + 1]), t});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.tile_t > y.tile_t; });
+  std::vector<std::vector<int32_t>> xc(8), xm(8);
+  double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (const Item &it : items) {
+    const int x = (int)(std::min_element(load, load + 8) - load);
+    load[x] += it.tile_t * (double)(it.c1 - it.c0) / b.cpw;
+    for (int64_t c = it.c0; c < it.c1; ++c) {
+      xc[x].push_back((int32_t)c);
+      xm[x].push_back(it.m);
     }
-  while (lc.size() % b.cpw) {
-    lc.push_back(-1);
-    lm.push_back(0);
+  }
+  std::vector<int32_t> lc, lm;
+  lc.reserve(b.n_cands + 8 * b.cpw);
+  lm.reserve(b.n_cands + 8 * b.cpw);
+  b.xcd_off[0] = 0;
+  for (int x = 0; x < 8; ++x) {
+    lc.insert(lc.end(), xc[x].begin(), xc[x].end());
+    lm.insert(lm.end(), xm[x].begin(), xm[x].end());
+    while (lc.size() % b.cpw) {
+      lc.push_back(-1);
+      lm.push_back(0);
+    }
+    b.xcd_off[x + 1] = (int64_t)lc.size() / b.cpw;
   }
   b.n_tiles = (int64_t)lc.size() / b.cpw;
   if (b.n_tiles == 0) return DEBYE_OK;
@@ -190,6 +221,7 @@ dfit::FitArgs fit_args(const debye_plan *p, const Bucket &bk, const debye_batch 
   a.cand_per_wave = bk.cpw;
   a.lane_cand = bk.d_lane_cand;
   a.lane_mat = bk.d_lane_mat;
+  for (int x = 0; x < 9; ++x) a.xcd_off[x] = bk.xcd_off[x];
   (void)p;
   return a;
 }

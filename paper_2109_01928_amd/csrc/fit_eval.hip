@@ -272,12 +272,14 @@ void fit_kernel(const FitArgs a) {
   const int q = sub % SP;            // pole block
   const int fl = sub / SP;           // frequency lane
   // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
-  // block b runs on XCD b % 8; giving each XCD a contiguous range of tiles
-  // keeps the tiles of one material (they are contiguous in the work list) on
-  // one L2.  The grid is rounded up to a multiple of 8; surplus blocks exit.
-  const int64_t tiles_per_xcd = (a.n_tiles + 7) / 8;
-  const int64_t tile = (int64_t)(blockIdx.x & 7) * tiles_per_xcd + (blockIdx.x >> 3);
-  if (tile >= a.n_tiles) return;
+  // block b runs on XCD b % 8 as its (b / 8)-th block.  The plan gives every
+  // XCD its own list of tiles (whole materials where possible, so that a
+  // material's spectra stay in one L2; the lists balanced by work, each
+  // longest first).  The grid covers the longest list; surplus blocks exit.
+  const int xcd = blockIdx.x & 7;
+  const int64_t j = blockIdx.x >> 3;
+  if (j >= a.xcd_off[xcd + 1] - a.xcd_off[xcd]) return;
+  const int64_t tile = a.xcd_off[xcd] + j;
   const int64_t slot = tile * a.cand_per_wave + grp;
   const int32_t cand = a.lane_cand[slot];
   const bool active = cand >= 0;
@@ -707,7 +709,10 @@ template <int N> hipError_t launch_fit_n(const FitArgs &a, int64_t n_tiles, bool
   const size_t lds = (size_t)Shape<N, SP>::LDS_DOUBLES * 8 * a.cand_per_wave;
   FitArgs b = a;
   b.n_tiles = n_tiles;
-  const unsigned blocks = (unsigned)(((n_tiles + 7) / 8) * 8);
+  int64_t longest = 0;
+  for (int x = 0; x < 8; ++x) longest = a.xcd_off[x + 1] - a.xcd_off[x] > longest ? a.xcd_off[x + 1] - a.xcd_off[x] : longest;
+  if (longest == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)(longest * 8);
   if (grad)
     hipLaunchKernelGGL((fit_kernel<N, SP, true>), dim3(blocks), dim3(64), lds, s, b);
   else

@@ -17,6 +17,8 @@ struct FitArgs {
   int32_t freq_split;     // SF: lanes per candidate along the frequency axis
   int32_t cand_per_wave;  // 64 / (SP * SF)
   int64_t n_tiles;        // work tiles (one per wavefront)
+  // tiles of XCD x are xcd_off[x] .. xcd_off[x+1]-1 (in the order to run them)
+  int64_t xcd_off[9];
   const int32_t *lane_cand;  // [tiles * cand_per_wave] candidate index or -1
   const int32_t *lane_mat;   // [tiles * cand_per_wave] material of that candidate
   double *cost, *weights, *eps_inf;
