@@ -43,7 +43,8 @@ template <int N, int SP> struct Shape {
   static constexpr int NV = (SP == 1) ? N : NB + D;          // basis values seen by a lane
   static constexpr int NG = (SP == 1) ? N * (N + 1) / 2 : NB * (D + 1);  // Gram accumulators
   static constexpr int NT = N * (N + 1) / 2;                 // packed triangle
-  static constexpr int LDS_DOUBLES = (SP == 1) ? 0 : N * (N + 1) / 2 + 6 * N;  // per candidate
+  // per candidate: the parked factor (SP == 1), or the whole solve (SP > 1)
+  static constexpr int LDS_DOUBLES = (SP == 1) ? N * (N + 1) / 2 : N * (N + 1) / 2 + 6 * N;
 };
 
 constexpr __host__ __device__ int tri(int n, int i, int j) { return i * n - (i * (i - 1)) / 2 + (j - i); }
@@ -250,6 +251,19 @@ template <int N> struct LdsLayout {
         vz(base + NT + 4 * N), vw(base + NT + 5 * N) {}
 };
 
+// factor parked by the SP == 1 path: A (off-diagonal) and reciprocal pivots
+template <int N>
+__device__ __forceinline__ void unpark(const double *park, int cpw, int grp, double *A, double *uinv) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) {
+      const double v = park[tri(N, i, j) * cpw + grp];
+      if (i == j) uinv[i] = v;
+      else A[tri(N, i, j)] = v;
+    }
+}
+
 // --------------------------------------------------------------------------
 // The kernel.  GRAD adds the adjoint (grad w.r.t. log10 tau, and per-candidate
 // records for the target gradient).
@@ -386,6 +400,21 @@ void fit_kernel(const FitArgs a) {
       invd_own[i] = invd_r[i];
     }
     chol_solve<N>(G, uinv_r, zt);
+    // Park the factor in LDS (reciprocal pivots in place of its diagonal,
+    // which the solves never read), element-major so that a wave's lanes touch
+    // consecutive addresses.  The later solves read it back; meanwhile its
+    // registers serve the frequency passes.
+    {
+      double *park = lds_all;
+      const int cpw = WAVE / SL;
+      if (fl == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int j = i; j < N; ++j) park[tri(N, i, j) * cpw + grp] = (i == j) ? uinv_r[i] : G[tri(N, i, j)];
+      }
+      __syncthreads();
+    }
   } else {
     // assemble the packed triangle in LDS (all lanes of a candidate write the same values)
     L = lds_all + (int64_t)grp * S::LDS_DOUBLES;
@@ -434,17 +463,7 @@ void fit_kernel(const FitArgs a) {
     gl[cI] = 0.0;
   }
   {
-    int64_t k = fl;
-    double w_n = 0, ei_n = 0;
-    if (k < F) {
-      w_n = om[k];
-      ei_n = epi[k];
-    }
-    for (; k < F; k += SF) {
-      const double w = w_n, ei = ei_n;
-      const int64_t kn = (k + SF < F) ? k + SF : k;
-      w_n = om[kn];
-      ei_n = epi[kn];
+    auto step = [&](double w, double ei) {
       double Iv[NB], Rv[NB];
       basis_point<NB>(w, tau, Rv, Iv);
       double part = 0.0;
@@ -453,7 +472,16 @@ void fit_kernel(const FitArgs a) {
       const double r = ei - group_sum<SP>(part);
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], Iv[cI], r);
+    };
+    // two points per trip: the compensated sums then alternate between two
+    // registers instead of being copied back every point
+    int64_t k = fl;
+    for (; k + SF < F; k += 2 * SF) {
+      const double w0 = om[k], e0 = epi[k], w1 = om[k + SF], e1 = epi[k + SF];
+      step(w0, e0);
+      step(w1, e1);
     }
+    if (k < F) step(om[k], epi[k]);
   }
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL);
@@ -463,7 +491,9 @@ void fit_kernel(const FitArgs a) {
     double dz[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) dz[i] = __builtin_fma(gv[i], invd_r[i], -damping * zt[i]);
-    chol_solve<N>(G, uinv_r, dz);
+    double Af[S::NT], uf[N];
+    unpark<N>(lds_all, WAVE / SL, grp, Af, uf);
+    chol_solve<N>(Af, uf, dz);
 #pragma unroll
     for (int i = 0; i < N; ++i) zt[i] += dz[i];
   } else {
@@ -561,7 +591,9 @@ void fit_kernel(const FitArgs a) {
       mt[cI] = s * gw[cI] * invd_own[cI];
     }
     if constexpr (SP == 1) {
-      chol_solve<N>(G, uinv_r, mt);
+      double Af[S::NT], uf[N];
+      unpark<N>(lds_all, WAVE / SL, grp, Af, uf);
+      chol_solve<N>(Af, uf, mt);
     } else {
       const LdsLayout<N> lay(L);
       double *A = lay.A, *uinv = lay.uinv, *vw = lay.vw;
