@@ -220,8 +220,9 @@ def main():
     tfile = os.path.join(ROOT, "profiles", "fit_eval_N8_mixed_traffic.json")
     if args.workload == "mixed" and os.path.exists(tfile):
         rec = json.load(open(tfile))
-        if rec.get("source_sha256_16") == kernel_source_hash():
-            traffic = rec.get("bytes_per_launch")
+        split = str(plan.info()[0]["freq_split"])
+        if rec.get("source_sha256_16") == kernel_source_hash() and split in rec.get("by_freq_split", {}):
+            traffic = rec["by_freq_split"][split]["bytes"]
 
     line = {
         "metric": "Debye-fit cost evals/s (fwd, fwd+adjoint), rel err <=1e-10 vs FP64 oracle",

@@ -414,7 +414,9 @@ int debye_plan_autotune(debye_plan *p, const debye_batch *b, const double *log10
       float ms = 0;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (e != hipSuccess) return cleanup(hip_fail(e, "autotune launch"));
-      if (ms < best_ms) {
+      // a wider split must win clearly (3 %): it costs reductions, and timing
+      // noise should not flip the schedule between runs
+      if (ms < 0.97f * best_ms) {
         best_ms = ms;
         best_sf = sf;
       }
