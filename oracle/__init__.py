@@ -64,6 +64,11 @@ def lib():
         L.orc_fit_from_basis.argtypes = [C.c_int64, _d, _d, _d, _d, C.c_int32, C.c_double, C.c_uint32, C.c_int32,
                                          _d]
         L.orc_fit_cond.argtypes = [C.c_int64, _d, _d, _d, C.c_int32, _d, C.c_double, C.c_uint32, _d, _d, _d]
+        L.orc_de_init.argtypes = [C.c_int32, _i64, _i32, C.c_int64, _d, _d, C.c_uint64, _d, _d, _d, _i64]
+        L.orc_de_trial.argtypes = [C.c_int32, _i64, _i32, C.c_int64, _d, _d, C.c_double, C.c_double, C.c_double,
+                                   C.c_uint64, C.c_int32, _d, _d]
+        L.orc_de_select.argtypes = [C.c_int32, _i64, _i32, C.c_int64, C.c_int32, _d, _d, _d, _d, _d, _d, _i64, _d,
+                                    C.c_int64]
         L.orc_fit_cond_batch.argtypes = [C.c_int32, _i64, _i64, _i32, _d, _d, _d, _d, C.c_int64, C.c_double,
                                          C.c_uint32, _d, C.c_int]
         L.orc_num_threads.restype = C.c_int
@@ -333,6 +338,61 @@ def pso_run(b: Batch, lb, ub, iters, inertia=0.7, c1=1.5, c2=1.5, seed=0, ld=Non
         cost = fit_eval(b, sw.x, damping, flags, nthreads=nthreads)[0]
     pso_step(b.cand_off, b.n_poles, lb, ub, inertia, c1, c2, seed, iters + 1, False, cost, sw)
     return sw
+
+
+class Population:
+    """Differential-evolution state in the library's layout (rows of stride ld)."""
+
+    def __init__(self, P, M, ld, hist_len=0):
+        self.x = np.zeros((P, ld))
+        self.u = np.zeros((P, ld))
+        self.fit = np.zeros(P)
+        self.best_x = np.zeros((M, ld))
+        self.best_cost = np.zeros(M)
+        self.best_idx = np.zeros(M, dtype=np.int64)
+        self.history = np.full((M, max(hist_len, 1)), np.nan)
+
+
+def de_init(cand_off, n_poles, lb, ub, seed, pop: Population):
+    cand_off = np.ascontiguousarray(cand_off, np.int64)
+    n_poles = np.ascontiguousarray(n_poles, np.int32)
+    lib().orc_de_init(len(n_poles), _p(cand_off, _i64), _p(n_poles, _i32), pop.x.shape[1], _p(_f64(lb), _d),
+                      _p(_f64(ub), _d), seed, _p(pop.x, _d), _p(pop.fit, _d), _p(pop.best_cost, _d),
+                      _p(pop.best_idx, _i64))
+
+
+def de_trial(cand_off, n_poles, lb, ub, f_lo, f_hi, cr, seed, t, pop: Population):
+    """Trial vectors of generation t into pop.u (DE/rand/1/bin)."""
+    cand_off = np.ascontiguousarray(cand_off, np.int64)
+    n_poles = np.ascontiguousarray(n_poles, np.int32)
+    rc = lib().orc_de_trial(len(n_poles), _p(cand_off, _i64), _p(n_poles, _i32), pop.x.shape[1], _p(_f64(lb), _d),
+                            _p(_f64(ub), _d), f_lo, f_hi, cr, seed, t, _p(pop.x, _d), _p(pop.u, _d))
+    if rc:
+        raise ValueError("differential evolution needs at least 4 members per non-empty population")
+
+
+def de_select(cand_off, n_poles, t, u, cost_u, pop: Population):
+    cand_off = np.ascontiguousarray(cand_off, np.int64)
+    n_poles = np.ascontiguousarray(n_poles, np.int32)
+    u = _f64(u)
+    cost_u = _f64(cost_u)
+    lib().orc_de_select(len(n_poles), _p(cand_off, _i64), _p(n_poles, _i32), pop.x.shape[1], t, _p(u, _d),
+                        _p(cost_u, _d), _p(pop.x, _d), _p(pop.fit, _d), _p(pop.best_x, _d), _p(pop.best_cost, _d),
+                        _p(pop.best_idx, _i64), _p(pop.history, _d), pop.history.shape[1])
+
+
+def de_run(b: Batch, lb, ub, iters, f_lo=0.5, f_hi=1.0, cr=0.7, seed=0, ld=None, damping=1e-8, flags=0,
+           nthreads=0):
+    """Whole DE fit: init, evaluate the initial population (generation 0),
+    then `iters` x (trials, evaluate, select).  P*(iters+1) evaluations."""
+    ld = ld or int(b.n_poles.max())
+    pop = Population(b.P, b.M, ld, iters + 1)
+    de_init(b.cand_off, b.n_poles, lb, ub, seed, pop)
+    de_select(b.cand_off, b.n_poles, 0, pop.x.copy(), fit_eval(b, pop.x, damping, flags, nthreads=nthreads)[0], pop)
+    for t in range(1, iters + 1):
+        de_trial(b.cand_off, b.n_poles, lb, ub, f_lo, f_hi, cr, seed, t, pop)
+        de_select(b.cand_off, b.n_poles, t, pop.u, fit_eval(b, pop.u, damping, flags, nthreads=nthreads)[0], pop)
+    return pop
 
 
 def lbfgs(b: Batch, theta, lb, ub, steps=50, mem=10, max_trials=30, c1=1e-4, damping=1e-8, flags=0,

@@ -113,7 +113,8 @@ void philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]
 inline double u01(uint64_t r) { return (double)(r >> 11) * 0x1.0p-53; }
 
 // Stream identifiers used as the last counter word.
-enum { STREAM_PSO_INIT = 0, STREAM_PSO_STEP = 1, STREAM_NOISE = 2 };
+enum { STREAM_PSO_INIT = 0, STREAM_PSO_STEP = 1, STREAM_NOISE = 2, STREAM_DE_INIT = 3, STREAM_DE_TRIAL = 4,
+       STREAM_DE_CROSS = 5, STREAM_DE_F = 6 };
 
 // ---------------------------------------------------------------------------
 // Material models (relaxation functions).  eps = eps' - j eps'' (Eq. 1).
@@ -898,6 +899,130 @@ int orc_pso_step(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int
         x[c * ld + d] = xn;
       }
     }
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Differential evolution, DE/rand/1/bin (Storn & Price 1997), one population
+// per material over log10 tau, generation-synchronous: every trial of a
+// generation is built from the population as it stood at the start of it,
+// all trials are evaluated together, then each member is replaced by its
+// trial if the trial's cost is not larger.  Random numbers from Philox with
+// key (seed, material):
+//   initial member p, coordinate d:  ctr (d, p, 0, STREAM_DE_INIT), word 0
+//   trial of member i, generation t: ctr (i, t, 0, STREAM_DE_TRIAL), words
+//       0..2 -> the three donors, word 3 -> the coordinate always crossed
+//   coordinate d of that trial:      ctr (i, t, d + 1, STREAM_DE_CROSS),
+//       word 0 -> crossover test, word 1 -> redraw when out of the box
+//   scale factor of generation t:    ctr (0, t, 0, STREAM_DE_F), word 0,
+//       F = F_lo + (F_hi - F_lo) u  (dither per generation)
+// An integer in [0, K) is ((w >> 32) * K) >> 32 (exact, no rounding).
+// Donors r1, r2, r3 are distinct and differ from i: drawn from the remaining
+// P-1, P-2, P-3 indices in increasing order (needs P >= 4).  A trial
+// coordinate outside [lb, ub] is redrawn uniformly in the box.
+// ---------------------------------------------------------------------------
+inline int64_t draw_below(uint64_t w, int64_t K) { return (int64_t)(((w >> 32) * (uint64_t)K) >> 32); }
+
+// the k-th (0-based) index of 0..P-1 that is not in `taken` (sorted, n entries)
+inline int64_t skip_taken(int64_t k, const int64_t *taken, int n) {
+  for (int j = 0; j < n; ++j)
+    if (k >= taken[j]) ++k;
+  return k;
+}
+
+void de_donors(uint64_t seed, int64_t m, int64_t i, int32_t t, int64_t P, int64_t r[3], uint64_t *jrand_w) {
+  uint64_t ctr[4] = {(uint64_t)i, (uint64_t)t, 0, STREAM_DE_TRIAL}, key[2] = {seed, (uint64_t)m}, w[4];
+  philox4x64_10(ctr, key, w);
+  int64_t taken[3] = {i, 0, 0};
+  r[0] = skip_taken(draw_below(w[0], P - 1), taken, 1);
+  taken[1] = r[0];
+  std::sort(taken, taken + 2);
+  r[1] = skip_taken(draw_below(w[1], P - 2), taken, 2);
+  taken[2] = r[1];
+  std::sort(taken, taken + 3);
+  r[2] = skip_taken(draw_below(w[2], P - 3), taken, 3);
+  *jrand_w = w[3];
+}
+
+int orc_de_init(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int64_t ld, const double *lb,
+                const double *ub, uint64_t seed, double *x, double *fit, double *best_cost, int64_t *best_idx) {
+  for (int32_t m = 0; m < M; ++m) {
+    for (int64_t c = cand_off[m]; c < cand_off[m + 1]; ++c) {
+      const int64_t p = c - cand_off[m];
+      for (int d = 0; d < n_poles[m]; ++d) {
+        uint64_t ctr[4] = {(uint64_t)d, (uint64_t)p, 0, STREAM_DE_INIT}, key[2] = {seed, (uint64_t)m}, w[4];
+        philox4x64_10(ctr, key, w);
+        x[c * ld + d] = lb[m] + (ub[m] - lb[m]) * u01(w[0]);
+      }
+      fit[c] = INFINITY;
+    }
+    best_cost[m] = INFINITY;
+    best_idx[m] = -1;
+  }
+  return 0;
+}
+
+// trial vectors of generation t (t >= 1) from population x
+int orc_de_trial(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int64_t ld, const double *lb,
+                 const double *ub, double f_lo, double f_hi, double cr, uint64_t seed, int32_t t, const double *x,
+                 double *u) {
+  for (int32_t m = 0; m < M; ++m) {
+    const int64_t c0 = cand_off[m], P = cand_off[m + 1] - c0;
+    const int N = n_poles[m];
+    if (P == 0) continue;
+    if (P < 4) return -1;
+    uint64_t fctr[4] = {0, (uint64_t)t, 0, STREAM_DE_F}, key[2] = {seed, (uint64_t)m}, fw[4];
+    philox4x64_10(fctr, key, fw);
+    const double F = f_lo + (f_hi - f_lo) * u01(fw[0]);
+    const double lo = lb[m], span = ub[m] - lb[m];
+    for (int64_t i = 0; i < P; ++i) {
+      int64_t r[3];
+      uint64_t jw;
+      de_donors(seed, m, i, t, P, r, &jw);
+      const int64_t jrand = draw_below(jw, N);
+      const double *xi = x + (c0 + i) * ld;
+      const double *a = x + (c0 + r[0]) * ld, *b = x + (c0 + r[1]) * ld, *c = x + (c0 + r[2]) * ld;
+      for (int d = 0; d < N; ++d) {
+        uint64_t ctr[4] = {(uint64_t)i, (uint64_t)t, (uint64_t)d + 1, STREAM_DE_CROSS}, w[4];
+        philox4x64_10(ctr, key, w);
+        double v = xi[d];
+        if (u01(w[0]) < cr || d == jrand) {
+          const double diff = b[d] - c[d];
+          const double step = F * diff;
+          v = a[d] + step;
+          if (!(v >= lo && v <= ub[m])) v = lo + span * u01(w[1]);
+        }
+        u[(c0 + i) * ld + d] = v;
+      }
+    }
+  }
+  return 0;
+}
+
+// greedy selection of generation t (t = 0: the initial population itself, u = x)
+int orc_de_select(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int64_t ld, int32_t t,
+                  const double *u, const double *cost_u, double *x, double *fit, double *best_x, double *best_cost,
+                  int64_t *best_idx, double *history, int64_t hist_ld) {
+  for (int32_t m = 0; m < M; ++m) {
+    const int64_t c0 = cand_off[m], c1 = cand_off[m + 1];
+    const int N = n_poles[m];
+    for (int64_t c = c0; c < c1; ++c)
+      if (cost_u[c] <= fit[c]) {   // NaN never replaces
+        fit[c] = cost_u[c];
+        for (int d = 0; d < N; ++d) x[c * ld + d] = u[c * ld + d];
+      }
+    int64_t best = -1;
+    for (int64_t c = c0; c < c1; ++c) {
+      if (std::isnan(fit[c])) continue;
+      if (best < 0 || fit[c] < fit[best]) best = c;
+    }
+    if (best >= 0 && fit[best] < best_cost[m]) {
+      best_cost[m] = fit[best];
+      best_idx[m] = best - c0;
+      for (int d = 0; d < N; ++d) best_x[m * ld + d] = x[best * ld + d];
+    }
+    if (history) history[m * hist_ld + t] = best_cost[m];
   }
   return 0;
 }
