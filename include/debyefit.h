@@ -270,6 +270,66 @@ int debye_pso_run(const debye_plan *plan, const debye_batch *b, int64_t ld, cons
                   int32_t use_graph, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Differential evolution (the paper's DE-DLS alternative, Sec. III-A; Storn &
+ * Price 1997, strategy rand/1/bin), one population per material over log10
+ * tau: the candidates of material m are its members.  Generation-synchronous:
+ * every trial of generation t >= 1 is built from the population as it stood
+ * before the generation, the trials are evaluated together, and member i is
+ * replaced by its trial when cost(trial) <= cost(member) (a NaN cost never
+ * replaces).  Trial i: donors r1, r2, r3 distinct and != i, drawn uniformly;
+ * mutant x_r1 + F (x_r2 - x_r3) (each operation rounded separately) with
+ * F = f_lo + (f_hi - f_lo) u drawn once per material and generation
+ * (dither); binomial crossover with rate cr and one forced coordinate; a
+ * crossed coordinate outside [lb[m], ub[m]] is redrawn uniformly in the box.
+ * A population of fewer than 4 members is not evolved (trial = target).
+ * Random numbers: Philox4x64-10, key (seed, material); the counters are
+ * listed in the library source.  Fed the same costs, runs are bit-identical
+ * to the CPU reference.
+ *   debye_de_init:   x uniform in the box; fit = +inf; best_cost = +inf,
+ *                    best_idx = -1.
+ *   debye_de_trial:  u = trials of generation t from x.
+ *   debye_de_select: greedy replacement with cost_u = cost(u); then the
+ *                    material's best (lowest index among equal costs) if it
+ *                    improves; history[m * hist_ld + t] = best cost (may be
+ *                    NULL).  Generation 0 is the initial population: call it
+ *                    with u = x and cost_u = cost(x).
+ *   debye_de_run:    init, generation 0, then `iters` generations, each
+ *                    [trial -> debye_fit_eval -> select]; with use_graph the
+ *                    generation is captured once into a HIP graph and
+ *                    replayed (bit-identical).  history needs
+ *                    hist_ld >= iters + 1.  Calls with one plan must not overlap.
+ * All pointers are device pointers; rows have stride ld >= max_poles.
+ * ------------------------------------------------------------------------ */
+typedef struct debye_de_params {
+  double f_lo, f_hi, cr;   /* 0 <= f_lo <= f_hi <= 2, 0 <= cr <= 1 */
+  uint64_t seed;
+} debye_de_params;
+
+int debye_de_init(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_de_params p,
+                  double *x, double *fit, double *best_cost, int64_t *best_idx, hipStream_t stream);
+int debye_de_trial(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_de_params p,
+                   int32_t t, const double *x, double *u, hipStream_t stream);
+int debye_de_select(const debye_batch *b, int64_t ld, int32_t t, const double *u, const double *cost_u, double *x,
+                    double *fit, double *best_x, double *best_cost, int64_t *best_idx, double *history,
+                    int64_t hist_ld, hipStream_t stream);
+
+typedef struct debye_population {
+  double *x, *u;          /* [n_cand][ld] members and trials */
+  double *fit;            /* [n_cand] cost of the members */
+  double *cost;           /* [n_cand] cost of the trials (workspace/output) */
+  double *best_x;         /* [M][ld] */
+  double *best_cost;      /* [M] */
+  int64_t *best_idx;      /* [M] */
+  double *history;        /* [M][hist_ld] or NULL */
+  int64_t hist_ld;
+  int8_t *status;         /* [n_cand] or NULL */
+} debye_population;
+
+int debye_de_run(const debye_plan *plan, const debye_batch *b, int64_t ld, const double *lb, const double *ub,
+                 debye_de_params p, int32_t iters, double damping, uint32_t flags, const debye_population *pop,
+                 int32_t use_graph, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Gradient polish: L-BFGS (Liu & Nocedal 1989; two-loop recursion, memory
  * `mem`), Armijo backtracking alpha = 1, 1/2, ... (max_trials, constant c1),
  * on one candidate per material, theta [M][ld] in place, inside the search box

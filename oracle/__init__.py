@@ -362,13 +362,12 @@ def de_init(cand_off, n_poles, lb, ub, seed, pop: Population):
 
 
 def de_trial(cand_off, n_poles, lb, ub, f_lo, f_hi, cr, seed, t, pop: Population):
-    """Trial vectors of generation t into pop.u (DE/rand/1/bin)."""
+    """Trial vectors of generation t into pop.u (DE/rand/1/bin); a population
+    of fewer than 4 members gets its targets as trials."""
     cand_off = np.ascontiguousarray(cand_off, np.int64)
     n_poles = np.ascontiguousarray(n_poles, np.int32)
-    rc = lib().orc_de_trial(len(n_poles), _p(cand_off, _i64), _p(n_poles, _i32), pop.x.shape[1], _p(_f64(lb), _d),
-                            _p(_f64(ub), _d), f_lo, f_hi, cr, seed, t, _p(pop.x, _d), _p(pop.u, _d))
-    if rc:
-        raise ValueError("differential evolution needs at least 4 members per non-empty population")
+    lib().orc_de_trial(len(n_poles), _p(cand_off, _i64), _p(n_poles, _i32), pop.x.shape[1], _p(_f64(lb), _d),
+                       _p(_f64(ub), _d), f_lo, f_hi, cr, seed, t, _p(pop.x, _d), _p(pop.u, _d))
 
 
 def de_select(cand_off, n_poles, t, u, cost_u, pop: Population):

@@ -919,8 +919,9 @@ int orc_pso_step(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int
 //       F = F_lo + (F_hi - F_lo) u  (dither per generation)
 // An integer in [0, K) is ((w >> 32) * K) >> 32 (exact, no rounding).
 // Donors r1, r2, r3 are distinct and differ from i: drawn from the remaining
-// P-1, P-2, P-3 indices in increasing order (needs P >= 4).  A trial
-// coordinate outside [lb, ub] is redrawn uniformly in the box.
+// P-1, P-2, P-3 indices in increasing order.  A population of fewer than four
+// members is not evolved (its trials are the targets).  A trial coordinate
+// outside [lb, ub] is redrawn uniformly in the box.
 // ---------------------------------------------------------------------------
 inline int64_t draw_below(uint64_t w, int64_t K) { return (int64_t)(((w >> 32) * (uint64_t)K) >> 32); }
 
@@ -971,7 +972,11 @@ int orc_de_trial(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int
     const int64_t c0 = cand_off[m], P = cand_off[m + 1] - c0;
     const int N = n_poles[m];
     if (P == 0) continue;
-    if (P < 4) return -1;
+    if (P < 4) {   // too few members for three distinct donors: the trial is the target
+      for (int64_t c = c0; c < c0 + P; ++c)
+        for (int d = 0; d < N; ++d) u[c * ld + d] = x[c * ld + d];
+      continue;
+    }
     uint64_t fctr[4] = {0, (uint64_t)t, 0, STREAM_DE_F}, key[2] = {seed, (uint64_t)m}, fw[4];
     philox4x64_10(fctr, key, fw);
     const double F = f_lo + (f_hi - f_lo) * u01(fw[0]);

@@ -34,7 +34,8 @@ EXPORTED = ["debye_plan_create", "debye_plan_destroy", "debye_plan_set_freq_spli
             "debye_plan_info",
             "debye_last_error", "debye_version", "debye_basis", "debye_fit_eval", "debye_fit_eval_grad",
             "debye_material_eval", "debye_material_vjp", "debye_pso_init", "debye_pso_step",
-            "debye_pso_run", "debye_lbfgs_polish"]
+            "debye_pso_run", "debye_de_init", "debye_de_trial", "debye_de_select", "debye_de_run",
+            "debye_lbfgs_polish"]
 
 
 class DebyeError(RuntimeError):
@@ -57,6 +58,16 @@ class _CSwarm(C.Structure):
     _fields_ = [("x", C.c_void_p), ("v", C.c_void_p), ("pbest_x", C.c_void_p), ("pbest_cost", C.c_void_p),
                 ("gbest_x", C.c_void_p), ("gbest_cost", C.c_void_p), ("gbest_idx", C.c_void_p),
                 ("history", C.c_void_p), ("hist_ld", C.c_int64), ("cost", C.c_void_p), ("status", C.c_void_p)]
+
+
+class _CDe(C.Structure):
+    _fields_ = [("f_lo", C.c_double), ("f_hi", C.c_double), ("cr", C.c_double), ("seed", C.c_uint64)]
+
+
+class _CPop(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("u", C.c_void_p), ("fit", C.c_void_p), ("cost", C.c_void_p),
+                ("best_x", C.c_void_p), ("best_cost", C.c_void_p), ("best_idx", C.c_void_p),
+                ("history", C.c_void_p), ("hist_ld", C.c_int64), ("status", C.c_void_p)]
 
 
 class _CLbfgs(C.Structure):
@@ -93,6 +104,10 @@ def lib():
                                  _vp, _vp, _vp, i64, _vp]
     L.debye_pso_run.argtypes = [_vp, C.POINTER(_CBatch), i64, _vp, _vp, _CPso, i32, dbl, u32, C.POINTER(_CSwarm), i32,
                                 _vp]
+    L.debye_de_init.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CDe, _vp, _vp, _vp, _vp, _vp]
+    L.debye_de_trial.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CDe, i32, _vp, _vp, _vp]
+    L.debye_de_select.argtypes = [C.POINTER(_CBatch), i64, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, i64, _vp]
+    L.debye_de_run.argtypes = [_vp, C.POINTER(_CBatch), i64, _vp, _vp, _CDe, i32, dbl, u32, C.POINTER(_CPop), i32, _vp]
     L.debye_lbfgs_polish.argtypes = [C.POINTER(_CBatch), _vp, _vp, _vp, i64, _vp, _vp, dbl, u32, _CLbfgs, _vp, _vp]
     _lib = L
     return L
@@ -301,6 +316,61 @@ def pso_run(plan: Plan, b: Batch, lb, ub, sw: Swarm, iters, inertia=0.7, c1=1.5,
                                _CPso(inertia, c1, c2, seed), int(iters), float(damping), flags, C.byref(cs),
                                1 if use_graph else 0, _stream()))
     return cost
+
+
+@dataclasses.dataclass
+class Population:
+    """Differential-evolution state (see debye_population)."""
+    x: torch.Tensor
+    u: torch.Tensor
+    fit: torch.Tensor
+    cost: torch.Tensor
+    best_x: torch.Tensor
+    best_cost: torch.Tensor
+    best_idx: torch.Tensor
+    history: torch.Tensor
+
+    @staticmethod
+    def empty(P, M, ld, hist_len, device="cuda"):
+        f = dict(dtype=torch.float64, device=device)
+        return Population(torch.zeros((P, ld), **f), torch.zeros((P, ld), **f), torch.zeros(P, **f),
+                          torch.zeros(P, **f), torch.zeros((M, ld), **f), torch.zeros(M, **f),
+                          torch.zeros(M, dtype=torch.int64, device=device),
+                          torch.full((M, max(hist_len, 1)), float("nan"), **f))
+
+
+def de_init(b: Batch, lb, ub, pop: Population, f_lo=0.5, f_hi=1.0, cr=0.7, seed=0):
+    cb = b.cstruct()
+    _check(lib().debye_de_init(C.byref(cb), pop.x.shape[1], _ptr(lb), _ptr(ub), _CDe(f_lo, f_hi, cr, seed),
+                               _ptr(pop.x), _ptr(pop.fit), _ptr(pop.best_cost), _ptr(pop.best_idx), _stream()))
+
+
+def de_trial(b: Batch, lb, ub, pop: Population, t, f_lo=0.5, f_hi=1.0, cr=0.7, seed=0):
+    """pop.u = trial vectors of generation t (debye_de_trial)."""
+    cb = b.cstruct()
+    _check(lib().debye_de_trial(C.byref(cb), pop.x.shape[1], _ptr(lb), _ptr(ub), _CDe(f_lo, f_hi, cr, seed), int(t),
+                                _ptr(pop.x), _ptr(pop.u), _stream()))
+
+
+def de_select(b: Batch, pop: Population, t, u, cost_u, history=True):
+    """Greedy replacement by the trials u with costs cost_u (debye_de_select)."""
+    cb = b.cstruct()
+    h = pop.history if history else None
+    _check(lib().debye_de_select(C.byref(cb), pop.x.shape[1], int(t), _ptr(u), _ptr(cost_u), _ptr(pop.x),
+                                 _ptr(pop.fit), _ptr(pop.best_x), _ptr(pop.best_cost), _ptr(pop.best_idx), _ptr(h),
+                                 pop.history.shape[1], _stream()))
+
+
+def de_run(plan: Plan, b: Batch, lb, ub, pop: Population, iters, f_lo=0.5, f_hi=1.0, cr=0.7, seed=0,
+           damping=DEFAULT_DAMPING, flags=0, use_graph=True, status=None):
+    """A whole differential-evolution fit (debye_de_run)."""
+    cp = _CPop(pop.x.data_ptr(), pop.u.data_ptr(), pop.fit.data_ptr(), pop.cost.data_ptr(), pop.best_x.data_ptr(),
+               pop.best_cost.data_ptr(), pop.best_idx.data_ptr(), pop.history.data_ptr(), pop.history.shape[1],
+               None if status is None else status.data_ptr())
+    cb = b.cstruct()
+    _check(lib().debye_de_run(plan.handle, C.byref(cb), pop.x.shape[1], _ptr(lb), _ptr(ub),
+                              _CDe(f_lo, f_hi, cr, seed), int(iters), float(damping), flags, C.byref(cp),
+                              1 if use_graph else 0, _stream()))
 
 
 def lbfgs_polish(b1: Batch, theta, lb, ub, steps=50, mem=10, max_trials=30, c1=1e-4, damping=DEFAULT_DAMPING,

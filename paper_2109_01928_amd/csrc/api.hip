@@ -71,7 +71,7 @@ struct SwarmGraph {
 };
 
 struct debye_plan {
-  SwarmGraph graph;
+  SwarmGraph graph, de_graph;
   int32_t M = 0, max_poles = 0;
   int64_t n_freq = 0, n_cand = 0;
   std::vector<int64_t> f_off, cand_off;
@@ -226,6 +226,79 @@ dfit::FitArgs fit_args(const debye_plan *p, const Bucket &bk, const debye_batch 
   return a;
 }
 
+// ---- captured optimiser iterations ----
+void graph_destroy(SwarmGraph &g) {
+  if (g.stream) (void)hipStreamSynchronize(g.stream);
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.ev_in) (void)hipEventDestroy(g.ev_in);
+  if (g.ev_out) (void)hipEventDestroy(g.ev_out);
+  if (g.stream) (void)hipStreamDestroy(g.stream);
+  if (g.counter) (void)hipFree(g.counter);
+  g = SwarmGraph();
+}
+
+// move the work onto the graph's own stream (ordered after the caller's)
+int graph_enter(SwarmGraph &g, hipStream_t caller) {
+  if (!g.stream) {
+    CHECK_HIP(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking), "graph stream");
+    CHECK_HIP(hipEventCreateWithFlags(&g.ev_in, hipEventDisableTiming), "graph event");
+    CHECK_HIP(hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming), "graph event");
+    if (hipMalloc(&g.counter, sizeof(int32_t)) != hipSuccess) return fail(DEBYE_ENOMEM, "graph counter");
+  }
+  CHECK_HIP(hipEventRecord(g.ev_in, caller), "event");
+  CHECK_HIP(hipStreamWaitEvent(g.stream, g.ev_in, 0), "event wait");
+  return DEBYE_OK;
+}
+
+int graph_leave(SwarmGraph &g, hipStream_t caller) {
+  CHECK_HIP(hipEventRecord(g.ev_out, g.stream), "event");
+  CHECK_HIP(hipStreamWaitEvent(caller, g.ev_out, 0), "event wait");
+  return DEBYE_OK;
+}
+
+// Replay `iters` iterations of body(stream, counter) from one captured graph;
+// the device counter holds the iteration number, t0 for the first replay, and
+// the body ends with its increment.  The capture is reused while `key` (every
+// argument the captured nodes depend on) is unchanged.
+template <class BODY>
+int graph_replay(SwarmGraph &g, const std::vector<unsigned char> &key, int32_t t0, int32_t iters, BODY &&body) {
+  if (iters <= 0) return DEBYE_OK;
+  hipStream_t s = g.stream;
+  if (!g.exec || g.key != key) {
+    if (g.exec) {
+      (void)hipGraphExecDestroy(g.exec);
+      g.exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    const int rc = body(s, g.counter);
+    const hipError_t e2 = rc ? hipSuccess : dfit::launch_tick(g.counter, s);
+    const hipError_t e3 = hipStreamEndCapture(s, &graph);
+    if (rc || e2 != hipSuccess || e3 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc ? rc : hip_fail(e2 != hipSuccess ? e2 : e3, "graph capture");
+    }
+    const hipError_t e4 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e4 != hipSuccess) {
+      g.exec = nullptr;
+      return hip_fail(e4, "graph instantiate");
+    }
+    g.key = key;
+  }
+  CHECK_HIP(dfit::launch_set_counter(g.counter, t0, s), "counter");
+  for (int32_t t = 0; t < iters; ++t) CHECK_HIP(hipGraphLaunch(g.exec, s), "graph launch");
+  return DEBYE_OK;
+}
+
+struct KeyBytes {
+  std::vector<unsigned char> v;
+  template <class T> void put(const T &x) {
+    const unsigned char *c = (const unsigned char *)&x;
+    v.insert(v.end(), c, c + sizeof(T));
+  }
+};
+
 // Enqueue launch(bucket, stream) for every non-empty bucket.  With several
 // buckets they fork from `stream` onto the plan's side streams and join back,
 // so different pole counts overlap on the GPU; under stream capture the fork
@@ -344,12 +417,8 @@ int debye_plan_create(const debye_batch *shape, const int64_t *f_off_host, const
 
 int debye_plan_destroy(debye_plan *p) {
   if (!p) return DEBYE_OK;
-  if (p->graph.stream) (void)hipStreamSynchronize(p->graph.stream);
-  if (p->graph.exec) (void)hipGraphExecDestroy(p->graph.exec);
-  if (p->graph.ev_in) (void)hipEventDestroy(p->graph.ev_in);
-  if (p->graph.ev_out) (void)hipEventDestroy(p->graph.ev_out);
-  if (p->graph.stream) (void)hipStreamDestroy(p->graph.stream);
-  if (p->graph.counter) (void)hipFree(p->graph.counter);
+  graph_destroy(p->graph);
+  graph_destroy(p->de_graph);
   for (hipStream_t st : p->side)
     if (st) (void)hipStreamSynchronize(st);
   for (auto &b : p->buckets) free_bucket(b);
@@ -659,14 +728,7 @@ int debye_pso_run(const debye_plan *pc, const debye_batch *b, int64_t ld, const 
   SwarmGraph &g = plan->graph;
   hipStream_t s = stream;
   if (use_graph) {
-    if (!g.stream) {
-      CHECK_HIP(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking), "graph stream");
-      CHECK_HIP(hipEventCreateWithFlags(&g.ev_in, hipEventDisableTiming), "graph event");
-      CHECK_HIP(hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming), "graph event");
-      if (hipMalloc(&g.counter, sizeof(int32_t)) != hipSuccess) return fail(DEBYE_ENOMEM, "graph counter");
-    }
-    CHECK_HIP(hipEventRecord(g.ev_in, stream), "event");
-    CHECK_HIP(hipStreamWaitEvent(g.stream, g.ev_in, 0), "event wait");
+    if ((rc = graph_enter(g, stream))) return rc;
     s = g.stream;
   }
   dfit::PsoArgs a0 = pso_args(b, ld, lb, ub, p, 0, 0, sw);
@@ -678,55 +740,170 @@ int debye_pso_run(const debye_plan *pc, const debye_batch *b, int64_t ld, const 
       if ((rc = debye_fit_eval(plan, b, sw->x, ld, damping, flags, sw->cost, nullptr, nullptr, sw->status, s)))
         return rc;
     }
-  } else if (iters > 0) {
-    // key: every argument the captured nodes depend on
-    std::vector<unsigned char> key;
-    auto put = [&](const void *q, size_t n) {
-      const unsigned char *c = (const unsigned char *)q;
-      key.insert(key.end(), c, c + n);
-    };
-    put(b, sizeof *b);
-    put(&ld, sizeof ld);
-    put(&lb, sizeof lb);
-    put(&ub, sizeof ub);
-    put(&p, sizeof p);
-    put(&damping, sizeof damping);
-    put(&flags, sizeof flags);
-    put(sw, sizeof *sw);
-    if (!g.exec || g.key != key) {
-      if (g.exec) {
-        (void)hipGraphExecDestroy(g.exec);
-        g.exec = nullptr;
-      }
-      hipGraph_t graph = nullptr;
-      CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+  } else {
+    KeyBytes key;
+    key.put(*b);
+    key.put(ld);
+    key.put(lb);
+    key.put(ub);
+    key.put(p);
+    key.put(damping);
+    key.put(flags);
+    key.put(*sw);
+    rc = graph_replay(g, key.v, 1, iters, [&](hipStream_t gs, int32_t *counter) -> int {
       dfit::PsoArgs a = pso_args(b, ld, lb, ub, p, 0, 1, sw);
-      a.t_dev = g.counter;
-      hipError_t e1 = dfit::launch_pso_step(a, s);
-      int rc2 = debye_fit_eval(plan, b, sw->x, ld, damping, flags, sw->cost, nullptr, nullptr, sw->status, s);
-      hipError_t e2 = dfit::launch_tick(g.counter, s);
-      hipError_t e3 = hipStreamEndCapture(s, &graph);
-      if (e1 != hipSuccess || rc2 || e2 != hipSuccess || e3 != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc2 ? rc2 : hip_fail(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3), "swarm graph capture");
-      }
-      hipError_t e4 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e4 != hipSuccess) {
-        g.exec = nullptr;
-        return hip_fail(e4, "swarm graph instantiate");
-      }
-      g.key = key;
-    }
-    CHECK_HIP(dfit::launch_set_counter(g.counter, 1, s), "counter");
-    for (int32_t t = 1; t <= iters; ++t) CHECK_HIP(hipGraphLaunch(g.exec, s), "swarm graph launch");
+      a.t_dev = counter;
+      CHECK_HIP(dfit::launch_pso_step(a, gs), "swarm step");
+      return debye_fit_eval(plan, b, sw->x, ld, damping, flags, sw->cost, nullptr, nullptr, sw->status, gs);
+    });
+    if (rc) return rc;
   }
   CHECK_HIP(dfit::launch_pso_step(pso_args(b, ld, lb, ub, p, iters + 1, 0, sw), s), "final bests");
-  if (use_graph) {
-    CHECK_HIP(hipEventRecord(g.ev_out, s), "event");
-    CHECK_HIP(hipStreamWaitEvent(stream, g.ev_out, 0), "event wait");
-  }
+  if (use_graph) return graph_leave(g, stream);
   return DEBYE_OK;
+}
+
+// ---- differential evolution ----
+static int de_check(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_de_params p) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (ld < b->max_poles) return fail(DEBYE_ERANGE, "ld < max_poles");
+  if (!lb || !ub) return fail(DEBYE_EINVAL, "lb/ub are NULL");
+  if (!(p.f_lo >= 0.0 && p.f_lo <= p.f_hi && p.f_hi <= 2.0) || !(p.cr >= 0.0 && p.cr <= 1.0))
+    return fail(DEBYE_ERANGE, "DE parameters out of range (0 <= f_lo <= f_hi <= 2, 0 <= cr <= 1)");
+  return DEBYE_OK;
+}
+
+static dfit::DeArgs de_args(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_de_params p,
+                            int32_t t) {
+  dfit::DeArgs a{};
+  a.M = b->n_mat;
+  a.cand_off = b->cand_off;
+  a.n_poles = b->n_poles;
+  a.ld = ld;
+  a.lb = lb;
+  a.ub = ub;
+  a.f_lo = p.f_lo;
+  a.f_hi = p.f_hi;
+  a.cr = p.cr;
+  a.seed = p.seed;
+  a.t = t;
+  return a;
+}
+
+int debye_de_init(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_de_params p, double *x,
+                  double *fit, double *best_cost, int64_t *best_idx, hipStream_t stream) {
+  int rc = de_check(b, ld, lb, ub, p);
+  if (rc) return rc;
+  if (!x || !fit || !best_cost || !best_idx) return fail(DEBYE_EINVAL, "NULL population pointer");
+  dfit::DeArgs a = de_args(b, ld, lb, ub, p, 0);
+  a.x = x;
+  a.fit = fit;
+  a.best_cost = best_cost;
+  a.best_idx = best_idx;
+  CHECK_HIP(dfit::launch_de_init(a, b->n_cand, stream), "DE init");
+  return DEBYE_OK;
+}
+
+int debye_de_trial(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_de_params p, int32_t t,
+                   const double *x, double *u, hipStream_t stream) {
+  int rc = de_check(b, ld, lb, ub, p);
+  if (rc) return rc;
+  if (!x || !u) return fail(DEBYE_EINVAL, "NULL population pointer");
+  if (t < 1) return fail(DEBYE_ERANGE, "generation must be >= 1");
+  dfit::DeArgs a = de_args(b, ld, lb, ub, p, t);
+  a.x = const_cast<double *>(x);
+  a.u = u;
+  CHECK_HIP(dfit::launch_de_trial(a, b->n_cand, stream), "DE trial");
+  return DEBYE_OK;
+}
+
+int debye_de_select(const debye_batch *b, int64_t ld, int32_t t, const double *u, const double *cost_u, double *x,
+                    double *fit, double *best_x, double *best_cost, int64_t *best_idx, double *history,
+                    int64_t hist_ld, hipStream_t stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (ld < b->max_poles) return fail(DEBYE_ERANGE, "ld < max_poles");
+  if (!u || !cost_u || !x || !fit || !best_x || !best_cost || !best_idx) return fail(DEBYE_EINVAL, "NULL pointer");
+  if (t < 0 || (history && hist_ld <= t)) return fail(DEBYE_ERANGE, "generation must be >= 0 and < hist_ld");
+  dfit::DeArgs a = de_args(b, ld, nullptr, nullptr, debye_de_params{0, 0, 0, 0}, t);
+  a.u = const_cast<double *>(u);
+  a.cost_u = cost_u;
+  a.x = x;
+  a.fit = fit;
+  a.best_x = best_x;
+  a.best_cost = best_cost;
+  a.best_idx = best_idx;
+  a.history = history;
+  a.hist_ld = hist_ld;
+  CHECK_HIP(dfit::launch_de_select(a, stream), "DE select");
+  return DEBYE_OK;
+}
+
+int debye_de_run(const debye_plan *pc, const debye_batch *b, int64_t ld, const double *lb, const double *ub,
+                 debye_de_params p, int32_t iters, double damping, uint32_t flags, const debye_population *pop,
+                 int32_t use_graph, hipStream_t stream) {
+  int rc = check_plan_batch(pc, b, ld);
+  if (rc) return rc;
+  if ((rc = check_damping(damping, flags))) return rc;
+  if ((rc = de_check(b, ld, lb, ub, p))) return rc;
+  if (!pop || !pop->x || !pop->u || !pop->fit || !pop->cost || !pop->best_x || !pop->best_cost || !pop->best_idx)
+    return fail(DEBYE_EINVAL, "NULL population pointer");
+  if (iters < 0) return fail(DEBYE_ERANGE, "iters must be >= 0");
+  if (pop->history && pop->hist_ld < (int64_t)iters + 1) return fail(DEBYE_ERANGE, "hist_ld must be >= iters + 1");
+  debye_plan *plan = const_cast<debye_plan *>(pc);
+  SwarmGraph &g = plan->de_graph;
+  hipStream_t s = stream;
+  if (use_graph) {
+    if ((rc = graph_enter(g, stream))) return rc;
+    s = g.stream;
+  }
+  auto sel = [&](int32_t t) {
+    dfit::DeArgs a = de_args(b, ld, lb, ub, p, t);
+    a.u = pop->u;
+    a.cost_u = pop->cost;
+    a.x = pop->x;
+    a.fit = pop->fit;
+    a.best_x = pop->best_x;
+    a.best_cost = pop->best_cost;
+    a.best_idx = pop->best_idx;
+    a.history = pop->history;
+    a.hist_ld = pop->hist_ld;
+    return a;
+  };
+  dfit::DeArgs a0 = sel(0);
+  CHECK_HIP(dfit::launch_de_init(a0, b->n_cand, s), "DE init");
+  // generation 0: the initial population is its own trial set
+  if ((rc = debye_fit_eval(plan, b, pop->x, ld, damping, flags, pop->cost, nullptr, nullptr, pop->status, s)))
+    return rc;
+  CHECK_HIP(hipMemcpyAsync(pop->u, pop->x, (size_t)b->n_cand * ld * 8, hipMemcpyDeviceToDevice, s), "copy");
+  CHECK_HIP(dfit::launch_de_select(a0, s), "DE select");
+  auto generation = [&](hipStream_t gs, int32_t t, const int32_t *t_dev) -> int {
+    dfit::DeArgs a = sel(t);
+    a.t_dev = t_dev;
+    CHECK_HIP(dfit::launch_de_trial(a, b->n_cand, gs), "DE trial");
+    int r = debye_fit_eval(plan, b, pop->u, ld, damping, flags, pop->cost, nullptr, nullptr, pop->status, gs);
+    if (r) return r;
+    CHECK_HIP(dfit::launch_de_select(a, gs), "DE select");
+    return DEBYE_OK;
+  };
+  if (!use_graph) {
+    for (int32_t t = 1; t <= iters; ++t)
+      if ((rc = generation(s, t, nullptr))) return rc;
+    return DEBYE_OK;
+  }
+  KeyBytes key;
+  key.put(*b);
+  key.put(ld);
+  key.put(lb);
+  key.put(ub);
+  key.put(p);
+  key.put(damping);
+  key.put(flags);
+  key.put(*pop);
+  rc = graph_replay(g, key.v, 1, iters, [&](hipStream_t gs, int32_t *counter) { return generation(gs, 0, counter); });
+  if (rc) return rc;
+  return graph_leave(g, stream);
 }
 
 int debye_lbfgs_polish(const debye_batch *b, const int64_t *f_off_host, const int32_t *n_poles_host, double *theta,

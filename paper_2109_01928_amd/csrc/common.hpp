@@ -74,6 +74,7 @@ __device__ __forceinline__ U64x4 philox4x64(uint64_t c0, uint64_t c1, uint64_t c
 // top 53 bits as a double in [0, 1)
 __device__ __forceinline__ double unit53(uint64_t r) { return (double)(r >> 11) * 0x1.0p-53; }
 
-enum { STREAM_PSO_INIT = 0, STREAM_PSO_STEP = 1, STREAM_NOISE = 2 };
+enum { STREAM_PSO_INIT = 0, STREAM_PSO_STEP = 1, STREAM_NOISE = 2, STREAM_DE_INIT = 3, STREAM_DE_TRIAL = 4,
+       STREAM_DE_CROSS = 5, STREAM_DE_F = 6 };
 
 }  // namespace dfit

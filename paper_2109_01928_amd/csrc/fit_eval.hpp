@@ -87,6 +87,29 @@ hipError_t launch_set_counter(int32_t *c, int32_t value, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_tick(int32_t *c, hipStream_t s);
 
+// differential evolution (de.hip)
+struct DeArgs {
+  int32_t M;
+  const int64_t *cand_off;
+  const int32_t *n_poles;
+  int64_t ld;
+  const double *lb, *ub;
+  double f_lo, f_hi, cr;
+  uint64_t seed;
+  int32_t t;
+  const int32_t *t_dev;  // if set, the generation number is read from device memory
+  double *x, *u;         // population and trial vectors [n_cand][ld]
+  const double *cost_u;  // cost of the trials
+  double *fit;           // cost of the members
+  double *best_x, *best_cost;
+  int64_t *best_idx;
+  double *history;
+  int64_t hist_ld;
+};
+hipError_t launch_de_init(const DeArgs &a, int64_t n_cand, hipStream_t s);
+hipError_t launch_de_trial(const DeArgs &a, int64_t n_cand, hipStream_t s);
+hipError_t launch_de_select(const DeArgs &a, hipStream_t s);
+
 struct LbfgsArgs {
   int32_t M;
   const int32_t *n_poles;

@@ -5,7 +5,6 @@ uniform), binomial crossover (one coordinate at CR = 0, the expected share
 otherwise), the box, greedy selection, and that it finds a brute-force
 global minimum."""
 import numpy as np
-import pytest
 
 import workloads as W
 
@@ -121,10 +120,12 @@ def test_selection_is_greedy_and_nan_never_wins(orc):
     assert pop.history[0, 0] == 1.0 and pop.history[0, 1] == 0.5
 
 
-def test_small_population_rejected(orc):
+def test_small_population_is_not_evolved(orc):
     pop = _pop(orc, 3, 2)
-    with pytest.raises(ValueError):
-        orc.de_trial([0, 3], [2], [-10.0], [-6.0], 0.5, 1.0, 0.7, 1, 1, pop)
+    orc.de_init([0, 3], [2], [-10.0], [-6.0], 1, pop)
+    pop.u[:] = 0.0
+    orc.de_trial([0, 3], [2], [-10.0], [-6.0], 0.5, 1.0, 0.7, 1, 1, pop)
+    np.testing.assert_array_equal(pop.u, pop.x)
 
 
 def test_de_finds_single_pole_global_minimum(orc):
