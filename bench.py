@@ -62,6 +62,8 @@ def main():
                     help="mixed (default): 1024 mixed materials, F=1000, N=8, 256x200; single: one HN, F=50, N=5, "
                          "40x50; ragged: 4096 materials of uneven F/N/swarm size; hncc: 1024 HN/CC, F=2000, N=12; "
                          "tables: 65536 HN-sum tables, F=4096, N=20, 128 particles")
+    ap.add_argument("--optimizer", default="pso", choices=["pso", "de"],
+                    help="global search: particle swarm (default) or differential evolution (rand/1/bin)")
     ap.add_argument("--materials", type=int, default=0, help="override the workload's material count")
     ap.add_argument("--iters", type=int, default=-1, help="override the workload's swarm iterations")
     ap.add_argument("--polish-steps", type=int, default=-1)
@@ -141,25 +143,41 @@ def main():
                           "alg_bytes_per_eval": algorithmic_bytes(F, N, 256)}), flush=True)
         return
 
+    pop = D.Population.empty(P, M, wl.ld, args.iters + 1, dev) if args.optimizer == "de" else None
+
+    def timed_eval(bb, theta, evs, events):
+        if events is not None:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        D.fit_eval(plan, bb, theta, want_weights=False, out=out)
+        if events is not None:
+            e1.record(stream)
+            evs.append((e0, e1))
+
     def one_step(events=None):
         er, ei = D.material_eval(kind_t, params_t, b, noise_seed=wl.noise_seed)
         bb = b.with_targets(er, ei)
-        D.pso_init(bb, lb, ub, sw, wl.inertia, wl.c1, wl.c2, wl.seed)
         evs = []
-        for t in range(args.iters + 1):
-            if t > 0:
-                D.pso_step(bb, lb, ub, sw, t, True, out[0], wl.inertia, wl.c1, wl.c2, wl.seed)
-            if events is not None:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-            D.fit_eval(plan, bb, sw.x, want_weights=False, out=out)
-            if events is not None:
-                e1.record(stream)
-                evs.append((e0, e1))
-        D.pso_step(bb, lb, ub, sw, args.iters + 1, False, out[0], wl.inertia, wl.c1, wl.c2, wl.seed)
+        if args.optimizer == "de":
+            D.de_init(bb, lb, ub, pop, seed=wl.seed)
+            timed_eval(bb, pop.x, evs, events)
+            D.de_select(bb, pop, 0, pop.x, out[0])
+            for t in range(1, args.iters + 1):
+                D.de_trial(bb, lb, ub, pop, t, seed=wl.seed)
+                timed_eval(bb, pop.u, evs, events)
+                D.de_select(bb, pop, t, pop.u, out[0])
+            best = pop.best_x
+        else:
+            D.pso_init(bb, lb, ub, sw, wl.inertia, wl.c1, wl.c2, wl.seed)
+            for t in range(args.iters + 1):
+                if t > 0:
+                    D.pso_step(bb, lb, ub, sw, t, True, out[0], wl.inertia, wl.c1, wl.c2, wl.seed)
+                timed_eval(bb, sw.x, evs, events)
+            D.pso_step(bb, lb, ub, sw, args.iters + 1, False, out[0], wl.inertia, wl.c1, wl.c2, wl.seed)
+            best = sw.gbest_x
         hist = None
         if args.polish_steps > 0:
-            theta1 = sw.gbest_x.clone()
+            theta1 = best.clone()
             hist = D.lbfgs_polish(b1.with_targets(er, ei), theta1, lb, ub, steps=args.polish_steps, mem=MEM,
                                   max_trials=T_TRIALS)
         if events is not None:
@@ -192,17 +210,23 @@ def main():
     # the same swarm fit replayed from a captured HIP graph vs eager launches
     bbx = b.with_targets(er, ei)
     t_sw = {}
+    def whole_fit(mode):
+        if args.optimizer == "de":
+            D.de_run(plan, bbx, lb, ub, pop, args.iters, seed=wl.seed, use_graph=mode)
+        else:
+            D.pso_run(plan, bbx, lb, ub, sw, args.iters, wl.inertia, wl.c1, wl.c2, wl.seed, use_graph=mode)
+
     for mode in (False, True):
-        D.pso_run(plan, bbx, lb, ub, sw, args.iters, wl.inertia, wl.c1, wl.c2, wl.seed, use_graph=mode)
+        whole_fit(mode)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        D.pso_run(plan, bbx, lb, ub, sw, args.iters, wl.inertia, wl.c1, wl.c2, wl.seed, use_graph=mode)
+        whole_fit(mode)
         torch.cuda.synchronize()
         t_sw["graph" if mode else "eager"] = 1e3 * (time.perf_counter() - t1)
 
     # forward + adjoint kernel rate on the final swarm positions
     bb = b.with_targets(er, ei)
-    theta = sw.x.clone()
+    theta = (pop.x if args.optimizer == "de" else sw.x).clone()
     D.fit_eval_grad(plan, bb, theta)
     torch.cuda.synchronize()
     g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -237,7 +261,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded materials; no dataset in the paper)",
-        "config": {"workload": f"{wl.name} + L-BFGS polish {args.polish_steps} steps x {T_TRIALS} trials",
+        "config": {"workload": f"{wl.name} {args.optimizer.upper()} + L-BFGS polish {args.polish_steps} steps x "
+                               f"{T_TRIALS} trials",
                    "materials": M, "freq_points": F if uniform else "ragged", "poles": N if uniform else "ragged",
                    "particles": P_per if uniform else "ragged", "iterations": args.iters,
                    "evals_per_step": evals_step},

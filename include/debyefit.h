@@ -270,6 +270,52 @@ int debye_pso_run(const debye_plan *plan, const debye_batch *b, int64_t ld, cons
                   int32_t use_graph, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Average fractional error of fitted expansions (the paper's accuracy figure,
+ * Sec. IV, Table I), in percent, per candidate:
+ *   100 (mean_k |eps'_k - m'_k| / |eps'_k| + mean_k |eps''_k - m''_k| / |eps''_k|)
+ * with the model m = eps_inf + sum_i w_i / (1 + j omega_k tau_i) (m'' its loss,
+ * sign of Eq. 1) and points where eps'' = 0 left out of the second mean.
+ * log10_tau, weights: [n_cand][ld]; eps_inf, afe: [n_cand] (device).
+ * ------------------------------------------------------------------------ */
+int debye_afe(const debye_batch *b, const double *log10_tau, int64_t ld, const double *weights,
+              const double *eps_inf, double *afe, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Automatic number of poles (Sec. III-B: with the pole count set to -1 the
+ * fit starts from one pole and adds poles until the average fractional error
+ * drops below 5 % or 20 poles are reached).  Batched over materials: the
+ * materials still unresolved are fitted with the next `chunk` pole counts at
+ * once, as one ragged batch in which every (material, N) pair is an entry with
+ * its own swarm of `particles` (Philox key (seed, entry index), entries
+ * ordered material-major, N ascending); each swarm best is polished
+ * (`polish_steps` L-BFGS steps, memory 10, 30 trials, c1 = 1e-4) and its AFE
+ * computed.  A material is resolved at the smallest N of the round whose AFE
+ * is below afe_target; materials that reach n_max keep the n_max fit.  The
+ * result is the pole count that the one-at-a-time procedure would stop at for
+ * these per-entry swarms; `chunk` only trades extra fits for fewer rounds.
+ *   mats: spectra of the M materials (n_mat, n_freq, f_off, omega, eps_re,
+ *         eps_im are used; the other fields are ignored); f_off_host its host
+ *         copy; lb, ub: device [M] bounds of log10 tau.
+ *   outputs (device): n_poles_out [M], log10_tau_out and weights_out
+ *         [M][ld_out] (ld_out >= n_max; entries past n_poles_out[m] are left
+ *         unchanged), eps_inf_out [M], afe_out [M].
+ * Allocates its own workspace, synchronises `stream` after every round.
+ * ------------------------------------------------------------------------ */
+typedef struct debye_auto_params {
+  int32_t n_min, n_max;     /* 1 <= n_min <= n_max <= DEBYE_MAX_POLES (the paper: 1 .. 20) */
+  int32_t chunk;            /* pole counts fitted per round, >= 1 */
+  double afe_target;        /* percent (the paper: 5) */
+  int32_t particles, iters; /* swarm of each (material, N): >= 1 particles, >= 0 iterations */
+  debye_pso_params pso;
+  int32_t polish_steps;     /* >= 0 */
+} debye_auto_params;
+
+int debye_fit_auto(const debye_batch *mats, const int64_t *f_off_host, const double *lb, const double *ub,
+                   debye_auto_params p, double damping, uint32_t flags, int32_t *n_poles_out,
+                   double *log10_tau_out, double *weights_out, double *eps_inf_out, double *afe_out,
+                   int64_t ld_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Differential evolution (the paper's DE-DLS alternative, Sec. III-A; Storn &
  * Price 1997, strategy rand/1/bin), one population per material over log10
  * tau: the candidates of material m are its members.  Generation-synchronous:

@@ -414,3 +414,63 @@ def afe(omega, eps_re, eps_im, d_eps, tau, eps_inf):
     omega, eps_re, eps_im, d_eps, tau = map(_f64, (omega, eps_re, eps_im, d_eps, tau))
     return lib().orc_afe(len(omega), _p(omega, _d), _p(eps_re, _d), _p(eps_im, _d), len(d_eps),
                          _p(d_eps, _d), _p(tau, _d), float(eps_inf))
+
+
+def fit_auto(f_off, omega, eps_re, eps_im, lb, ub, n_min=1, n_max=20, afe_target=5.0, particles=64, iters=100,
+             inertia=0.7, c1=1.5, c2=1.5, seed=0, polish_steps=20, damping=1e-8, flags=0, nthreads=0):
+    """Automatic pole count (Sec. III-B), one pole count at a time as the paper
+    describes it: N = n_min, n_min + 1, ... until the average fractional error
+    of the fit is below afe_target (percent), or N = n_max.  The fit of
+    material m with N poles is a swarm of `particles` for `iters` iterations
+    with Philox key (seed, m * NN + N - n_min), NN = n_max - n_min + 1 (the
+    swarm of a batch entry at that index; the other entries of the batch are
+    empty), then `polish_steps` L-BFGS steps (memory 10, 30 trials, c1 = 1e-4)
+    on its best.  Returns (N [M], log10_tau [M][n_max], weights [M][n_max],
+    eps_inf [M], afe [M])."""
+    f_off = np.ascontiguousarray(f_off, np.int64)
+    omega, eps_re, eps_im = map(_f64, (omega, eps_re, eps_im))
+    M = len(f_off) - 1
+    lb = _f64(np.broadcast_to(lb, (M,)))
+    ub = _f64(np.broadcast_to(ub, (M,)))
+    NN = n_max - n_min + 1
+    E = M * NN
+    out_n = np.zeros(M, np.int32)
+    out_th = np.full((M, n_max), np.nan)
+    out_w = np.full((M, n_max), np.nan)
+    out_e = np.full(M, np.nan)
+    out_a = np.full(M, np.nan)
+    todo = list(range(M))
+    for N in range(n_min, n_max + 1):
+        if not todo:
+            break
+        # the full entry batch: only (m, N) of unresolved m carry particles
+        active = np.zeros(E, bool)
+        for m in todo:
+            active[m * NN + (N - n_min)] = True
+        ent_m = np.arange(E) // NN
+        F_e = np.where(active, np.diff(f_off)[ent_m], 1)
+        P_e = np.where(active, particles, 0)
+        fe = np.concatenate([[0], np.cumsum(F_e)])
+        src = np.concatenate([np.arange(f_off[m], f_off[m] + F_e[e]) for e, m in enumerate(ent_m)])
+        b = Batch(fe, np.concatenate([[0], np.cumsum(P_e)]), np.full(E, N, np.int32), omega[src], eps_re[src],
+                  eps_im[src])
+        sw = pso_run(b, lb[ent_m], ub[ent_m], iters, inertia, c1, c2, seed, ld=N, damping=damping, flags=flags,
+                     nthreads=nthreads)
+        for m in list(todo):
+            e = m * NN + (N - n_min)
+            a, z = f_off[m], f_off[m + 1]
+            one = Batch([0, z - a], [0, 1], [N], omega[a:z], eps_re[a:z], eps_im[a:z])
+            th = sw.gbest_x[e:e + 1, :N].copy()
+            if polish_steps > 0:
+                th, _ = lbfgs(one, th, lb[m], ub[m], steps=polish_steps, mem=10, max_trials=30, c1=1e-4,
+                              damping=damping, flags=flags)
+            c, w, einf, st = fit_eval(one, th, damping, flags)
+            err = afe(omega[a:z], eps_re[a:z], eps_im[a:z], w[0, :N], 10.0 ** th[0], einf[0])
+            if err < afe_target or N == n_max:
+                out_n[m] = N
+                out_th[m, :N] = th[0]
+                out_w[m, :N] = w[0, :N]
+                out_e[m] = einf[0]
+                out_a[m] = err
+                todo.remove(m)
+    return out_n, out_th, out_w, out_e, out_a

@@ -34,7 +34,7 @@ EXPORTED = ["debye_plan_create", "debye_plan_destroy", "debye_plan_set_freq_spli
             "debye_plan_info",
             "debye_last_error", "debye_version", "debye_basis", "debye_fit_eval", "debye_fit_eval_grad",
             "debye_material_eval", "debye_material_vjp", "debye_pso_init", "debye_pso_step",
-            "debye_pso_run", "debye_de_init", "debye_de_trial", "debye_de_select", "debye_de_run",
+            "debye_pso_run", "debye_afe", "debye_fit_auto", "debye_de_init", "debye_de_trial", "debye_de_select", "debye_de_run",
             "debye_lbfgs_polish"]
 
 
@@ -68,6 +68,11 @@ class _CPop(C.Structure):
     _fields_ = [("x", C.c_void_p), ("u", C.c_void_p), ("fit", C.c_void_p), ("cost", C.c_void_p),
                 ("best_x", C.c_void_p), ("best_cost", C.c_void_p), ("best_idx", C.c_void_p),
                 ("history", C.c_void_p), ("hist_ld", C.c_int64), ("status", C.c_void_p)]
+
+
+class _CAuto(C.Structure):
+    _fields_ = [("n_min", C.c_int32), ("n_max", C.c_int32), ("chunk", C.c_int32), ("afe_target", C.c_double),
+                ("particles", C.c_int32), ("iters", C.c_int32), ("pso", _CPso), ("polish_steps", C.c_int32)]
 
 
 class _CLbfgs(C.Structure):
@@ -104,6 +109,9 @@ def lib():
                                  _vp, _vp, _vp, i64, _vp]
     L.debye_pso_run.argtypes = [_vp, C.POINTER(_CBatch), i64, _vp, _vp, _CPso, i32, dbl, u32, C.POINTER(_CSwarm), i32,
                                 _vp]
+    L.debye_afe.argtypes = [C.POINTER(_CBatch), _vp, i64, _vp, _vp, _vp, _vp]
+    L.debye_fit_auto.argtypes = [C.POINTER(_CBatch), _vp, _vp, _vp, _CAuto, dbl, u32, _vp, _vp, _vp, _vp, _vp, i64,
+                                 _vp]
     L.debye_de_init.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CDe, _vp, _vp, _vp, _vp, _vp]
     L.debye_de_trial.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CDe, i32, _vp, _vp, _vp]
     L.debye_de_select.argtypes = [C.POINTER(_CBatch), i64, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, i64, _vp]
@@ -316,6 +324,35 @@ def pso_run(plan: Plan, b: Batch, lb, ub, sw: Swarm, iters, inertia=0.7, c1=1.5,
                                _CPso(inertia, c1, c2, seed), int(iters), float(damping), flags, C.byref(cs),
                                1 if use_graph else 0, _stream()))
     return cost
+
+
+def afe(b: Batch, theta, weights, eps_inf):
+    """Average fractional error (percent) of every candidate's fitted expansion (debye_afe)."""
+    out = torch.empty(b.P, dtype=torch.float64, device=theta.device)
+    cb = b.cstruct()
+    _check(lib().debye_afe(C.byref(cb), _ptr(theta), theta.shape[1], _ptr(weights), _ptr(eps_inf), _ptr(out),
+                           _stream()))
+    return out
+
+
+def fit_auto(b: Batch, lb, ub, n_min=1, n_max=20, chunk=4, afe_target=5.0, particles=64, iters=100,
+             inertia=0.7, c1=1.5, c2=1.5, seed=0, polish_steps=20, damping=DEFAULT_DAMPING, flags=0):
+    """Automatic pole count (debye_fit_auto): the smallest N in n_min..n_max whose
+    fitted expansion has an average fractional error below afe_target percent.
+    b describes the materials' spectra (its candidate fields are ignored).
+    Returns (n_poles [M], log10_tau [M][n_max], weights [M][n_max], eps_inf [M], afe [M])."""
+    dev = b.omega.device
+    M = b.M
+    n = torch.zeros(M, dtype=torch.int32, device=dev)
+    th = torch.full((M, n_max), float("nan"), dtype=torch.float64, device=dev)
+    w = torch.full((M, n_max), float("nan"), dtype=torch.float64, device=dev)
+    einf = torch.empty(M, dtype=torch.float64, device=dev)
+    err = torch.empty(M, dtype=torch.float64, device=dev)
+    cb = b.cstruct()
+    prm = _CAuto(n_min, n_max, chunk, afe_target, particles, iters, _CPso(inertia, c1, c2, seed), polish_steps)
+    _check(lib().debye_fit_auto(C.byref(cb), b.f_off_h.ctypes.data_as(_vp), _ptr(lb), _ptr(ub), prm, float(damping),
+                                flags, _ptr(n), _ptr(th), _ptr(w), _ptr(einf), _ptr(err), n_max, _stream()))
+    return n, th, w, einf, err
 
 
 @dataclasses.dataclass

@@ -51,6 +51,11 @@ constexpr int MAX_SIDE_STREAMS = 4;
 
 }  // namespace
 
+namespace dfit {
+// error text for debye_last_error() from the library's other host files
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace dfit
+
 struct Bucket {
   int32_t N = 0, SP = 1, SF = 1, cpw = 64;
   int64_t n_cands = 0, n_tiles = 0, max_f = 0, work = 0;
@@ -506,6 +511,19 @@ int debye_plan_info(const debye_plan *p, int32_t i, int32_t *n_poles, int32_t *p
   if (pole_split) *pole_split = b.SP;
   if (freq_split) *freq_split = b.SF;
   if (n_tiles) *n_tiles = b.n_tiles;
+  return DEBYE_OK;
+}
+
+int debye_afe(const debye_batch *b, const double *log10_tau, int64_t ld, const double *weights, const double *eps_inf,
+              double *afe, hipStream_t stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (ld < b->max_poles) return fail(DEBYE_ERANGE, "ld < max_poles");
+  if (!log10_tau || !weights || !eps_inf || !afe) return fail(DEBYE_EINVAL, "NULL pointer");
+  if (b->n_cand > INT32_MAX) return fail(DEBYE_ERANGE, "more than 2^31-1 candidates");
+  dfit::AfeArgs a{b->n_mat, b->f_off, b->cand_off, b->n_poles, b->omega, b->eps_re, b->eps_im,
+                  log10_tau, weights, eps_inf, ld, afe};
+  CHECK_HIP(dfit::launch_afe(a, b->n_cand, stream), "debye_afe launch");
   return DEBYE_OK;
 }
 

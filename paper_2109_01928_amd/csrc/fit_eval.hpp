@@ -87,6 +87,26 @@ hipError_t launch_set_counter(int32_t *c, int32_t value, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_tick(int32_t *c, hipStream_t s);
 
+// error text for debye_last_error() (api.hip); returns code
+int set_error(int code, const char *msg);
+
+// average fractional error of fitted expansions (material.hip)
+struct AfeArgs {
+  int32_t M;
+  const int64_t *f_off, *cand_off;
+  const int32_t *n_poles;
+  const double *omega, *eps_re, *eps_im;
+  const double *theta, *weights, *eps_inf;
+  int64_t ld;
+  double *afe;
+};
+hipError_t launch_afe(const AfeArgs &a, int64_t n_cand, hipStream_t s);
+hipError_t launch_gather_spectra(int64_t n_entries, const int64_t *src_off, const int32_t *src_mat,
+                                 const int64_t *dst_off, const double *s0, const double *s1, const double *s2,
+                                 double *d0, double *d1, double *d2, hipStream_t s);
+hipError_t launch_scatter_rows(int64_t n_entries, const int64_t *src_row, const int64_t *dst_row, const int32_t *n,
+                               const double *src, int64_t src_ld, double *dst, int64_t dst_ld, hipStream_t s);
+
 // differential evolution (de.hip)
 struct DeArgs {
   int32_t M;

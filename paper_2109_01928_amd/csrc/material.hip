@@ -230,3 +230,105 @@ hipError_t launch_basis(const double *omega, int64_t F, const double *theta, int
 }
 
 }  // namespace dfit
+
+namespace dfit {
+
+// --------------------------------------------------------------------------
+// Average fractional error of a fitted expansion (the paper's accuracy figure,
+// Sec. IV): 100 (mean_k |eps'_k - model'_k| / |eps'_k| + mean_k |eps''_k -
+// model''_k| / |eps''_k|), model = eps_inf + sum_i w_i / (1 + j w_k tau_i);
+// points with eps'' = 0 are left out of the second mean.  One 64-lane block
+// per candidate, lanes strided over the frequencies, fixed-order reduction.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void afe_kernel(const AfeArgs a) {
+  const int64_t c = blockIdx.x;
+  const int lane = threadIdx.x;
+  int lo = 0, hi = a.M - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.cand_off[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  const int m = lo;
+  const int64_t f0 = a.f_off[m], F = a.f_off[m + 1] - f0;
+  const int N = a.n_poles[m];
+  double tau[DFIT_MAX_POLES], w[DFIT_MAX_POLES];
+  for (int i = 0; i < N; ++i) {
+    tau[i] = exp10(a.theta[c * a.ld + i]);
+    w[i] = a.weights[c * a.ld + i];
+  }
+  const double einf = a.eps_inf[c];
+  double sr = 0.0, si = 0.0, ni = 0.0;
+  for (int64_t k = lane; k < F; k += 64) {
+    const double om = a.omega[f0 + k], er = a.eps_re[f0 + k], ei = a.eps_im[f0 + k];
+    double mr = einf, mi = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const double x = om * tau[i];
+      const double R = 1.0 / __builtin_fma(x, x, 1.0);
+      mr = __builtin_fma(w[i], R, mr);
+      mi = __builtin_fma(w[i], x * R, mi);
+    }
+    sr += fabs(er - mr) / fabs(er);
+    if (ei != 0.0) {
+      si += fabs(ei - mi) / fabs(ei);
+      ni += 1.0;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_xor(sr, off, 64);
+    si += __shfl_xor(si, off, 64);
+    ni += __shfl_xor(ni, off, 64);
+  }
+  if (lane == 0) a.afe[c] = 100.0 * (sr / (double)F + (ni > 0.0 ? si / ni : 0.0));
+}
+
+hipError_t launch_afe(const AfeArgs &a, int64_t n_cand, hipStream_t s) {
+  if (n_cand == 0) return hipSuccess;
+  if (n_cand > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(afe_kernel, dim3((unsigned)n_cand), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+// dst entry e <- the first dst_off[e+1] - dst_off[e] points of the spectra of
+// source material src_mat[e] (which has at least that many); one block per entry
+__global__ __launch_bounds__(256) void gather_spectra_kernel(const int64_t *src_off, const int32_t *src_mat,
+                                                             const int64_t *dst_off, const double *s0,
+                                                             const double *s1, const double *s2, double *d0,
+                                                             double *d1, double *d2) {
+  const int64_t e = blockIdx.x;
+  const int32_t m = src_mat[e];
+  const int64_t a = src_off[m], b = dst_off[e], F = dst_off[e + 1] - b;
+  for (int64_t k = threadIdx.x; k < F; k += blockDim.x) {
+    d0[b + k] = s0[a + k];
+    d1[b + k] = s1[a + k];
+    d2[b + k] = s2[a + k];
+  }
+}
+
+hipError_t launch_gather_spectra(int64_t n_entries, const int64_t *src_off, const int32_t *src_mat,
+                                 const int64_t *dst_off, const double *s0, const double *s1, const double *s2,
+                                 double *d0, double *d1, double *d2, hipStream_t s) {
+  if (n_entries == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_spectra_kernel, dim3((unsigned)n_entries), dim3(256), 0, s, src_off, src_mat, dst_off, s0,
+                     s1, s2, d0, d1, d2);
+  return hipGetLastError();
+}
+
+// rows: dst[dst_row[e] * dst_ld + i] = src[src_row[e] * src_ld + i], i < n[e]
+__global__ __launch_bounds__(64) void scatter_rows_kernel(int64_t n_entries, const int64_t *src_row,
+                                                          const int64_t *dst_row, const int32_t *n,
+                                                          const double *src, int64_t src_ld, double *dst,
+                                                          int64_t dst_ld) {
+  const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (e >= n_entries) return;
+  for (int i = 0; i < n[e]; ++i) dst[dst_row[e] * dst_ld + i] = src[src_row[e] * src_ld + i];
+}
+
+hipError_t launch_scatter_rows(int64_t n_entries, const int64_t *src_row, const int64_t *dst_row, const int32_t *n,
+                               const double *src, int64_t src_ld, double *dst, int64_t dst_ld, hipStream_t s) {
+  if (n_entries == 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)((n_entries + 63) / 64)), dim3(64), 0, s, n_entries, src_row,
+                     dst_row, n, src, src_ld, dst, dst_ld);
+  return hipGetLastError();
+}
+
+}  // namespace dfit
