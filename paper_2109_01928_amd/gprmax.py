@@ -1,0 +1,272 @@
+"""gprMax command front end (paper Sec. IV, Listings 1 and 2).
+
+Reads the dispersive-material commands of a gprMax input file, fits a
+multi-pole Debye expansion to each material on the GPU (all materials of the
+file in one batch), and writes the equivalent `#material` and
+`#add_dispersion_debye` commands.
+
+Command layouts.  `#havriliak_negami` is the paper's (Listing 1): lower and
+upper frequency (Hz), alpha, beta, eps_inf, delta eps, tau0 (s), conductivity
+(S/m), relative permeability, magnetic loss (Ohm/m), number of poles,
+identifier, optional seed.  The paper leaves the other layouts to the gprMax
+documentation; here they follow the same order (band, relaxation-function
+parameters, material properties, then sigma, mu_r, sigma_m, poles, id, seed):
+
+    #jonscher: f_lo f_hi n_p eps_inf A_p f_p sigma mu_r sigma_m n_poles id [seed]
+        eps = eps_inf + A_p (j f / f_p)^(n_p - 1)   (constant-Q form; f_p in Hz)
+    #crim: f_lo f_hi a f_w eps_inf_w d_eps_w tau_w eps_m sigma mu_r sigma_m n_poles id [seed]
+        sqrt(eps) = f_w sqrt(Debye water) + (1 - f_w) sqrt(eps_m), a = 0.5 only
+    #raw_data: path sigma mu_r sigma_m n_poles id [seed]
+        a text table of f (Hz), eps', eps'' (eps = eps' - j eps''), one point a
+        line, '#' comments; the band is the table's
+
+A pole count of -1 asks for the automatic count (1 .. 20 poles until the
+average fractional error is below 5 %, Sec. III-B).  Output numbers follow
+Listing 2: eps_inf and delta eps with four decimals, relaxation times with a
+four-decimal mantissa; conductivity, permeability and magnetic loss are
+copied from the command as written.
+
+Usage:  python -m paper_2109_01928_amd.gprmax input.in [-o output.in]
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import math
+import os
+import re
+import sys
+
+import numpy as np
+
+KINDS = {"#havriliak_negami": 1, "#jonscher": 4, "#crim": 5, "#raw_data": -1}
+N_FREQ = 100          # log-spaced points per band (both ends included)
+MAX_AUTO_POLES = 20
+
+
+@dataclasses.dataclass
+class Dispersive:
+    command: str
+    line: int
+    f_lo: float
+    f_hi: float
+    params: np.ndarray            # library parameter row (kinds of debye_material_eval)
+    kind: int                     # library kind; -1 for a table
+    sigma: str
+    mu_r: str
+    sigma_m: str
+    n_poles: int                  # -1: automatic
+    ident: str
+    seed: int
+    table: tuple | None = None    # (f, eps', eps'') for #raw_data
+
+
+class CommandError(ValueError):
+    pass
+
+
+def _floats(tokens, n, cmd, line):
+    try:
+        return [float(t) for t in tokens[:n]]
+    except ValueError as e:
+        raise CommandError(f"line {line}: {cmd}: expected {n} numbers ({e})") from None
+
+
+def _tail(tokens, cmd, line):
+    """sigma mu_r sigma_m n_poles id [seed]"""
+    if len(tokens) not in (5, 6):
+        raise CommandError(f"line {line}: {cmd}: expected sigma mu_r sigma_m n_poles id [seed]")
+    sigma, mu_r, sigma_m = tokens[:3]
+    for t in (sigma, mu_r, sigma_m):
+        _floats([t], 1, cmd, line)
+    try:
+        n = int(tokens[3])
+    except ValueError:
+        raise CommandError(f"line {line}: {cmd}: number of poles must be an integer") from None
+    if n != -1 and not 1 <= n <= 24:
+        raise CommandError(f"line {line}: {cmd}: number of poles must be -1 or 1..24")
+    seed = int(tokens[5]) if len(tokens) == 6 else 0
+    return sigma, mu_r, sigma_m, n, tokens[4], seed
+
+
+def read_table(path):
+    data = np.loadtxt(path, comments="#", ndmin=2)
+    if data.shape[1] < 3 or len(data) < 2:
+        raise CommandError(f"{path}: expected at least two rows of f eps' eps''")
+    order = np.argsort(data[:, 0])
+    return data[order, 0], data[order, 1], data[order, 2]
+
+
+def parse(text, base_dir="."):
+    """The dispersive commands of a gprMax input, in file order."""
+    out = []
+    for line_no, raw in enumerate(text.splitlines(), 1):
+        line = raw.strip()
+        m = re.match(r"^(#\w+)\s*:\s*(.*)$", line)
+        if not m or m.group(1) not in KINDS:
+            continue
+        cmd, tokens = m.group(1), m.group(2).split()
+        params = np.zeros(16)
+        if cmd == "#havriliak_negami":
+            if len(tokens) < 7:
+                raise CommandError(f"line {line_no}: {cmd}: too few parameters")
+            f_lo, f_hi, alpha, beta, eps_inf, d_eps, tau0 = _floats(tokens, 7, cmd, line_no)
+            params[:5] = [eps_inf, d_eps, tau0, alpha, beta]
+            rest, table = tokens[7:], None
+        elif cmd == "#jonscher":
+            if len(tokens) < 6:
+                raise CommandError(f"line {line_no}: {cmd}: too few parameters")
+            f_lo, f_hi, n_p, eps_inf, a_p, f_p = _floats(tokens, 6, cmd, line_no)
+            params[:4] = [eps_inf, a_p, 2 * math.pi * f_p, n_p]
+            rest, table = tokens[6:], None
+        elif cmd == "#crim":
+            if len(tokens) < 8:
+                raise CommandError(f"line {line_no}: {cmd}: too few parameters")
+            f_lo, f_hi, a, f_w, einf_w, de_w, tau_w, eps_m = _floats(tokens, 8, cmd, line_no)
+            if a != 0.5:
+                raise CommandError(f"line {line_no}: {cmd}: only the shape factor a = 0.5 is supported")
+            params[:5] = [einf_w, de_w, tau_w, f_w, eps_m]
+            rest, table = tokens[8:], None
+        else:
+            if not tokens:
+                raise CommandError(f"line {line_no}: {cmd}: missing file name")
+            path = tokens[0] if os.path.isabs(tokens[0]) else os.path.join(base_dir, tokens[0])
+            table = read_table(path)
+            f_lo, f_hi = float(table[0][0]), float(table[0][-1])
+            rest = tokens[1:]
+        if not (0 < f_lo < f_hi):
+            raise CommandError(f"line {line_no}: {cmd}: need 0 < f_lo < f_hi")
+        sigma, mu_r, sigma_m, n, ident, seed = _tail(rest, cmd, line_no)
+        out.append(Dispersive(cmd, line_no, f_lo, f_hi, params, KINDS[cmd], sigma, mu_r, sigma_m, n, ident, seed,
+                              table))
+    return out
+
+
+def number(v):
+    """Listing 2's style: four decimals, or a four-decimal mantissa below 1e-3."""
+    if v != 0 and abs(v) < 1e-3:
+        mant, exp = f"{v:.4e}".split("e")
+        return f"{mant}e{int(exp)}"
+    return f"{v:.4f}"
+
+
+def emit(cmd: Dispersive, eps_inf, d_eps, tau):
+    """The two gprMax commands that replace a dispersive one."""
+    pairs = " ".join(f"{number(d)} {number(t)}" for d, t in zip(d_eps, tau))
+    return (f"#material: {number(eps_inf)} {cmd.sigma} {cmd.mu_r} {cmd.sigma_m} {cmd.ident}\n"
+            f"#add_dispersion_debye: {len(d_eps)} {pairs} {cmd.ident}\n")
+
+
+def tau_bounds(f_lo, f_hi):
+    """log10 tau search box from the band: [floor(-log10(2 pi f_hi)) - 1, floor(-log10(2 pi f_lo))]."""
+    return (math.floor(-math.log10(2 * math.pi * f_hi)) - 1.0, float(math.floor(-math.log10(2 * math.pi * f_lo))))
+
+
+def fit(cmds, particles=64, iters=100, polish_steps=50, optimizer="pso", damping=1e-8, n_freq=N_FREQ,
+        device="cuda"):
+    """Fit every command on the GPU; materials sharing a seed and a pole
+    count are fitted together.  Returns per command (eps_inf, d_eps, tau, afe)."""
+    import torch
+
+    import paper_2109_01928_amd as D
+
+    results = [None] * len(cmds)
+    # spectra of every command
+    omega, er, ei = [], [], []
+    for c in cmds:
+        if c.table is not None:
+            f, a, b = c.table
+        else:
+            f = np.geomspace(c.f_lo, c.f_hi, n_freq)
+            a = b = None
+        omega.append(2 * np.pi * f)
+        er.append(a)
+        ei.append(b)
+    # targets of the analytic materials on the GPU
+    for i, c in enumerate(cmds):
+        if c.table is None:
+            e1, e2 = D.material_eval(np.array([c.kind], np.int8), c.params[None], [0, len(omega[i])], omega[i],
+                                     device=device)
+            er[i], ei[i] = e1.cpu().numpy(), e2.cpu().numpy()
+    groups = {}
+    for i, c in enumerate(cmds):
+        groups.setdefault((c.seed, c.n_poles), []).append(i)
+    for (seed, n), idx in groups.items():
+        F = [len(omega[i]) for i in idx]
+        f_off = np.concatenate([[0], np.cumsum(F)])
+        om = np.concatenate([omega[i] for i in idx])
+        e1 = torch.tensor(np.concatenate([er[i] for i in idx]), device=device)
+        e2 = torch.tensor(np.concatenate([ei[i] for i in idx]), device=device)
+        bounds = np.array([tau_bounds(cmds[i].f_lo, cmds[i].f_hi) for i in idx])
+        lb = torch.tensor(bounds[:, 0], device=device)
+        ub = torch.tensor(bounds[:, 1], device=device)
+        M = len(idx)
+        if n == -1:
+            b = D.Batch(f_off, np.arange(M + 1), np.ones(M, np.int32), om, e1, e2, device)
+            nn, th, w, einf, err = D.fit_auto(b, lb, ub, n_max=MAX_AUTO_POLES, particles=particles, iters=iters,
+                                              seed=seed, polish_steps=polish_steps, damping=damping)
+            nn, th, w, einf, err = (t.cpu().numpy() for t in (nn, th, w, einf, err))
+            for j, i in enumerate(idx):
+                k = nn[j]
+                results[i] = (einf[j], w[j, :k], 10.0 ** th[j, :k], err[j])
+            continue
+        cand_off = np.arange(M + 1) * particles
+        b = D.Batch(f_off, cand_off, np.full(M, n, np.int32), om, e1, e2, device)
+        plan = D.Plan(b)
+        if optimizer == "de":
+            pop = D.Population.empty(M * particles, M, n, iters + 1, device)
+            D.de_run(plan, b, lb, ub, pop, iters, seed=seed, damping=damping)
+            best = pop.best_x.clone()
+        else:
+            sw = D.Swarm.empty(M * particles, M, n, iters + 1, device)
+            D.pso_run(plan, b, lb, ub, sw, iters, seed=seed, damping=damping)
+            best = sw.gbest_x.clone()
+        b1 = D.Batch(f_off, np.arange(M + 1), np.full(M, n, np.int32), om, e1, e2, device)
+        if polish_steps > 0:
+            D.lbfgs_polish(b1, best, lb, ub, steps=polish_steps, damping=damping)
+        cost, w, einf, st = D.fit_eval(D.Plan(b1), b1, best, damping=damping)
+        err = D.afe(b1, best, w, einf)
+        th, w, einf, err = (t.cpu().numpy() for t in (best, w, einf, err))
+        for j, i in enumerate(idx):
+            results[i] = (einf[j], w[j, :n], 10.0 ** th[j, :n], err[j])
+    return results
+
+
+def translate(text, base_dir=".", **fit_kw):
+    """The input with every dispersive command replaced by its Debye expansion."""
+    cmds = parse(text, base_dir)
+    res = fit(cmds, **fit_kw) if cmds else []
+    by_line = {c.line: (c, r) for c, r in zip(cmds, res)}
+    out = []
+    for line_no, raw in enumerate(text.splitlines(), 1):
+        if line_no in by_line:
+            c, (einf, d_eps, tau, err) = by_line[line_no]
+            # a line that does not start with '#' is a comment to gprMax
+            out.append(f"Fitted {len(d_eps)} Debye poles (average fractional error {err:.2f} %) to: {raw.strip()}")
+            out.append(emit(c, einf, d_eps, tau).rstrip("\n"))
+        else:
+            out.append(raw)
+    return "\n".join(out) + "\n"
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="Replace gprMax dispersive-material commands by multi-pole Debye "
+                                             "expansions fitted on the GPU.")
+    ap.add_argument("input")
+    ap.add_argument("-o", "--output")
+    ap.add_argument("--optimizer", choices=["pso", "de"], default="pso")
+    ap.add_argument("--particles", type=int, default=64)
+    ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--polish-steps", type=int, default=50)
+    args = ap.parse_args(argv)
+    text = open(args.input).read()
+    out = translate(text, os.path.dirname(os.path.abspath(args.input)), particles=args.particles, iters=args.iters,
+                    polish_steps=args.polish_steps, optimizer=args.optimizer)
+    if args.output:
+        open(args.output, "w").write(out)
+    else:
+        sys.stdout.write(out)
+
+
+if __name__ == "__main__":
+    main()
