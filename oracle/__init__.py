@@ -69,6 +69,14 @@ def lib():
                                    C.c_uint64, C.c_int32, _d, _d]
         L.orc_de_select.argtypes = [C.c_int32, _i64, _i32, C.c_int64, C.c_int32, _d, _d, _d, _d, _d, _d, _i64, _d,
                                     C.c_int64]
+        L.orc_series_exp_log.argtypes = [C.c_int64, _d, _d, _d]
+        L.orc_student_t.argtypes = [C.c_uint64, C.c_int64, C.c_double, _d]
+        L.orc_da_temps.argtypes = [C.c_double, C.c_double, C.c_int32, _d, _d]
+        L.orc_da_init.argtypes = [C.c_int32, _i64, _i32, C.c_int64, _d, _d, C.c_uint64, _d, _d, _d, _i64]
+        L.orc_da_visit.argtypes = [C.c_int32, _i64, _i32, C.c_int64, _d, _d, C.c_double, C.c_double, C.c_uint64,
+                                   C.c_int32, _d, _d]
+        L.orc_da_accept.argtypes = [C.c_int32, _i64, _i32, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                    C.c_uint64, C.c_int32, _d, _d, _d, _d, _d, _d, _i64, _d, C.c_int64]
         L.orc_fit_cond_batch.argtypes = [C.c_int32, _i64, _i64, _i32, _d, _d, _d, _d, C.c_int64, C.c_double,
                                          C.c_uint32, _d, C.c_int]
         L.orc_num_threads.restype = C.c_int
@@ -474,3 +482,71 @@ def fit_auto(f_off, omega, eps_re, eps_im, lb, ub, n_min=1, n_max=20, afe_target
                 out_a[m] = err
                 todo.remove(m)
     return out_n, out_th, out_w, out_e, out_a
+
+
+# ---------------------------------------------------------------------------
+# Annealing (generalized simulated annealing, batched Markov chains)
+# ---------------------------------------------------------------------------
+DA_QV, DA_QA, DA_T0 = 2.62, -5.0, 5230.0
+
+
+def series_exp_log(x):
+    """The oracle's own exp and log (series with every operation rounded)."""
+    x = _f64(np.atleast_1d(x))
+    ex, lg = np.empty_like(x), np.empty_like(x)
+    lib().orc_series_exp_log(len(x), _p(x, _d), _p(ex, _d), _p(lg, _d))
+    return ex, lg
+
+
+def student_t(seed, n, nu):
+    """n draws of the annealing's visiting variate (Student-t, nu degrees of freedom)."""
+    out = np.empty(n)
+    lib().orc_student_t(seed, n, nu, _p(out, _d))
+    return out
+
+
+def da_temps(t, qv=DA_QV, t0=DA_T0):
+    vs, ta = C.c_double(), C.c_double()
+    lib().orc_da_temps(qv, t0, t, C.byref(vs), C.byref(ta))
+    return vs.value, ta.value
+
+
+def da_init(cand_off, n_poles, lb, ub, seed, pop: Population):
+    cand_off = np.ascontiguousarray(cand_off, np.int64)
+    n_poles = np.ascontiguousarray(n_poles, np.int32)
+    lib().orc_da_init(len(n_poles), _p(cand_off, _i64), _p(n_poles, _i32), pop.x.shape[1], _p(_f64(lb), _d),
+                      _p(_f64(ub), _d), seed, _p(pop.x, _d), _p(pop.fit, _d), _p(pop.best_cost, _d),
+                      _p(pop.best_idx, _i64))
+
+
+def da_visit(cand_off, n_poles, lb, ub, seed, t, pop: Population, qv=DA_QV, t0=DA_T0):
+    """Proposals of generation t into pop.u."""
+    cand_off = np.ascontiguousarray(cand_off, np.int64)
+    n_poles = np.ascontiguousarray(n_poles, np.int32)
+    lib().orc_da_visit(len(n_poles), _p(cand_off, _i64), _p(n_poles, _i32), pop.x.shape[1], _p(_f64(lb), _d),
+                       _p(_f64(ub), _d), qv, t0, seed, t, _p(pop.x, _d), _p(pop.u, _d))
+
+
+def da_accept(cand_off, n_poles, seed, t, u, cost_u, pop: Population, qv=DA_QV, qa=DA_QA, t0=DA_T0):
+    cand_off = np.ascontiguousarray(cand_off, np.int64)
+    n_poles = np.ascontiguousarray(n_poles, np.int32)
+    u, cost_u = _f64(u), _f64(cost_u)
+    lib().orc_da_accept(len(n_poles), _p(cand_off, _i64), _p(n_poles, _i32), pop.x.shape[1], qv, qa, t0, seed, t,
+                        _p(u, _d), _p(cost_u, _d), _p(pop.x, _d), _p(pop.fit, _d), _p(pop.best_x, _d),
+                        _p(pop.best_cost, _d), _p(pop.best_idx, _i64), _p(pop.history, _d), pop.history.shape[1])
+
+
+def da_run(b: Batch, lb, ub, iters, seed=0, qv=DA_QV, qa=DA_QA, t0=DA_T0, ld=None, damping=1e-8, flags=0,
+           nthreads=0):
+    """Whole annealing: chains initialised in the box (generation 0), then
+    `iters` x (propose, evaluate, accept).  P*(iters+1) evaluations."""
+    ld = ld or int(b.n_poles.max())
+    pop = Population(b.P, b.M, ld, iters + 1)
+    da_init(b.cand_off, b.n_poles, lb, ub, seed, pop)
+    da_accept(b.cand_off, b.n_poles, seed, 0, pop.x.copy(), fit_eval(b, pop.x, damping, flags, nthreads=nthreads)[0],
+              pop, qv, qa, t0)
+    for t in range(1, iters + 1):
+        da_visit(b.cand_off, b.n_poles, lb, ub, seed, t, pop, qv, t0)
+        da_accept(b.cand_off, b.n_poles, seed, t, pop.u, fit_eval(b, pop.u, damping, flags, nthreads=nthreads)[0],
+                  pop, qv, qa, t0)
+    return pop

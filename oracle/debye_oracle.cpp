@@ -114,7 +114,7 @@ inline double u01(uint64_t r) { return (double)(r >> 11) * 0x1.0p-53; }
 
 // Stream identifiers used as the last counter word.
 enum { STREAM_PSO_INIT = 0, STREAM_PSO_STEP = 1, STREAM_NOISE = 2, STREAM_DE_INIT = 3, STREAM_DE_TRIAL = 4,
-       STREAM_DE_CROSS = 5, STREAM_DE_F = 6 };
+       STREAM_DE_CROSS = 5, STREAM_DE_F = 6, STREAM_DA_INIT = 7, STREAM_DA_VISIT = 8, STREAM_DA_ACCEPT = 9 };
 
 // ---------------------------------------------------------------------------
 // Material models (relaxation functions).  eps = eps' - j eps'' (Eq. 1).
@@ -1017,6 +1017,208 @@ int orc_de_select(int32_t M, const int64_t *cand_off, const int32_t *n_poles, in
         fit[c] = cost_u[c];
         for (int d = 0; d < N; ++d) x[c * ld + d] = u[c * ld + d];
       }
+    int64_t best = -1;
+    for (int64_t c = c0; c < c1; ++c) {
+      if (std::isnan(fit[c])) continue;
+      if (best < 0 || fit[c] < fit[best]) best = c;
+    }
+    if (best >= 0 && fit[best] < best_cost[m]) {
+      best_cost[m] = fit[best];
+      best_idx[m] = best - c0;
+      for (int d = 0; d < N; ++d) best_x[m * ld + d] = x[best * ld + d];
+    }
+    if (history) history[m * hist_ld + t] = best_cost[m];
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Exponential and logarithm written out from their textbook series, every
+// operation rounded on its own, so that the annealing's random transforms are
+// reproducible bit for bit by any IEEE double implementation of the same steps.
+//   exp: x = k ln2 + r, k = rint(x / ln2), |r| <= ln2/2, ln2 split into a
+//        20-bit head (k * head exact) and a tail (Cody & Waite 1980);
+//        e^r = 1 + r (1 + r/2 (1 + r/3 (... (1 + r/17)))), then scaled by 2^k.
+//   log: x = m 2^e, m in [sqrt(1/2), sqrt(2)); s = (m - 1)/(m + 1),
+//        log m = 2 s (1 + s^2/3 + s^4/5 + ... + s^24/25) (the atanh series).
+// ---------------------------------------------------------------------------
+constexpr double LN2_HEAD = 0x1.62e42p-1, LN2_TAIL = 0x1.fdf473de6af28p-22;   // LN2_HEAD + LN2_TAIL = ln 2
+constexpr double INV_LN2 = 0x1.71547652b82fep+0;
+
+double series_exp(double x) {
+  if (x != x) return x;
+  if (x > 709.0) return INFINITY;
+  if (x < -745.0) return 0.0;
+  const double k = std::nearbyint(x * INV_LN2);
+  const double r = (x - k * LN2_HEAD) - k * LN2_TAIL;
+  double p = 1.0;
+  for (int n = 17; n >= 1; --n) p = 1.0 + (r / (double)n) * p;
+  return std::ldexp(p, (int)k);
+}
+
+double series_log(double x) {
+  if (x != x || x < 0.0) return NAN;
+  if (x == 0.0) return -INFINITY;
+  if (x == INFINITY) return INFINITY;
+  int e = 0;
+  double m = std::frexp(x, &e);   // [1/2, 1)
+  if (m < 0x1.6a09e667f3bcdp-1) {  // sqrt(1/2)
+    m = 2.0 * m;
+    e -= 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double z = s * s;
+  double q = 1.0 / 25.0;
+  for (int k = 11; k >= 0; --k) q = q * z + 1.0 / (double)(2 * k + 1);
+  const double lm = 2.0 * s * q;
+  return (double)e * LN2_HEAD + ((double)e * LN2_TAIL + lm);
+}
+
+// ---------------------------------------------------------------------------
+// Annealing (the paper's DA-DLS alternative, Sec. III-A): generalized
+// simulated annealing (Tsallis & Stariolo 1996) as used by dual annealing,
+// batched: the candidates of a material are independent Markov chains over
+// log10 tau.  Generation t >= 1 (scalars from the series above):
+//   visiting temperature  T(t) = T0 (2^(qv-1) - 1) / ((1 + t)^(qv-1) - 1)
+//   acceptance temperature Ta(t) = T(t) / t
+//   proposal  y_d = x_d + s(t) g_d, s(t) = T(t)^(1/(3-qv)) / sqrt(3 - qv),
+//             g_d Student-t with nu = (3 - qv)/(qv - 1) degrees of freedom
+//             (the one-dimensional visiting distribution), drawn by Bailey's
+//             polar method, then wrapped into [lb, ub] periodically
+//   accept    if f(y) < f(x); otherwise with probability
+//             [1 - (1 - qa)(f(y) - f(x))/Ta]^(1/(1-qa)) when the bracket is
+//             positive: u^(1-qa) < bracket
+// Random numbers, Philox key (seed, material):
+//   initial chain i, coordinate d:  ctr (d, i, 0, DA_INIT), word 0
+//   proposal coordinate d:          ctr (d, i, t, DA_VISIT + 16 j), pairs of
+//       words (0,1), (2,3) for the j-th round of the polar method (at most 16
+//       rounds; g = 0 if none is accepted)
+//   acceptance of chain i:          ctr (0, i, t, DA_ACCEPT), word 0
+// ---------------------------------------------------------------------------
+struct DaTemps { double visit_scale, accept_temp; };
+
+DaTemps da_temps(double qv, double t0, int32_t t) {
+  const double a = qv - 1.0;
+  const double num = series_exp(a * series_log(2.0)) - 1.0;
+  const double den = series_exp(a * series_log(1.0 + (double)t)) - 1.0;
+  const double T = t0 * num / den;
+  DaTemps r;
+  r.visit_scale = series_exp(series_log(T) / (3.0 - qv)) / std::sqrt(3.0 - qv);
+  r.accept_temp = T / (double)t;
+  return r;
+}
+
+double student_t_polar(uint64_t seed, uint64_t m, uint64_t d, uint64_t i, uint64_t t, double nu) {
+  for (int j = 0; j < 16; ++j) {
+    uint64_t ctr[4] = {d, i, t, (uint64_t)(STREAM_DA_VISIT + 16 * j)}, key[2] = {seed, m}, w[4];
+    philox4x64_10(ctr, key, w);
+    for (int h = 0; h < 2; ++h) {
+      const double u = 2.0 * u01(w[2 * h]) - 1.0, v = 2.0 * u01(w[2 * h + 1]) - 1.0;
+      const double W = u * u + v * v;
+      if (W > 0.0 && W <= 1.0) {
+        double q = series_exp((-2.0 / nu) * series_log(W));
+        if (q > 1e300) q = 1e300;
+        return u * std::sqrt(nu * (q - 1.0) / W);
+      }
+    }
+  }
+  return 0.0;
+}
+
+// periodic wrap into [lo, hi]
+inline double wrap_box(double y, double lo, double hi) {
+  if (y >= lo && y <= hi) return y;
+  const double span = hi - lo;
+  double r = std::fmod(y - lo, span);
+  if (r < 0.0) r = r + span;
+  return lo + r;
+}
+
+int orc_series_exp_log(int64_t n, const double *x, double *ex, double *lg) {
+  for (int64_t i = 0; i < n; ++i) {
+    if (ex) ex[i] = series_exp(x[i]);
+    if (lg) lg[i] = series_log(x[i]);
+  }
+  return 0;
+}
+
+int orc_student_t(uint64_t seed, int64_t n, double nu, double *out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = student_t_polar(seed, 0, 0, (uint64_t)i, 1, nu);
+  return 0;
+}
+
+int orc_da_temps(double qv, double t0, int32_t t, double *visit_scale, double *accept_temp) {
+  const DaTemps r = da_temps(qv, t0, t);
+  *visit_scale = r.visit_scale;
+  *accept_temp = r.accept_temp;
+  return 0;
+}
+
+int orc_da_init(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int64_t ld, const double *lb,
+                const double *ub, uint64_t seed, double *x, double *fit, double *best_cost, int64_t *best_idx) {
+  for (int32_t m = 0; m < M; ++m) {
+    for (int64_t c = cand_off[m]; c < cand_off[m + 1]; ++c) {
+      const int64_t i = c - cand_off[m];
+      for (int d = 0; d < n_poles[m]; ++d) {
+        uint64_t ctr[4] = {(uint64_t)d, (uint64_t)i, 0, STREAM_DA_INIT}, key[2] = {seed, (uint64_t)m}, w[4];
+        philox4x64_10(ctr, key, w);
+        x[c * ld + d] = lb[m] + (ub[m] - lb[m]) * u01(w[0]);
+      }
+      fit[c] = INFINITY;
+    }
+    best_cost[m] = INFINITY;
+    best_idx[m] = -1;
+  }
+  return 0;
+}
+
+// proposals of generation t >= 1
+int orc_da_visit(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int64_t ld, const double *lb,
+                 const double *ub, double qv, double t0, uint64_t seed, int32_t t, const double *x, double *y) {
+  const DaTemps tp = da_temps(qv, t0, t);
+  const double nu = (3.0 - qv) / (qv - 1.0);
+  for (int32_t m = 0; m < M; ++m)
+    for (int64_t c = cand_off[m]; c < cand_off[m + 1]; ++c) {
+      const int64_t i = c - cand_off[m];
+      for (int d = 0; d < n_poles[m]; ++d) {
+        const double g = student_t_polar(seed, (uint64_t)m, (uint64_t)d, (uint64_t)i, (uint64_t)t, nu);
+        y[c * ld + d] = wrap_box(x[c * ld + d] + tp.visit_scale * g, lb[m], ub[m]);
+      }
+    }
+  return 0;
+}
+
+// acceptance of generation t (t = 0: the initial chains, all accepted)
+int orc_da_accept(int32_t M, const int64_t *cand_off, const int32_t *n_poles, int64_t ld, double qv, double qa,
+                  double t0, uint64_t seed, int32_t t, const double *y, const double *cost_y, double *x, double *fit,
+                  double *best_x, double *best_cost, int64_t *best_idx, double *history, int64_t hist_ld) {
+  const DaTemps tp = t > 0 ? da_temps(qv, t0, t) : DaTemps{0.0, 0.0};
+  for (int32_t m = 0; m < M; ++m) {
+    const int64_t c0 = cand_off[m], c1 = cand_off[m + 1];
+    const int N = n_poles[m];
+    for (int64_t c = c0; c < c1; ++c) {
+      const double fy = cost_y[c], fx = fit[c];
+      bool take;
+      if (t == 0 || fy < fx) {
+        take = !(fy != fy);
+      } else if (fy != fy) {
+        take = false;
+      } else {
+        const double z = 1.0 - (1.0 - qa) * (fy - fx) / tp.accept_temp;
+        take = false;
+        if (z > 0.0) {
+          uint64_t ctr[4] = {0, (uint64_t)(c - c0), (uint64_t)t, STREAM_DA_ACCEPT}, key[2] = {seed, (uint64_t)m}, w[4];
+          philox4x64_10(ctr, key, w);
+          const double u = u01(w[0]);
+          take = series_exp((1.0 - qa) * series_log(u)) < z;
+        }
+      }
+      if (take) {
+        fit[c] = fy;
+        for (int d = 0; d < N; ++d) x[c * ld + d] = y[c * ld + d];
+      }
+    }
+    // best visited state: the lowest-index minimum of the chains' accepted costs
     int64_t best = -1;
     for (int64_t c = c0; c < c1; ++c) {
       if (std::isnan(fit[c])) continue;
