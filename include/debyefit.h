@@ -376,6 +376,53 @@ int debye_de_run(const debye_plan *plan, const debye_batch *b, int64_t ld, const
                  int32_t use_graph, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Annealing (the paper's DA-DLS alternative, Sec. III-A; generalized
+ * simulated annealing, Tsallis & Stariolo 1996, as in dual annealing),
+ * batched: the candidates of material m are independent Markov chains over
+ * log10 tau.  Generation t >= 1:
+ *   visiting temperature   T(t) = t0 (2^(qv-1) - 1) / ((1 + t)^(qv-1) - 1)
+ *   acceptance temperature Ta(t) = T(t) / t
+ *   proposal  y = x + s(t) g (every coordinate), s(t) = T(t)^(1/(3-qv)) /
+ *             sqrt(3 - qv), g_d Student-t with (3 - qv)/(qv - 1) degrees of
+ *             freedom, wrapped periodically into [lb[m], ub[m]]
+ *   accept    if cost(y) < cost(x); otherwise with probability
+ *             [1 - (1 - qa)(cost(y) - cost(x))/Ta]^(1/(1-qa)) when positive
+ *             (a NaN cost is never accepted)
+ * then the material's best visited state (lowest index among equal costs)
+ * if it improves; history[m * hist_ld + t] (may be NULL).  Random numbers:
+ * Philox4x64-10, key (seed, material), counters listed in the library source;
+ * exp and log are taken from their series, operation by operation, so that
+ * runs are bit-identical to the CPU reference.  The state uses the
+ * debye_population layout (x the chains, u the proposals, fit their costs).
+ *   debye_da_init:   chains uniform in the box; fit, best_cost = +inf,
+ *                    best_idx = -1.
+ *   debye_da_visit:  y = proposals of generation t from x.
+ *   debye_da_accept: generation t >= 1 as above; t = 0 takes y = x with
+ *                    cost_y = cost(x) (the initial chains).
+ *   debye_da_run:    init, generation 0, `iters` generations [visit ->
+ *                    debye_fit_eval -> accept], optionally replayed from a
+ *                    captured HIP graph (bit-identical); hist_ld >= iters + 1.
+ * Defaults of the method: qv = 2.62, qa = -5, t0 = 5230.
+ * ------------------------------------------------------------------------ */
+typedef struct debye_da_params {
+  double qv;      /* 1 < qv < 3 */
+  double qa;      /* qa < 1 */
+  double t0;      /* initial visiting temperature > 0 */
+  uint64_t seed;
+} debye_da_params;
+
+int debye_da_init(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_da_params p,
+                  double *x, double *fit, double *best_cost, int64_t *best_idx, hipStream_t stream);
+int debye_da_visit(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_da_params p,
+                   int32_t t, const double *x, double *y, hipStream_t stream);
+int debye_da_accept(const debye_batch *b, int64_t ld, debye_da_params p, int32_t t, const double *y,
+                    const double *cost_y, double *x, double *fit, double *best_x, double *best_cost,
+                    int64_t *best_idx, double *history, int64_t hist_ld, hipStream_t stream);
+int debye_da_run(const debye_plan *plan, const debye_batch *b, int64_t ld, const double *lb, const double *ub,
+                 debye_da_params p, int32_t iters, double damping, uint32_t flags, const debye_population *pop,
+                 int32_t use_graph, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Gradient polish: L-BFGS (Liu & Nocedal 1989; two-loop recursion, memory
  * `mem`), Armijo backtracking alpha = 1, 1/2, ... (max_trials, constant c1),
  * on one candidate per material, theta [M][ld] in place, inside the search box

@@ -35,7 +35,7 @@ EXPORTED = ["debye_plan_create", "debye_plan_destroy", "debye_plan_set_freq_spli
             "debye_last_error", "debye_version", "debye_basis", "debye_fit_eval", "debye_fit_eval_grad",
             "debye_material_eval", "debye_material_vjp", "debye_pso_init", "debye_pso_step",
             "debye_pso_run", "debye_afe", "debye_fit_auto", "debye_de_init", "debye_de_trial", "debye_de_select", "debye_de_run",
-            "debye_lbfgs_polish"]
+            "debye_da_init", "debye_da_visit", "debye_da_accept", "debye_da_run", "debye_lbfgs_polish"]
 
 
 class DebyeError(RuntimeError):
@@ -62,6 +62,10 @@ class _CSwarm(C.Structure):
 
 class _CDe(C.Structure):
     _fields_ = [("f_lo", C.c_double), ("f_hi", C.c_double), ("cr", C.c_double), ("seed", C.c_uint64)]
+
+
+class _CDa(C.Structure):
+    _fields_ = [("qv", C.c_double), ("qa", C.c_double), ("t0", C.c_double), ("seed", C.c_uint64)]
 
 
 class _CPop(C.Structure):
@@ -116,6 +120,10 @@ def lib():
     L.debye_de_trial.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CDe, i32, _vp, _vp, _vp]
     L.debye_de_select.argtypes = [C.POINTER(_CBatch), i64, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, i64, _vp]
     L.debye_de_run.argtypes = [_vp, C.POINTER(_CBatch), i64, _vp, _vp, _CDe, i32, dbl, u32, C.POINTER(_CPop), i32, _vp]
+    L.debye_da_init.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CDa, _vp, _vp, _vp, _vp, _vp]
+    L.debye_da_visit.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CDa, i32, _vp, _vp, _vp]
+    L.debye_da_accept.argtypes = [C.POINTER(_CBatch), i64, _CDa, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, i64, _vp]
+    L.debye_da_run.argtypes = [_vp, C.POINTER(_CBatch), i64, _vp, _vp, _CDa, i32, dbl, u32, C.POINTER(_CPop), i32, _vp]
     L.debye_lbfgs_polish.argtypes = [C.POINTER(_CBatch), _vp, _vp, _vp, i64, _vp, _vp, dbl, u32, _CLbfgs, _vp, _vp]
     _lib = L
     return L
@@ -408,6 +416,41 @@ def de_run(plan: Plan, b: Batch, lb, ub, pop: Population, iters, f_lo=0.5, f_hi=
     _check(lib().debye_de_run(plan.handle, C.byref(cb), pop.x.shape[1], _ptr(lb), _ptr(ub),
                               _CDe(f_lo, f_hi, cr, seed), int(iters), float(damping), flags, C.byref(cp),
                               1 if use_graph else 0, _stream()))
+
+
+DA_QV, DA_QA, DA_T0 = 2.62, -5.0, 5230.0
+
+
+def da_init(b: Batch, lb, ub, pop: Population, qv=DA_QV, qa=DA_QA, t0=DA_T0, seed=0):
+    cb = b.cstruct()
+    _check(lib().debye_da_init(C.byref(cb), pop.x.shape[1], _ptr(lb), _ptr(ub), _CDa(qv, qa, t0, seed), _ptr(pop.x),
+                               _ptr(pop.fit), _ptr(pop.best_cost), _ptr(pop.best_idx), _stream()))
+
+
+def da_visit(b: Batch, lb, ub, pop: Population, t, qv=DA_QV, qa=DA_QA, t0=DA_T0, seed=0):
+    """pop.u = proposals of generation t (debye_da_visit)."""
+    cb = b.cstruct()
+    _check(lib().debye_da_visit(C.byref(cb), pop.x.shape[1], _ptr(lb), _ptr(ub), _CDa(qv, qa, t0, seed), int(t),
+                                _ptr(pop.x), _ptr(pop.u), _stream()))
+
+
+def da_accept(b: Batch, pop: Population, t, y, cost_y, qv=DA_QV, qa=DA_QA, t0=DA_T0, seed=0, history=True):
+    cb = b.cstruct()
+    h = pop.history if history else None
+    _check(lib().debye_da_accept(C.byref(cb), pop.x.shape[1], _CDa(qv, qa, t0, seed), int(t), _ptr(y), _ptr(cost_y),
+                                 _ptr(pop.x), _ptr(pop.fit), _ptr(pop.best_x), _ptr(pop.best_cost),
+                                 _ptr(pop.best_idx), _ptr(h), pop.history.shape[1], _stream()))
+
+
+def da_run(plan: Plan, b: Batch, lb, ub, pop: Population, iters, qv=DA_QV, qa=DA_QA, t0=DA_T0, seed=0,
+           damping=DEFAULT_DAMPING, flags=0, use_graph=True, status=None):
+    """A whole annealing fit (debye_da_run)."""
+    cp = _CPop(pop.x.data_ptr(), pop.u.data_ptr(), pop.fit.data_ptr(), pop.cost.data_ptr(), pop.best_x.data_ptr(),
+               pop.best_cost.data_ptr(), pop.best_idx.data_ptr(), pop.history.data_ptr(), pop.history.shape[1],
+               None if status is None else status.data_ptr())
+    cb = b.cstruct()
+    _check(lib().debye_da_run(plan.handle, C.byref(cb), pop.x.shape[1], _ptr(lb), _ptr(ub), _CDa(qv, qa, t0, seed),
+                              int(iters), float(damping), flags, C.byref(cp), 1 if use_graph else 0, _stream()))
 
 
 def lbfgs_polish(b1: Batch, theta, lb, ub, steps=50, mem=10, max_trials=30, c1=1e-4, damping=DEFAULT_DAMPING,

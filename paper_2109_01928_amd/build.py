@@ -13,9 +13,9 @@ ARCH = os.environ.get("DEBYEFIT_ARCH", "gfx950")
 
 COMMON = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", f"-I{INC}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
-# per-file extra flags: the swarm and DE updates must be rounded operation by operation
-EXTRA = {"pso.hip": ["-ffp-contract=off"], "de.hip": ["-ffp-contract=off"]}
-SOURCES = ["fit_eval.hip", "material.hip", "pso.hip", "de.hip", "lbfgs.hip", "api.hip", "auto.hip"]
+# per-file extra flags: the optimiser updates must be rounded operation by operation
+EXTRA = {"pso.hip": ["-ffp-contract=off"], "de.hip": ["-ffp-contract=off"], "da.hip": ["-ffp-contract=off"]}
+SOURCES = ["fit_eval.hip", "material.hip", "pso.hip", "de.hip", "da.hip", "lbfgs.hip", "api.hip", "auto.hip"]
 
 
 def _compile(name, objdir, verbose):

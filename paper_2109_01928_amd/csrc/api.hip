@@ -76,7 +76,7 @@ struct SwarmGraph {
 };
 
 struct debye_plan {
-  SwarmGraph graph, de_graph;
+  SwarmGraph graph, de_graph, da_graph;
   int32_t M = 0, max_poles = 0;
   int64_t n_freq = 0, n_cand = 0;
   std::vector<int64_t> f_off, cand_off;
@@ -424,6 +424,7 @@ int debye_plan_destroy(debye_plan *p) {
   if (!p) return DEBYE_OK;
   graph_destroy(p->graph);
   graph_destroy(p->de_graph);
+  graph_destroy(p->da_graph);
   for (hipStream_t st : p->side)
     if (st) (void)hipStreamSynchronize(st);
   for (auto &b : p->buckets) free_bucket(b);
@@ -903,6 +904,147 @@ int debye_de_run(const debye_plan *pc, const debye_batch *b, int64_t ld, const d
     int r = debye_fit_eval(plan, b, pop->u, ld, damping, flags, pop->cost, nullptr, nullptr, pop->status, gs);
     if (r) return r;
     CHECK_HIP(dfit::launch_de_select(a, gs), "DE select");
+    return DEBYE_OK;
+  };
+  if (!use_graph) {
+    for (int32_t t = 1; t <= iters; ++t)
+      if ((rc = generation(s, t, nullptr))) return rc;
+    return DEBYE_OK;
+  }
+  KeyBytes key;
+  key.put(*b);
+  key.put(ld);
+  key.put(lb);
+  key.put(ub);
+  key.put(p);
+  key.put(damping);
+  key.put(flags);
+  key.put(*pop);
+  rc = graph_replay(g, key.v, 1, iters, [&](hipStream_t gs, int32_t *counter) { return generation(gs, 0, counter); });
+  if (rc) return rc;
+  return graph_leave(g, stream);
+}
+
+// ---- annealing ----
+static int da_check(const debye_batch *b, int64_t ld, debye_da_params p) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (ld < b->max_poles) return fail(DEBYE_ERANGE, "ld < max_poles");
+  if (!(p.qv > 1.0 && p.qv < 3.0) || !(p.qa < 1.0) || !(p.t0 > 0.0) || !std::isfinite(p.t0) || !std::isfinite(p.qa))
+    return fail(DEBYE_ERANGE, "annealing parameters out of range (1 < qv < 3, qa < 1, t0 > 0)");
+  return DEBYE_OK;
+}
+
+static dfit::DaArgs da_args(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_da_params p,
+                            int32_t t) {
+  dfit::DaArgs a{};
+  a.M = b->n_mat;
+  a.cand_off = b->cand_off;
+  a.n_poles = b->n_poles;
+  a.ld = ld;
+  a.lb = lb;
+  a.ub = ub;
+  a.qv = p.qv;
+  a.qa = p.qa;
+  a.t0 = p.t0;
+  a.seed = p.seed;
+  a.t = t;
+  return a;
+}
+
+int debye_da_init(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_da_params p, double *x,
+                  double *fit, double *best_cost, int64_t *best_idx, hipStream_t stream) {
+  int rc = da_check(b, ld, p);
+  if (rc) return rc;
+  if (!lb || !ub || !x || !fit || !best_cost || !best_idx) return fail(DEBYE_EINVAL, "NULL pointer");
+  dfit::DaArgs a = da_args(b, ld, lb, ub, p, 0);
+  a.x = x;
+  a.fit = fit;
+  a.best_cost = best_cost;
+  a.best_idx = best_idx;
+  CHECK_HIP(dfit::launch_da_init(a, b->n_cand, stream), "annealing init");
+  return DEBYE_OK;
+}
+
+int debye_da_visit(const debye_batch *b, int64_t ld, const double *lb, const double *ub, debye_da_params p, int32_t t,
+                   const double *x, double *y, hipStream_t stream) {
+  int rc = da_check(b, ld, p);
+  if (rc) return rc;
+  if (!lb || !ub || !x || !y) return fail(DEBYE_EINVAL, "NULL pointer");
+  if (t < 1) return fail(DEBYE_ERANGE, "generation must be >= 1");
+  dfit::DaArgs a = da_args(b, ld, lb, ub, p, t);
+  a.x = const_cast<double *>(x);
+  a.u = y;
+  CHECK_HIP(dfit::launch_da_visit(a, b->n_cand, stream), "annealing visit");
+  return DEBYE_OK;
+}
+
+int debye_da_accept(const debye_batch *b, int64_t ld, debye_da_params p, int32_t t, const double *y,
+                    const double *cost_y, double *x, double *fit, double *best_x, double *best_cost, int64_t *best_idx,
+                    double *history, int64_t hist_ld, hipStream_t stream) {
+  int rc = da_check(b, ld, p);
+  if (rc) return rc;
+  if (!y || !cost_y || !x || !fit || !best_x || !best_cost || !best_idx) return fail(DEBYE_EINVAL, "NULL pointer");
+  if (t < 0 || (history && hist_ld <= t)) return fail(DEBYE_ERANGE, "generation must be >= 0 and < hist_ld");
+  dfit::DaArgs a = da_args(b, ld, nullptr, nullptr, p, t);
+  a.u = const_cast<double *>(y);
+  a.cost_u = cost_y;
+  a.x = x;
+  a.fit = fit;
+  a.best_x = best_x;
+  a.best_cost = best_cost;
+  a.best_idx = best_idx;
+  a.history = history;
+  a.hist_ld = hist_ld;
+  CHECK_HIP(dfit::launch_da_accept(a, stream), "annealing accept");
+  return DEBYE_OK;
+}
+
+int debye_da_run(const debye_plan *pc, const debye_batch *b, int64_t ld, const double *lb, const double *ub,
+                 debye_da_params p, int32_t iters, double damping, uint32_t flags, const debye_population *pop,
+                 int32_t use_graph, hipStream_t stream) {
+  int rc = check_plan_batch(pc, b, ld);
+  if (rc) return rc;
+  if ((rc = check_damping(damping, flags))) return rc;
+  if ((rc = da_check(b, ld, p))) return rc;
+  if (!lb || !ub) return fail(DEBYE_EINVAL, "lb/ub are NULL");
+  if (!pop || !pop->x || !pop->u || !pop->fit || !pop->cost || !pop->best_x || !pop->best_cost || !pop->best_idx)
+    return fail(DEBYE_EINVAL, "NULL population pointer");
+  if (iters < 0) return fail(DEBYE_ERANGE, "iters must be >= 0");
+  if (pop->history && pop->hist_ld < (int64_t)iters + 1) return fail(DEBYE_ERANGE, "hist_ld must be >= iters + 1");
+  debye_plan *plan = const_cast<debye_plan *>(pc);
+  SwarmGraph &g = plan->da_graph;
+  hipStream_t s = stream;
+  if (use_graph) {
+    if ((rc = graph_enter(g, stream))) return rc;
+    s = g.stream;
+  }
+  auto args = [&](int32_t t) {
+    dfit::DaArgs a = da_args(b, ld, lb, ub, p, t);
+    a.u = pop->u;
+    a.cost_u = pop->cost;
+    a.x = pop->x;
+    a.fit = pop->fit;
+    a.best_x = pop->best_x;
+    a.best_cost = pop->best_cost;
+    a.best_idx = pop->best_idx;
+    a.history = pop->history;
+    a.hist_ld = pop->hist_ld;
+    return a;
+  };
+  dfit::DaArgs a0 = args(0);
+  CHECK_HIP(dfit::launch_da_init(a0, b->n_cand, s), "annealing init");
+  if ((rc = debye_fit_eval(plan, b, pop->x, ld, damping, flags, pop->cost, nullptr, nullptr, pop->status, s)))
+    return rc;
+  CHECK_HIP(hipMemcpyAsync(pop->u, pop->x, (size_t)b->n_cand * ld * 8, hipMemcpyDeviceToDevice, s), "copy");
+  CHECK_HIP(dfit::launch_da_accept(a0, s), "annealing accept");
+  auto generation = [&](hipStream_t gs, int32_t t, const int32_t *t_dev) -> int {
+    dfit::DaArgs a = args(t);
+    a.t_dev = t_dev;
+    CHECK_HIP(dfit::launch_da_visit(a, b->n_cand, gs), "annealing visit");
+    int r = debye_fit_eval(plan, b, pop->u, ld, damping, flags, pop->cost, nullptr, nullptr, pop->status, gs);
+    if (r) return r;
+    CHECK_HIP(dfit::launch_da_accept(a, gs), "annealing accept");
     return DEBYE_OK;
   };
   if (!use_graph) {

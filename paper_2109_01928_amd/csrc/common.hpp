@@ -75,6 +75,6 @@ __device__ __forceinline__ U64x4 philox4x64(uint64_t c0, uint64_t c1, uint64_t c
 __device__ __forceinline__ double unit53(uint64_t r) { return (double)(r >> 11) * 0x1.0p-53; }
 
 enum { STREAM_PSO_INIT = 0, STREAM_PSO_STEP = 1, STREAM_NOISE = 2, STREAM_DE_INIT = 3, STREAM_DE_TRIAL = 4,
-       STREAM_DE_CROSS = 5, STREAM_DE_F = 6 };
+       STREAM_DE_CROSS = 5, STREAM_DE_F = 6, STREAM_DA_INIT = 7, STREAM_DA_VISIT = 8, STREAM_DA_ACCEPT = 9 };
 
 }  // namespace dfit

@@ -130,6 +130,29 @@ hipError_t launch_de_init(const DeArgs &a, int64_t n_cand, hipStream_t s);
 hipError_t launch_de_trial(const DeArgs &a, int64_t n_cand, hipStream_t s);
 hipError_t launch_de_select(const DeArgs &a, hipStream_t s);
 
+// annealing (da.hip)
+struct DaArgs {
+  int32_t M;
+  const int64_t *cand_off;
+  const int32_t *n_poles;
+  int64_t ld;
+  const double *lb, *ub;
+  double qv, qa, t0;
+  uint64_t seed;
+  int32_t t;
+  const int32_t *t_dev;  // if set, the generation number is read from device memory
+  double *x, *u;         // chain states and proposals [n_cand][ld]
+  const double *cost_u;  // cost of the proposals
+  double *fit;           // cost of the states
+  double *best_x, *best_cost;
+  int64_t *best_idx;
+  double *history;
+  int64_t hist_ld;
+};
+hipError_t launch_da_init(const DaArgs &a, int64_t n_cand, hipStream_t s);
+hipError_t launch_da_visit(const DaArgs &a, int64_t n_cand, hipStream_t s);
+hipError_t launch_da_accept(const DaArgs &a, hipStream_t s);
+
 struct LbfgsArgs {
   int32_t M;
   const int32_t *n_poles;
