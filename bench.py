@@ -62,8 +62,9 @@ def main():
                     help="mixed (default): 1024 mixed materials, F=1000, N=8, 256x200; single: one HN, F=50, N=5, "
                          "40x50; ragged: 4096 materials of uneven F/N/swarm size; hncc: 1024 HN/CC, F=2000, N=12; "
                          "tables: 65536 HN-sum tables, F=4096, N=20, 128 particles")
-    ap.add_argument("--optimizer", default="pso", choices=["pso", "de"],
-                    help="global search: particle swarm (default) or differential evolution (rand/1/bin)")
+    ap.add_argument("--optimizer", default="pso", choices=["pso", "de", "da"],
+                    help="global search: particle swarm (default), differential evolution (rand/1/bin) or "
+                         "annealing (batched generalized simulated annealing chains)")
     ap.add_argument("--materials", type=int, default=0, help="override the workload's material count")
     ap.add_argument("--iters", type=int, default=-1, help="override the workload's swarm iterations")
     ap.add_argument("--polish-steps", type=int, default=-1)
@@ -143,7 +144,7 @@ def main():
                           "alg_bytes_per_eval": algorithmic_bytes(F, N, 256)}), flush=True)
         return
 
-    pop = D.Population.empty(P, M, wl.ld, args.iters + 1, dev) if args.optimizer == "de" else None
+    pop = D.Population.empty(P, M, wl.ld, args.iters + 1, dev) if args.optimizer in ("de", "da") else None
 
     def timed_eval(bb, theta, evs, events):
         if events is not None:
@@ -153,6 +154,8 @@ def main():
         if events is not None:
             e1.record(stream)
             evs.append((e0, e1))
+
+    final = [None]   # each material's fitted log10 tau of the last step
 
     def one_step(events=None):
         er, ei = D.material_eval(kind_t, params_t, b, noise_seed=wl.noise_seed)
@@ -167,6 +170,15 @@ def main():
                 timed_eval(bb, pop.u, evs, events)
                 D.de_select(bb, pop, t, pop.u, out[0])
             best = pop.best_x
+        elif args.optimizer == "da":
+            D.da_init(bb, lb, ub, pop, seed=wl.seed)
+            timed_eval(bb, pop.x, evs, events)
+            D.da_accept(bb, pop, 0, pop.x, out[0], seed=wl.seed)
+            for t in range(1, args.iters + 1):
+                D.da_visit(bb, lb, ub, pop, t, seed=wl.seed)
+                timed_eval(bb, pop.u, evs, events)
+                D.da_accept(bb, pop, t, pop.u, out[0], seed=wl.seed)
+            best = pop.best_x
         else:
             D.pso_init(bb, lb, ub, sw, wl.inertia, wl.c1, wl.c2, wl.seed)
             for t in range(args.iters + 1):
@@ -176,9 +188,9 @@ def main():
             D.pso_step(bb, lb, ub, sw, args.iters + 1, False, out[0], wl.inertia, wl.c1, wl.c2, wl.seed)
             best = sw.gbest_x
         hist = None
+        final[0] = best.clone()
         if args.polish_steps > 0:
-            theta1 = best.clone()
-            hist = D.lbfgs_polish(b1.with_targets(er, ei), theta1, lb, ub, steps=args.polish_steps, mem=MEM,
+            hist = D.lbfgs_polish(b1.with_targets(er, ei), final[0], lb, ub, steps=args.polish_steps, mem=MEM,
                                   max_trials=T_TRIALS)
         if events is not None:
             events.extend(evs)
@@ -213,6 +225,8 @@ def main():
     def whole_fit(mode):
         if args.optimizer == "de":
             D.de_run(plan, bbx, lb, ub, pop, args.iters, seed=wl.seed, use_graph=mode)
+        elif args.optimizer == "da":
+            D.da_run(plan, bbx, lb, ub, pop, args.iters, seed=wl.seed, use_graph=mode)
         else:
             D.pso_run(plan, bbx, lb, ub, sw, args.iters, wl.inertia, wl.c1, wl.c2, wl.seed, use_graph=mode)
 
@@ -226,7 +240,7 @@ def main():
 
     # forward + adjoint kernel rate on the final swarm positions
     bb = b.with_targets(er, ei)
-    theta = (pop.x if args.optimizer == "de" else sw.x).clone()
+    theta = (pop.x if pop is not None else sw.x).clone()
     D.fit_eval_grad(plan, bb, theta)
     torch.cuda.synchronize()
     g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -276,6 +290,12 @@ def main():
                      else "fit_kernel (all pole-count buckets of one evaluation)",
                      "avg_launch_s": avg, "flops_per_eval": wb, "evals_per_launch": P},
     }
+    # fit quality of the last step: average fractional error (Sec. IV) of each material's result
+    b1t = b1.with_targets(er, ei)
+    _, w1, e1, _ = D.fit_eval(D.Plan(b1t), b1t, final[0])
+    afe = D.afe(b1t, final[0], w1, e1).cpu().numpy()
+    line["fit_quality"] = {"afe_percent_median": float(np.median(afe)), "afe_percent_max": float(np.max(afe)),
+                           "afe_below_5_percent": float(np.mean(afe < 5.0))}
     if hist is not None:
         h = hist.cpu().numpy()
         drop = 1 - h[:, -1] / h[:, 0]

@@ -7,6 +7,7 @@
 // on the principal branch in polar form.
 
 #include "common.hpp"
+#include "rng.hpp"
 #include "fit_eval.hpp"
 
 namespace dfit {

@@ -8,6 +8,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "rng.hpp"
 #include "fit_eval.hpp"
 
 namespace dfit {

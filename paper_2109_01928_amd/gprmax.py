@@ -213,9 +213,10 @@ def fit(cmds, particles=64, iters=100, polish_steps=50, optimizer="pso", damping
         cand_off = np.arange(M + 1) * particles
         b = D.Batch(f_off, cand_off, np.full(M, n, np.int32), om, e1, e2, device)
         plan = D.Plan(b)
-        if optimizer == "de":
+        if optimizer in ("de", "da"):
             pop = D.Population.empty(M * particles, M, n, iters + 1, device)
-            D.de_run(plan, b, lb, ub, pop, iters, seed=seed, damping=damping)
+            run = D.de_run if optimizer == "de" else D.da_run
+            run(plan, b, lb, ub, pop, iters, seed=seed, damping=damping)
             best = pop.best_x.clone()
         else:
             sw = D.Swarm.empty(M * particles, M, n, iters + 1, device)
@@ -254,7 +255,8 @@ def main(argv=None):
                                              "expansions fitted on the GPU.")
     ap.add_argument("input")
     ap.add_argument("-o", "--output")
-    ap.add_argument("--optimizer", choices=["pso", "de"], default="pso")
+    ap.add_argument("--optimizer", choices=["pso", "de", "da"], default="pso",
+                    help="global search (PSO-DLS default, DE-DLS, DA-DLS); fixed pole counts only")
     ap.add_argument("--particles", type=int, default=64)
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--polish-steps", type=int, default=50)
