@@ -60,6 +60,7 @@ struct Bucket {
   int32_t N = 0, SP = 1, SF = 1, cpw = 64;
   int64_t n_cands = 0, n_tiles = 0, max_f = 0, work = 0;
   int64_t xcd_off[9] = {};   // tiles of XCD x: xcd_off[x] .. xcd_off[x+1]-1
+  bool uni = false;          // split 1 and every tile holds one material: wave-uniform spectra loads
   double flops = 0;          // algorithmic FP64 work of one evaluation of the bucket
   std::vector<int32_t> mats;
   int32_t *d_lane_cand = nullptr, *d_lane_mat = nullptr, *d_mats = nullptr;
@@ -172,6 +173,13 @@ int build_tiles(debye_plan &p, Bucket &b) {
     b.xcd_off[x + 1] = (int64_t)lc.size() / b.cpw;
   }
   b.n_tiles = (int64_t)lc.size() / b.cpw;
+  b.uni = b.SP == 1 && b.SF == 1;
+  for (int64_t t = 0; b.uni && t < b.n_tiles; ++t)
+    for (int64_t l = t * b.cpw; l < (t + 1) * b.cpw; ++l)
+      if (lc[l] >= 0 && lm[l] != lm[t * b.cpw]) {
+        b.uni = false;
+        break;
+      }
   if (b.n_tiles == 0) return DEBYE_OK;
   if (hipMalloc(&b.d_lane_cand, lc.size() * 4) != hipSuccess || hipMalloc(&b.d_lane_mat, lm.size() * 4) != hipSuccess ||
       hipMalloc(&b.d_mats, b.mats.size() * 4) != hipSuccess)
@@ -470,33 +478,46 @@ int debye_plan_autotune(debye_plan *p, const debye_batch *b, const double *log10
     return cleanup(fail(DEBYE_ENOMEM, "autotune: cost buffer allocation failed"));
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return cleanup(fail(DEBYE_EHIP, "autotune: event creation failed"));
+  // time `reps` launches of a bucket at its current schedule
+  auto time_bucket = [&](Bucket &bk, int n, float *ms) -> int {
+    dfit::FitArgs a = fit_args(p, bk, b, log10_tau, ld, damping, flags);
+    a.cost = cost;
+    hipError_t e = hipEventRecord(e0, stream);
+    for (int r = 0; r < n && e == hipSuccess; ++r) e = dfit::launch_fit(bk.N, a, bk.n_tiles, false, bk.uni, stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    return e == hipSuccess ? DEBYE_OK : hip_fail(e, "autotune launch");
+  };
   for (Bucket &bk : p->buckets) {
     if (!bk.n_cands || p->sf_override.count(bk.N) || p->sf_override.count(0)) continue;
     const int64_t avg_f = bk.work / (bk.n_cands * bk.N);
-    int best_sf = 1;
-    float best_ms = INFINITY;
+    std::vector<int> splits;
     for (int sf = 1; sf <= 64 / bk.SP; sf *= 2) {
       if (sf > 1 && avg_f / sf < 8) break;
-      p->sf_tuned[bk.N] = sf;
-      if ((rc = build_tiles(*p, bk))) return cleanup(rc);
-      dfit::FitArgs a = fit_args(p, bk, b, log10_tau, ld, damping, flags);
-      a.cost = cost;
-      hipError_t e = dfit::launch_fit(bk.N, a, bk.n_tiles, false, stream);  // warm-up
-      if (e == hipSuccess) e = hipEventRecord(e0, stream);
-      for (int r = 0; r < reps && e == hipSuccess; ++r) e = dfit::launch_fit(bk.N, a, bk.n_tiles, false, stream);
-      if (e == hipSuccess) e = hipEventRecord(e1, stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) return cleanup(hip_fail(e, "autotune launch"));
-      // a wider split must win clearly (3 %): it costs reductions, and timing
-      // noise should not flip the schedule between runs
-      if (ms < 0.97f * best_ms) {
-        best_ms = ms;
-        best_sf = sf;
-      }
+      splits.push_back(sf);
     }
-    p->sf_tuned[bk.N] = best_sf;
+    // bring the clocks up first (about 30 ms of this bucket's work), so that
+    // the first split timed is not penalised
+    float ms = 0;
+    p->sf_tuned[bk.N] = splits[0];
+    if ((rc = build_tiles(*p, bk)) || (rc = time_bucket(bk, 1, &ms))) return cleanup(rc);
+    const int warm = std::min(200, std::max(1, (int)(30.0f / std::max(ms, 0.01f))));
+    if ((rc = time_bucket(bk, warm, &ms))) return cleanup(rc);
+    // two rounds over the splits, the best time of each
+    std::vector<float> best(splits.size(), INFINITY);
+    for (int round = 0; round < 2; ++round)
+      for (size_t i = 0; i < splits.size(); ++i) {
+        p->sf_tuned[bk.N] = splits[i];
+        if ((rc = build_tiles(*p, bk)) || (rc = time_bucket(bk, reps, &ms))) return cleanup(rc);
+        best[i] = std::min(best[i], ms);
+      }
+    // a wider split must win clearly (3 %): it costs reductions, and timing
+    // noise should not flip the schedule between runs
+    size_t pick = 0;
+    for (size_t i = 1; i < splits.size(); ++i)
+      if (best[i] < 0.97f * best[pick]) pick = i;
+    p->sf_tuned[bk.N] = splits[pick];
     if ((rc = build_tiles(*p, bk))) return cleanup(rc);
   }
   return cleanup(DEBYE_OK);
@@ -550,7 +571,7 @@ int debye_fit_eval(const debye_plan *p, const debye_batch *b, const double *log1
     a.weights = weights;
     a.eps_inf = eps_inf;
     a.status = status;
-    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, false, s), "debye_fit_eval launch");
+    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, false, bk.uni, s), "debye_fit_eval launch");
     return DEBYE_OK;
   });
 }
@@ -588,7 +609,7 @@ int debye_fit_eval_grad(const debye_plan *pc, const debye_batch *b, const double
     a.grad_theta = grad_log10_tau;
     a.record = targets ? p->d_record : nullptr;
     a.rec_ld = p->rec_ld;
-    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, true, s), "debye_fit_eval_grad launch");
+    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, true, false, s), "debye_fit_eval_grad launch");
     if (!targets) return DEBYE_OK;
     {
       dfit::TargetGradArgs t{};

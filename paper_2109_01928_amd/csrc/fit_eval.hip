@@ -271,20 +271,24 @@ __device__ __forceinline__ void unpark(const double *park, int cpw, int grp, dou
 // target waves per SIMD: bounds the register budget of each instantiation
 template <int N, int SP> constexpr int waves_per_simd() { return (SP == 1 && N <= 6) ? 3 : 2; }
 
-template <int N, int SP, bool GRAD>
+// UNI: every active lane of every tile belongs to one material and the
+// frequency split is 1 (the plan checks); the spectra are then read with
+// wave-uniform addresses.
+template <int N, int SP, bool GRAD, bool UNI>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_simd<N, SP>())))
 void fit_kernel(const FitArgs a) {
+  static_assert(!UNI || SP == 1, "uniform tiles use one lane per candidate");
   using S = Shape<N, SP>;
   constexpr int NB = S::NB, NV = S::NV, NG = S::NG, D = S::D;
   extern __shared__ double lds_all[];
 
   const int lane = threadIdx.x;
-  const int SF = a.freq_split;
+  const int SF = UNI ? 1 : a.freq_split;
   const int SL = SP * SF;            // lanes per candidate
   const int grp = lane / SL;         // candidate slot in the wave
   const int sub = lane - grp * SL;
   const int q = sub % SP;            // pole block
-  const int fl = sub / SP;           // frequency lane
+  const int fl = UNI ? 0 : sub / SP; // frequency lane
   // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
   // block b runs on XCD b % 8 as its (b / 8)-th block.  The plan gives every
   // XCD its own list of tiles (whole materials where possible, so that a
@@ -301,7 +305,11 @@ void fit_kernel(const FitArgs a) {
   const int64_t c = active ? cand : 0;
 
   int64_t f0 = 0, F = 0;
-  if (active) {
+  if constexpr (UNI) {
+    const int32_t mu = __builtin_amdgcn_readfirstlane(a.lane_mat[tile * a.cand_per_wave]);
+    f0 = a.f_off[mu];
+    F = a.f_off[mu + 1] - f0;
+  } else if (active) {
     f0 = a.f_off[mat];
     F = a.f_off[mat + 1] - f0;
   }
@@ -736,7 +744,7 @@ constexpr int pole_split_for(int n) { return n <= 8 ? 1 : (n <= 12 ? 2 : 4); }
 
 template <int N> int lds_bytes_per_cand() { return Shape<N, pole_split_for(N)>::LDS_DOUBLES * 8; }
 
-template <int N> hipError_t launch_fit_n(const FitArgs &a, int64_t n_tiles, bool grad, hipStream_t s) {
+template <int N> hipError_t launch_fit_n(const FitArgs &a, int64_t n_tiles, bool grad, bool uni, hipStream_t s) {
   constexpr int SP = pole_split_for(N);
   const size_t lds = (size_t)Shape<N, SP>::LDS_DOUBLES * 8 * a.cand_per_wave;
   FitArgs b = a;
@@ -746,9 +754,15 @@ template <int N> hipError_t launch_fit_n(const FitArgs &a, int64_t n_tiles, bool
   if (longest == 0) return hipSuccess;
   const unsigned blocks = (unsigned)(longest * 8);
   if (grad)
-    hipLaunchKernelGGL((fit_kernel<N, SP, true>), dim3(blocks), dim3(64), lds, s, b);
-  else
-    hipLaunchKernelGGL((fit_kernel<N, SP, false>), dim3(blocks), dim3(64), lds, s, b);
+    hipLaunchKernelGGL((fit_kernel<N, SP, true, false>), dim3(blocks), dim3(64), lds, s, b);
+  else if constexpr (SP == 1) {
+    if (uni && a.freq_split == 1)
+      hipLaunchKernelGGL((fit_kernel<N, SP, false, true>), dim3(blocks), dim3(64), lds, s, b);
+    else
+      hipLaunchKernelGGL((fit_kernel<N, SP, false, false>), dim3(blocks), dim3(64), lds, s, b);
+  } else {
+    hipLaunchKernelGGL((fit_kernel<N, SP, false, false>), dim3(blocks), dim3(64), lds, s, b);
+  }
   return hipGetLastError();
 }
 
@@ -769,9 +783,9 @@ template <int... Ns> struct Table {
     ((n == Ns ? (r = lds_bytes_per_cand<Ns>()) : 0), ...);
     return r;
   }
-  static hipError_t fit(int n, const FitArgs &a, int64_t tiles, bool grad, hipStream_t s) {
+  static hipError_t fit(int n, const FitArgs &a, int64_t tiles, bool grad, bool uni, hipStream_t s) {
     hipError_t e = hipErrorInvalidValue;
-    ((n == Ns ? (e = launch_fit_n<Ns>(a, tiles, grad, s)) : hipSuccess), ...);
+    ((n == Ns ? (e = launch_fit_n<Ns>(a, tiles, grad, uni, s)) : hipSuccess), ...);
     return e;
   }
   static hipError_t target(int n, const TargetGradArgs &a, int64_t max_f, int32_t n_mats, hipStream_t s) {
@@ -784,8 +798,8 @@ using AllN = Table<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18
 
 int pole_split(int n) { return AllN::pole_split(n); }
 int lds_bytes_per_candidate(int n) { return AllN::lds(n); }
-hipError_t launch_fit(int n, const FitArgs &a, int64_t n_tiles, bool grad, hipStream_t s) {
-  return AllN::fit(n, a, n_tiles, grad, s);
+hipError_t launch_fit(int n, const FitArgs &a, int64_t n_tiles, bool grad, bool uni, hipStream_t s) {
+  return AllN::fit(n, a, n_tiles, grad, uni, s);
 }
 hipError_t launch_target_grad(int n, const TargetGradArgs &a, int64_t max_f, int32_t n_mats, hipStream_t s) {
   return AllN::target(n, a, max_f, n_mats, s);
