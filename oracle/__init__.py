@@ -77,6 +77,7 @@ def lib():
                                    C.c_int32, _d, _d]
         L.orc_da_accept.argtypes = [C.c_int32, _i64, _i32, C.c_int64, C.c_double, C.c_double, C.c_double,
                                     C.c_uint64, C.c_int32, _d, _d, _d, _d, _d, _d, _i64, _d, C.c_int64]
+        L.orc_material_eval_idx.argtypes = [C.c_int32, _i8, _d, _i64, _d, C.c_uint64, _i64, _d, _d, C.c_int]
         L.orc_fit_cond_batch.argtypes = [C.c_int32, _i64, _i64, _i32, _d, _d, _d, _d, C.c_int64, C.c_double,
                                          C.c_uint32, _d, C.c_int]
         L.orc_num_threads.restype = C.c_int
@@ -125,6 +126,23 @@ def material_eval(kind, params, f_off, omega, noise_seed=0, jac=False, nthreads=
     if rc != 0:
         raise ValueError("material_eval: unknown material kind")
     return (er, ei, J) if jac else (er, ei)
+
+
+def material_eval_sample(kind, params, f_off, omega, mat_index, noise_seed=0, nthreads=0):
+    """Targets of a sample of a batch's materials: material m of the arguments
+    draws its noise as material mat_index[m] of the full batch."""
+    kind = np.ascontiguousarray(kind, dtype=np.int8)
+    params = _f64(params).reshape(-1, PARAM_STRIDE)
+    f_off = np.ascontiguousarray(f_off, dtype=np.int64)
+    idx = np.ascontiguousarray(mat_index, dtype=np.int64)
+    omega = _f64(omega)
+    er = np.empty(int(f_off[-1]))
+    ei = np.empty(int(f_off[-1]))
+    rc = lib().orc_material_eval_idx(len(kind), _p(kind, _i8), _p(params, _d), _p(f_off, _i64), _p(omega, _d),
+                                     C.c_uint64(noise_seed), _p(idx, _i64), _p(er, _d), _p(ei, _d), nthreads)
+    if rc != 0:
+        raise ValueError("material_eval: unknown material kind")
+    return er, ei
 
 
 def basis(omega, theta):

@@ -656,6 +656,22 @@ int orc_material_eval(int32_t M, const int8_t *kind, const double *params, const
   return bad ? -1 : 0;
 }
 
+// as orc_material_eval, material m drawing its noise as material mat_index[m]
+// of a larger batch (to evaluate a sample of that batch's materials)
+int orc_material_eval_idx(int32_t M, const int8_t *kind, const double *params, const int64_t *f_off,
+                          const double *omega, uint64_t noise_seed, const int64_t *mat_index, double *eps_re,
+                          double *eps_im, int nthreads) {
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic) num_threads(nthreads_or_default(nthreads)) reduction(| : bad)
+  for (int32_t m = 0; m < M; ++m) {
+    int64_t a = f_off[m], F = f_off[m + 1] - f_off[m];
+    if (material_one(kind[m], params + (size_t)m * PARAM_STRIDE, F, omega + a, noise_seed, mat_index[m],
+                     eps_re + a, eps_im + a, nullptr) != 0)
+      bad |= 1;
+  }
+  return bad ? -1 : 0;
+}
+
 int orc_basis(const double *omega, int64_t F, const double *theta, int32_t N, double *re_out,
               double *im_out) {
   for (int i = 0; i < N; ++i) {

@@ -198,3 +198,14 @@ def test_material_jacobian_matches_central_differences(orc, kind, p):
 def test_unknown_kind_rejected(orc):
     with pytest.raises(ValueError):
         orc.material_eval([9], np.zeros((1, 16)), [0, 3], np.ones(3))
+
+
+def test_material_sample_equals_full_batch_slices(orc):
+    wl = W.tables(M=40, F=64, iters=0)
+    er, ei = orc.material_eval(wl.kind, wl.params, wl.f_off, wl.omega, noise_seed=wl.noise_seed)
+    idx = np.array([3, 17, 39])
+    fo = np.arange(4) * 64
+    om = np.concatenate([wl.omega[wl.f_off[m]:wl.f_off[m + 1]] for m in idx])
+    e1, e2 = orc.material_eval_sample(wl.kind[idx], wl.params[idx], fo, om, idx, noise_seed=wl.noise_seed)
+    np.testing.assert_array_equal(e1, np.concatenate([er[wl.f_off[m]:wl.f_off[m + 1]] for m in idx]))
+    np.testing.assert_array_equal(e2, np.concatenate([ei[wl.f_off[m]:wl.f_off[m + 1]] for m in idx]))
