@@ -70,6 +70,10 @@ def main():
     ap.add_argument("--polish-steps", type=int, default=-1)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--per-material", type=int, default=0,
+                    help="also time the plain per-material loop (one material per launch sequence, forward only, "
+                         "same swarm) on this many materials until each reaches the batched run's final cost, "
+                         "capped at 10x the iterations, extrapolated to all materials")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default frequency splits")
     ap.add_argument("--freq-split", type=int, default=0,
                     help="fixed frequency split for every pole count (implies --no-autotune)")
@@ -292,7 +296,7 @@ def main():
     }
     # fit quality of the last step: average fractional error (Sec. IV) of each material's result
     b1t = b1.with_targets(er, ei)
-    _, w1, e1, _ = D.fit_eval(D.Plan(b1t), b1t, final[0])
+    c1, w1, e1, _ = D.fit_eval(D.Plan(b1t), b1t, final[0])
     afe = D.afe(b1t, final[0], w1, e1).cpu().numpy()
     line["fit_quality"] = {"afe_percent_median": float(np.median(afe)), "afe_percent_max": float(np.max(afe)),
                            "afe_below_5_percent": float(np.mean(afe < 5.0))}
@@ -302,6 +306,9 @@ def main():
         line["polish"] = {"median_rel_cost_drop": float(np.median(drop)), "min_rel_cost_drop": float(drop.min()),
                           "monotone": bool(np.all(np.diff(h, axis=1) <= 0))}
 
+    if args.per_material:
+        line["per_material_loop"] = per_material_loop(D, wl, er, ei, c1.cpu().numpy(), args, ms_per_step / 1e3)
+
     if not args.no_cpu_baseline:
         line["cpu_baseline"], line["parity_sample"] = cpu_leg(D, W, wl, bb, plan, args.cpu_seconds)
         # counted evaluations: only those within the parity tolerance (sampled rate)
@@ -309,6 +316,46 @@ def main():
         line["value_raw"] = value
         line["value"] = value * ps["within_1e-10"] / ps["candidates"]
     print(json.dumps(line), flush=True)
+
+
+def per_material_loop(D, wl, er, ei, target, args, batched_s):
+    """The plain per-material alternative to the batched fit: each material
+    alone (its own plan and swarm, forward evaluations only, the host reading
+    the best cost after every iteration) iterates until its best cost is within
+    1e-3 of the batched run's final (polished) cost, or 10x the iterations."""
+    import torch
+
+    cap = 10 * wl.iters
+    times, reached, iters_used = [], 0, []
+    for m in range(min(args.per_material, wl.M)):
+        f0, f1 = int(wl.f_off[m]), int(wl.f_off[m + 1])
+        P, N = int(wl.cand_off[m + 1] - wl.cand_off[m]), int(wl.n_poles[m])
+        bm = D.Batch([0, f1 - f0], [0, P], [N], wl.omega[f0:f1], er[f0:f1].contiguous(), ei[f0:f1].contiguous())
+        plan = D.Plan(bm)
+        sw = D.Swarm.empty(P, 1, N, cap + 2)
+        lbm = torch.tensor(wl.lb[m:m + 1], device="cuda")
+        ubm = torch.tensor(wl.ub[m:m + 1], device="cuda")
+        goal = target[m] * (1 + 1e-3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        D.pso_init(bm, lbm, ubm, sw, wl.inertia, wl.c1, wl.c2, wl.seed)
+        cost = D.fit_eval(plan, bm, sw.x, want_weights=False)[0]
+        t, best = 0, float("inf")
+        while best > goal and t < cap:
+            t += 1
+            D.pso_step(bm, lbm, ubm, sw, t, True, cost, wl.inertia, wl.c1, wl.c2, wl.seed)
+            cost = D.fit_eval(plan, bm, sw.x, want_weights=False)[0]
+            best = float(sw.gbest_cost.item())
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        reached += best <= goal
+        iters_used.append(t)
+    k = len(times)
+    est = float(np.mean(times)) * wl.M
+    return {"materials_timed": k, "extrapolated_s": est, "batched_step_s": batched_s,
+            "batched_speedup": est / batched_s, "reached_batched_cost": f"{reached}/{k}",
+            "median_iterations": float(np.median(iters_used)), "iteration_cap": cap,
+            "note": "extrapolated linearly from the timed materials; forward only (no adjoint polish)"}
 
 
 def make_workload(W, args):
