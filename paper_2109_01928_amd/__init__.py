@@ -31,6 +31,7 @@ PARAM_STRIDE = 16
 DEFAULT_DAMPING = 1e-8
 
 EXPORTED = ["debye_plan_create", "debye_plan_destroy", "debye_plan_set_freq_split", "debye_plan_autotune",
+            "debye_schedule_preview",
             "debye_plan_info",
             "debye_last_error", "debye_version", "debye_basis", "debye_fit_eval", "debye_fit_eval_grad",
             "debye_material_eval", "debye_material_vjp", "debye_pso_init", "debye_pso_step",
@@ -103,6 +104,7 @@ def lib():
     L.debye_plan_set_freq_split.argtypes = [_vp, i32, i32]
     L.debye_plan_info.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
     L.debye_plan_autotune.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, i32, _vp]
+    L.debye_schedule_preview.argtypes = [_vp, _vp, _vp, i32, i32, i32, i32, _vp, _vp, i64, _vp, _vp]
     L.debye_basis.argtypes = [_vp, i64, _vp, i64, i64, i32, _vp, _vp, _vp]
     L.debye_fit_eval.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, _vp, _vp, _vp, _vp, _vp]
     L.debye_fit_eval_grad.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -179,6 +181,26 @@ class Batch:
         b.__dict__.update(self.__dict__)
         b.eps_re, b.eps_im = eps_re.contiguous(), eps_im.contiguous()
         return b
+
+
+def schedule_preview(f_off, cand_off, mats, n_poles, pole_split, freq_split):
+    """Host-only preview of a bucket's work tiles (debye_schedule_preview):
+    (lane_cand, lane_mat, xcd_off, uniform); no GPU needed."""
+    f_off = np.ascontiguousarray(f_off, np.int64)
+    cand_off = np.ascontiguousarray(cand_off, np.int64)
+    mats = np.ascontiguousarray(mats, np.int32)
+    xo = np.zeros(9, np.int64)
+    uni = C.c_int32()
+    p = lambda a: a.ctypes.data_as(_vp)
+    n = lib().debye_schedule_preview(p(f_off), p(cand_off), p(mats), len(mats), n_poles, pole_split, freq_split,
+                                     None, None, 0, p(xo), C.byref(uni))
+    if n < 0:
+        _check(n)
+    lc = np.empty(n, np.int32)
+    lm = np.empty(n, np.int32)
+    _check(min(0, lib().debye_schedule_preview(p(f_off), p(cand_off), p(mats), len(mats), n_poles, pole_split,
+                                               freq_split, p(lc), p(lm), n, p(xo), C.byref(uni))))
+    return lc, lm, xo, bool(uni.value)
 
 
 class Plan:

@@ -122,64 +122,86 @@ int pick_split(const debye_plan &p, const Bucket &b) {
   return sf;
 }
 
-// Work tiles of a bucket and their split over the 8 XCDs.  Work items are
-// runs of one material's candidates (a material with more than 1/32 of the
-// bucket's tiles is cut into pieces, so that a few big swarms still spread
-// over the chip); the items, longest tiles first, go one by one to the XCD
-// with the least estimated work (LPT), which keeps a material's spectra in
-// one L2 and finishes the XCDs together.  Each XCD's candidates are packed
-// into tiles in that order (a tile may span two materials of the same XCD).
-int build_tiles(debye_plan &p, Bucket &b) {
-  free_bucket(b);
-  b.SF = pick_split(p, b);
-  b.cpw = 64 / (b.SP * b.SF);
+// Work tiles of a bucket and their split over the 8 XCDs (host only).  Work
+// items are runs of one material's candidates (a material with more than
+// 1/32 of the bucket's tiles is cut into pieces, so that a few big swarms
+// still spread over the chip); the items, longest tiles first, go one by one
+// to the XCD with the least estimated work (LPT), which keeps a material's
+// spectra in one L2 and finishes the XCDs together.  Each XCD's candidates
+// are packed into tiles in that order (a tile may span two materials of the
+// same XCD).  uni: split 1, one pole block, and every tile's candidates of
+// one material.
+struct Schedule {
+  std::vector<int32_t> lane_cand, lane_mat;
+  int64_t xcd_off[9] = {};
+  bool uni = false;
+};
+
+Schedule make_schedule(const int64_t *f_off, const int64_t *cand_off, const std::vector<int32_t> &mats, int N, int SP,
+                       int SF) {
+  const int cpw = 64 / (SP * SF);
   struct Item {
     int32_t m;
     int64_t c0, c1;   // candidates [c0, c1)
     double tile_t;    // estimated duration of one tile: points per lane plus the solve
   };
-  int64_t total_tiles = 0;
-  for (int32_t m : b.mats) total_tiles += (p.cand_off[m + 1] - p.cand_off[m] + b.cpw - 1) / b.cpw;
-  const int64_t max_item = std::max<int64_t>(1, total_tiles / 32) * b.cpw;  // candidates
+  int64_t total_tiles = 0, n_cands = 0;
+  for (int32_t m : mats) {
+    total_tiles += (cand_off[m + 1] - cand_off[m] + cpw - 1) / cpw;
+    n_cands += cand_off[m + 1] - cand_off[m];
+  }
+  const int64_t max_item = std::max<int64_t>(1, total_tiles / 32) * cpw;  // candidates
   std::vector<Item> items;
-  for (int32_t m : b.mats) {
-    const int64_t F = p.f_off[m + 1] - p.f_off[m];
-    const double t = (double)((F + b.SF - 1) / b.SF) + 0.05 * b.N * b.N;
-    for (int64_t c = p.cand_off[m]; c < p.cand_off[m + 1]; c += max_item)
-      items.push_back({m, c, std::min(c + max_item, p.cand_off[m + 1]), t});
+  for (int32_t m : mats) {
+    const int64_t F = f_off[m + 1] - f_off[m];
+    const double t = (double)((F + SF - 1) / SF) + 0.05 * N * N;
+    for (int64_t c = cand_off[m]; c < cand_off[m + 1]; c += max_item)
+      items.push_back({m, c, std::min(c + max_item, cand_off[m + 1]), t});
   }
   std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.tile_t > y.tile_t; });
   std::vector<std::vector<int32_t>> xc(8), xm(8);
   double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (const Item &it : items) {
     const int x = (int)(std::min_element(load, load + 8) - load);
-    load[x] += it.tile_t * (double)(it.c1 - it.c0) / b.cpw;
+    load[x] += it.tile_t * (double)(it.c1 - it.c0) / cpw;
     for (int64_t c = it.c0; c < it.c1; ++c) {
       xc[x].push_back((int32_t)c);
       xm[x].push_back(it.m);
     }
   }
-  std::vector<int32_t> lc, lm;
-  lc.reserve(b.n_cands + 8 * b.cpw);
-  lm.reserve(b.n_cands + 8 * b.cpw);
-  b.xcd_off[0] = 0;
+  Schedule sc;
+  std::vector<int32_t> &lc = sc.lane_cand, &lm = sc.lane_mat;
+  lc.reserve(n_cands + 8 * cpw);
+  lm.reserve(n_cands + 8 * cpw);
   for (int x = 0; x < 8; ++x) {
     lc.insert(lc.end(), xc[x].begin(), xc[x].end());
     lm.insert(lm.end(), xm[x].begin(), xm[x].end());
-    while (lc.size() % b.cpw) {
+    while (lc.size() % cpw) {
       lc.push_back(-1);
       lm.push_back(0);
     }
-    b.xcd_off[x + 1] = (int64_t)lc.size() / b.cpw;
+    sc.xcd_off[x + 1] = (int64_t)lc.size() / cpw;
   }
-  b.n_tiles = (int64_t)lc.size() / b.cpw;
-  b.uni = b.SP == 1 && b.SF == 1;
-  for (int64_t t = 0; b.uni && t < b.n_tiles; ++t)
-    for (int64_t l = t * b.cpw; l < (t + 1) * b.cpw; ++l)
-      if (lc[l] >= 0 && lm[l] != lm[t * b.cpw]) {
-        b.uni = false;
+  const int64_t n_tiles = (int64_t)lc.size() / cpw;
+  sc.uni = SP == 1 && SF == 1;
+  for (int64_t t = 0; sc.uni && t < n_tiles; ++t)
+    for (int64_t l = t * cpw; l < (t + 1) * cpw; ++l)
+      if (lc[l] >= 0 && lm[l] != lm[t * cpw]) {
+        sc.uni = false;
         break;
       }
+  return sc;
+}
+
+int build_tiles(debye_plan &p, Bucket &b) {
+  free_bucket(b);
+  b.SF = pick_split(p, b);
+  b.cpw = 64 / (b.SP * b.SF);
+  const Schedule sc = make_schedule(p.f_off.data(), p.cand_off.data(), b.mats, b.N, b.SP, b.SF);
+  for (int x = 0; x < 9; ++x) b.xcd_off[x] = sc.xcd_off[x];
+  b.uni = sc.uni;
+  const std::vector<int32_t> &lc = sc.lane_cand, &lm = sc.lane_mat;
+  b.n_tiles = (int64_t)lc.size() / b.cpw;
   if (b.n_tiles == 0) return DEBYE_OK;
   if (hipMalloc(&b.d_lane_cand, lc.size() * 4) != hipSuccess || hipMalloc(&b.d_lane_mat, lm.size() * 4) != hipSuccess ||
       hipMalloc(&b.d_mats, b.mats.size() * 4) != hipSuccess)
@@ -521,6 +543,28 @@ int debye_plan_autotune(debye_plan *p, const debye_batch *b, const double *log10
     if ((rc = build_tiles(*p, bk))) return cleanup(rc);
   }
   return cleanup(DEBYE_OK);
+}
+
+int debye_schedule_preview(const int64_t *f_off, const int64_t *cand_off, const int32_t *mats, int32_t n_mats,
+                           int32_t n_poles, int32_t pole_split, int32_t freq_split, int32_t *lane_cand,
+                           int32_t *lane_mat, int64_t capacity, int64_t *xcd_off, int32_t *uniform) {
+  if (!f_off || !cand_off || (n_mats > 0 && !mats) || !xcd_off || !uniform)
+    return fail(DEBYE_EINVAL, "NULL pointer");
+  if (n_mats < 0 || n_poles < 1 || n_poles > DEBYE_MAX_POLES || (pole_split != 1 && pole_split != 2 && pole_split != 4) ||
+      freq_split < 1 || freq_split * pole_split > 64 || (freq_split & (freq_split - 1)))
+    return fail(DEBYE_ERANGE, "schedule preview: bad sizes");
+  const std::vector<int32_t> ms(mats, mats + n_mats);
+  const Schedule sc = make_schedule(f_off, cand_off, ms, n_poles, pole_split, freq_split);
+  for (int x = 0; x < 9; ++x) xcd_off[x] = sc.xcd_off[x];
+  *uniform = sc.uni ? 1 : 0;
+  const int64_t n = (int64_t)sc.lane_cand.size();
+  if (lane_cand && lane_mat) {
+    if (capacity < n) return fail(DEBYE_ERANGE, "schedule preview: capacity %lld < %lld slots", (long long)capacity,
+                                  (long long)n);
+    std::copy(sc.lane_cand.begin(), sc.lane_cand.end(), lane_cand);
+    std::copy(sc.lane_mat.begin(), sc.lane_mat.end(), lane_mat);
+  }
+  return (int)std::min<int64_t>(n, INT32_MAX);
 }
 
 int debye_plan_info(const debye_plan *p, int32_t i, int32_t *n_poles, int32_t *pole_split, int32_t *freq_split,
