@@ -130,6 +130,23 @@ __device__ __forceinline__ void basis_point(double w, const double *tau, double 
   }
 }
 
+// The forward passes need only R: with I = w tau R, the factor tau moves out
+// of every frequency sum (applied once per candidate) and w out of every pole
+// sum (applied once per point), and 1 + x^2 is 1 + w^2 tau^2 with w^2 shared
+// by the poles and tau^2 by the points.  The rounding of d is the same as
+// through x = w tau (one product rounded, then a fused add).
+template <int NB>
+__device__ __forceinline__ void basis_R(double w2, const double *tau2, double *R) {
+#pragma unroll
+  for (int c = 0; c + 1 < NB; c += 2) {
+    const double d0 = __builtin_fma(w2, tau2[c], 1.0), d1 = __builtin_fma(w2, tau2[c + 1], 1.0);
+    const double r = rcp_nr(d0 * d1);
+    R[c] = d1 * r;
+    R[c + 1] = d0 * r;
+  }
+  if constexpr (NB & 1) R[NB - 1] = rcp_nr(__builtin_fma(w2, tau2[NB - 1], 1.0));
+}
+
 // --------------------------------------------------------------------------
 // Dense solve helpers on a packed upper triangle held in registers (SP == 1)
 // or in LDS (SP > 1).  A = U^T U, U upper, diagonal stored as reciprocals in uinv.
@@ -334,8 +351,13 @@ void fit_kernel(const FitArgs a) {
       tau[cI] = exp10(t);
     }
   }
+  double tau2[NB];
+#pragma unroll
+  for (int cI = 0; cI < NB; ++cI) tau2[cI] = tau[cI] * tau[cI];
 
-  // ---- pass 1: Gram, right-hand side, column sums of R, sum of eps'
+  // ---- pass 1: Gram, right-hand side, column sums of R, sum of eps'.
+  // Accumulated with U = w R in place of I = tau U; the factors tau are
+  // applied after the frequency sums.
   double G[NG], bv[NB], Sv[NB];
 #pragma unroll
   for (int e = 0; e < NG; ++e) G[e] = 0.0;
@@ -360,9 +382,10 @@ void fit_kernel(const FitArgs a) {
       er_n = epr[kn];
       ei_n = epi[kn];
       double Iv[NV], Rv[NB];
-      basis_point<NB>(w, tau, Rv, Iv);
+      basis_R<NB>(w * w, tau2, Rv);
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
+        Iv[cI] = w * Rv[cI];
         Sv[cI] += Rv[cI];
         bv[cI] = __builtin_fma(Iv[cI], ei, bv[cI]);
       }
@@ -384,9 +407,23 @@ void fit_kernel(const FitArgs a) {
   }
 #pragma unroll
   for (int e = 0; e < NG; ++e) G[e] = freq_sum(G[e], SP, SL);
+  if constexpr (SP > 1) {
+    double tv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) tv[v] = v < NB ? tau[v] : ring_fetch<SP>(tau[v % NB], v / NB);
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI)
+#pragma unroll
+      for (int d = 0; d <= D; ++d) G[cI * (D + 1) + d] *= tau[cI] * tv[cI + d];
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) G[tri(N, i, j)] *= tau[i] * tau[j];
+  }
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) {
-    bv[cI] = freq_sum(bv[cI], SP, SL);
+    bv[cI] = freq_sum(bv[cI], SP, SL) * tau[cI];
     Sv[cI] = freq_sum(Sv[cI], SP, SL);
     bad = bad || !(fabs(bv[cI]) < INFINITY);
   }
@@ -471,15 +508,19 @@ void fit_kernel(const FitArgs a) {
     gl[cI] = 0.0;
   }
   {
+    // I z = w sum_i (tau_i z_i) R_i, and I^T r = tau (R^T (w r))
+    double zs[NB];
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) zs[cI] = zc[cI] * tau[cI];
     auto step = [&](double w, double ei) {
-      double Iv[NB], Rv[NB];
-      basis_point<NB>(w, tau, Rv, Iv);
+      double Rv[NB];
+      basis_R<NB>(w * w, tau2, Rv);
       double part = 0.0;
 #pragma unroll
-      for (int cI = 0; cI < NB; ++cI) part = __builtin_fma(Iv[cI], zc[cI], part);
-      const double r = ei - group_sum<SP>(part);
+      for (int cI = 0; cI < NB; ++cI) part = __builtin_fma(Rv[cI], zs[cI], part);
+      const double wr = w * __builtin_fma(-w, group_sum<SP>(part), ei);
 #pragma unroll
-      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], Iv[cI], r);
+      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], Rv[cI], wr);
     };
     // two points per trip: the compensated sums then alternate between two
     // registers instead of being copied back every point
@@ -492,7 +533,7 @@ void fit_kernel(const FitArgs a) {
     if (k < F) step(om[k], epi[k]);
   }
 #pragma unroll
-  for (int cI = 0; cI < NB; ++cI) gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL);
+  for (int cI = 0; cI < NB; ++cI) gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL) * tau[cI];
 
   // correction: zt += A^-1 (D^-1 g - damping zt)
   if constexpr (SP == 1) {
@@ -533,9 +574,11 @@ void fit_kernel(const FitArgs a) {
 
   // ---- pass 3: residuals and cost (+ g_w for the adjoint)
   double cost = 0.0;
-  double gw[GRAD ? NB : 1];
+  double gw[GRAD ? NB : 1], gw2[GRAD ? NB : 1], wt[NB];
 #pragma unroll
-  for (int cI = 0; cI < (GRAD ? NB : 1); ++cI) gw[cI] = 0.0;
+  for (int cI = 0; cI < (GRAD ? NB : 1); ++cI) gw[cI] = gw2[cI] = 0.0;
+#pragma unroll
+  for (int cI = 0; cI < NB; ++cI) wt[cI] = wv_[cI] * tau[cI];
   {
     int64_t k = fl;
     double w_n = 0, er_n = 0, ei_n = 0;
@@ -550,21 +593,26 @@ void fit_kernel(const FitArgs a) {
       w_n = om[kn];
       er_n = epr[kn];
       ei_n = epi[kn];
-      double Rv[NB], Iv[NB];
-      basis_point<NB>(w, tau, Rv, Iv);
+      double Rv[NB];
+      basis_R<NB>(w * w, tau2, Rv);
       double pr = 0.0, pi = 0.0;
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
         pr = __builtin_fma(wv_[cI], Rv[cI], pr);
-        pi = __builtin_fma(wv_[cI], Iv[cI], pi);
+        pi = __builtin_fma(wt[cI], Rv[cI], pi);
       }
       const double rr = (er - einf) - group_sum<SP>(pr);
-      const double ri = ei - group_sum<SP>(pi);
+      const double ri = __builtin_fma(-w, group_sum<SP>(pi), ei);
       cost = __builtin_fma(rr, rr, cost);
       cost = __builtin_fma(ri, ri, cost);
       if constexpr (GRAD) {
+        // g_w = R^T r' + I^T r'' = R^T r' + tau (R^T (w r''))
+        const double wri = w * ri;
 #pragma unroll
-        for (int cI = 0; cI < NB; ++cI) gw[cI] = __builtin_fma(Rv[cI], rr, __builtin_fma(Iv[cI], ri, gw[cI]));
+        for (int cI = 0; cI < NB; ++cI) {
+          gw[cI] = __builtin_fma(Rv[cI], rr, gw[cI]);
+          gw2[cI] = __builtin_fma(Rv[cI], wri, gw2[cI]);
+        }
       }
     }
   }
@@ -594,7 +642,7 @@ void fit_kernel(const FitArgs a) {
     double mt[NB], mu[NB];
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) {
-      gw[cI] = -2.0 * freq_sum(gw[cI], SP, SL);
+      gw[cI] = -2.0 * __builtin_fma(tau[cI], freq_sum(gw2[cI], SP, SL), freq_sum(gw[cI], SP, SL));
       const double s = (flip && zc[cI] < 0.0) ? -1.0 : 1.0;
       mt[cI] = s * gw[cI] * invd_own[cI];
     }
