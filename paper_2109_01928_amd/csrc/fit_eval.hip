@@ -512,25 +512,42 @@ void fit_kernel(const FitArgs a) {
     double zs[NB];
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) zs[cI] = zc[cI] * tau[cI];
-    auto step = [&](double w, double ei) {
-      double Rv[NB];
+    // R at point k and w_k r_k
+    auto resid = [&](double w, double ei, double *Rv) {
       basis_R<NB>(w * w, tau2, Rv);
       double part = 0.0;
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) part = __builtin_fma(Rv[cI], zs[cI], part);
-      const double wr = w * __builtin_fma(-w, group_sum<SP>(part), ei);
-#pragma unroll
-      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], Rv[cI], wr);
+      return w * __builtin_fma(-w, group_sum<SP>(part), ei);
     };
-    // two points per trip: the compensated sums then alternate between two
-    // registers instead of being copied back every point
+    // The compensated sum takes the terms of two points at a time, their sum
+    // formed with one fused multiply-add (at most two roundings of terms of
+    // the same two points, so the error bound stays a small multiple of the
+    // roundoff of the terms' magnitudes).
+    auto pair = [&](int64_t k0) {
+      const double w0 = om[k0], e0 = epi[k0], w1 = om[k0 + SF], e1 = epi[k0 + SF];
+      double R0[NB], R1[NB];
+      const double wr0 = resid(w0, e0, R0), wr1 = resid(w1, e1, R1);
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], 1.0, __builtin_fma(R1[cI], wr1, R0[cI] * wr0));
+    };
+    // two pairs per trip: the compensated sums then alternate between two
+    // registers instead of being copied back every update
     int64_t k = fl;
-    for (; k + SF < F; k += 2 * SF) {
-      const double w0 = om[k], e0 = epi[k], w1 = om[k + SF], e1 = epi[k + SF];
-      step(w0, e0);
-      step(w1, e1);
+    for (; k + 3 * SF < F; k += 4 * SF) {
+      pair(k);
+      pair(k + 2 * SF);
     }
-    if (k < F) step(om[k], epi[k]);
+    if (k + SF < F) {
+      pair(k);
+      k += 2 * SF;
+    }
+    if (k < F) {
+      double R0[NB];
+      const double wr0 = resid(om[k], epi[k], R0);
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], R0[cI], wr0);
+    }
   }
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL) * tau[cI];
