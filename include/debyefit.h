@@ -119,7 +119,9 @@ int debye_plan_destroy(debye_plan *plan);
 
 /* Override the schedule's frequency split (lanes per candidate along the
  * frequency axis, a power of two; 0 restores the automatic choice) for pole
- * count n_poles (0 = all). Used by the autotuner and the tests. */
+ * count n_poles (0 = all). Used by the autotuner and the tests.  Re-tiling
+ * (here or in debye_plan_autotune) makes the plan's next optimiser run
+ * re-capture its graph.  Not while work of the plan is in flight. */
 int debye_plan_set_freq_split(debye_plan *plan, int32_t n_poles, int32_t split);
 
 /* Autotune the schedule on real data: for every pole-count bucket without an

@@ -85,6 +85,7 @@ struct debye_plan {
   std::vector<Bucket> buckets;
   std::map<int32_t, int32_t> sf_override;  // N (0 = all) -> frequency split
   std::map<int32_t, int32_t> sf_tuned;     // N -> split measured fastest by debye_plan_autotune
+  uint64_t sched_gen = 0;                  // bumped by every tile rebuild; part of every graph key
   double *d_record = nullptr;
   int64_t rec_ld = 0;
   // fork/join of the buckets over side streams: bucket i runs on side[lane_of[i]]
@@ -194,6 +195,8 @@ Schedule make_schedule(const int64_t *f_off, const int64_t *cand_off, const std:
 }
 
 int build_tiles(debye_plan &p, Bucket &b) {
+  // captured graphs hold the old tile buffers: the new generation keys them out
+  ++p.sched_gen;
   free_bucket(b);
   b.SF = pick_split(p, b);
   b.cpw = 64 / (b.SP * b.SF);
@@ -834,6 +837,7 @@ int debye_pso_run(const debye_plan *pc, const debye_batch *b, int64_t ld, const 
     key.put(damping);
     key.put(flags);
     key.put(*sw);
+    key.put(plan->sched_gen);
     rc = graph_replay(g, key.v, 1, iters, [&](hipStream_t gs, int32_t *counter) -> int {
       dfit::PsoArgs a = pso_args(b, ld, lb, ub, p, 0, 1, sw);
       a.t_dev = counter;
@@ -985,6 +989,7 @@ int debye_de_run(const debye_plan *pc, const debye_batch *b, int64_t ld, const d
   key.put(damping);
   key.put(flags);
   key.put(*pop);
+  key.put(pc->sched_gen);
   rc = graph_replay(g, key.v, 1, iters, [&](hipStream_t gs, int32_t *counter) { return generation(gs, 0, counter); });
   if (rc) return rc;
   return graph_leave(g, stream);
@@ -1126,6 +1131,7 @@ int debye_da_run(const debye_plan *pc, const debye_batch *b, int64_t ld, const d
   key.put(damping);
   key.put(flags);
   key.put(*pop);
+  key.put(pc->sched_gen);
   rc = graph_replay(g, key.v, 1, iters, [&](hipStream_t gs, int32_t *counter) { return generation(gs, 0, counter); });
   if (rc) return rc;
   return graph_leave(g, stream);

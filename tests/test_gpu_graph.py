@@ -75,6 +75,36 @@ def test_graph_replay_equals_eager(D, orc, which):
         assert torch.isfinite(junk).any()
 
 
+def test_graph_recaptured_after_schedule_change(D, orc):
+    """A plan re-tiled (new split, autotune) after a captured swarm fit must
+    not replay the old graph: the replay equals an eager fit on the new
+    schedule."""
+    import torch
+    wl = small_ragged(20, seed=21, Fr=(40, 300), Nr=(3, 12), Pr=(16, 100))
+    er, ei = targets_oracle(orc, wl)
+    b = D.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, _t(er), _t(ei))
+    plan = D.Plan(b)
+    lb, ub = _t(wl.lb), _t(wl.ub)
+    iters = 6
+    sw = D.Swarm.empty(wl.P, wl.M, wl.ld, iters + 1)
+    D.pso_run(plan, b, lb, ub, sw, iters, seed=3, use_graph=True)
+    theta = _t(W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, 8))
+    for change in ("split", "autotune", "split back"):
+        if change == "split":
+            plan.set_freq_split(4)
+        elif change == "autotune":
+            plan.set_freq_split(0)   # back to automatic, then measured
+            plan.autotune(b, theta, reps=1)
+        else:
+            plan.set_freq_split(1)
+        sw_e = D.Swarm.empty(wl.P, wl.M, wl.ld, iters + 1)
+        ce = D.pso_run(plan, b, lb, ub, sw_e, iters, seed=3, use_graph=False)
+        ref = _snapshot(sw_e, ce)
+        c = D.pso_run(plan, b, lb, ub, sw, iters, seed=3, use_graph=True)
+        _equal(ref, _snapshot(sw, c))
+        torch.cuda.synchronize()
+
+
 def test_gpu_swarm_fit_matches_oracle_swarm(D, orc):
     wl = W.single_hn()
     er, ei = targets_oracle(orc, wl)
