@@ -104,37 +104,17 @@ __device__ __forceinline__ double freq_sum_dd(double hi, double lo, int sp, int 
 
 // --------------------------------------------------------------------------
 // Debye basis of the owned poles at one frequency: R = 1/(1+x^2), I = x R.
-// Two poles share one reciprocal: r = 1/(d0 d1), R0 = d1 r, R1 = d0 r (within
-// a few ulp; the hardware reciprocal costs four fused multiply-adds).  With
-// |log10 tau| <= 30 (larger values are rejected as bad input) and w < 1e45
-// rad/s, x < 1e75 and the product d0 d1 < 1e301 cannot overflow.
-// Padded poles have tau = 0: x = 0, R = 1, I = 0.
-// --------------------------------------------------------------------------
-template <int NB>
-__device__ __forceinline__ void basis_point(double w, const double *tau, double *R, double *I) {
-#pragma unroll
-  for (int c = 0; c + 1 < NB; c += 2) {
-    const double x0 = w * tau[c], x1 = w * tau[c + 1];
-    const double d0 = __builtin_fma(x0, x0, 1.0), d1 = __builtin_fma(x1, x1, 1.0);
-    const double r = rcp_nr(d0 * d1);
-    const double r0 = d1 * r, r1 = d0 * r;
-    R[c] = r0;
-    R[c + 1] = r1;
-    I[c] = x0 * r0;
-    I[c + 1] = x1 * r1;
-  }
-  if constexpr (NB & 1) {
-    const double x = w * tau[NB - 1];
-    R[NB - 1] = rcp_nr(__builtin_fma(x, x, 1.0));
-    I[NB - 1] = x * R[NB - 1];
-  }
-}
-
-// The forward passes need only R: with I = w tau R, the factor tau moves out
-// of every frequency sum (applied once per candidate) and w out of every pole
+// Every pass needs only R: with I = w tau R, the factor tau moves out of
+// every frequency sum (applied once per candidate) and w out of every pole
 // sum (applied once per point), and 1 + x^2 is 1 + w^2 tau^2 with w^2 shared
-// by the poles and tau^2 by the points.  The rounding of d is the same as
-// through x = w tau (one product rounded, then a fused add).
+// by the poles and tau^2 by the points (the rounding of d is the same as
+// through x = w tau: one product rounded, then a fused add).  Two poles share
+// one reciprocal: r = 1/(d0 d1), R0 = d1 r, R1 = d0 r (within a few ulp; the
+// hardware reciprocal costs about 2.5 fused multiply-adds).  With
+// |log10 tau| <= 30 (larger values are rejected as bad input) and w < 1e45
+// rad/s, x < 1e75 and the product d0 d1 < 1e301 cannot overflow.  Padded
+// poles have tau = 0: R = 1, and their I columns vanish through tau.
+// --------------------------------------------------------------------------
 template <int NB>
 __device__ __forceinline__ void basis_R(double w2, const double *tau2, double *R) {
 #pragma unroll
@@ -687,10 +667,17 @@ void fit_kernel(const FitArgs a) {
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) mu[cI] = mt[cI] * invd_own[cI];
 
-    // ---- pass 4: basis derivatives against the residuals
-    double T1[NB], T2[NB], T3[NB], T4[NB];
+    // ---- pass 4: basis derivatives against the residuals.  With x^2 R = 1 - R,
+    // dR/dtheta = -2 ln10 I^2 and dI/dtheta = ln10 I (2R - 1); ln10 is applied
+    // after the sums, and the dot products run over R with tau-scaled weights
+    // as in the forward passes.
+    double T1[NB], T2[NB], T3[NB], T4[NB], zt4[NB], mt4[NB];
 #pragma unroll
-    for (int cI = 0; cI < NB; ++cI) T1[cI] = T2[cI] = T3[cI] = T4[cI] = 0.0;
+    for (int cI = 0; cI < NB; ++cI) {
+      T1[cI] = T2[cI] = T3[cI] = T4[cI] = 0.0;
+      zt4[cI] = zc[cI] * tau[cI];
+      mt4[cI] = mu[cI] * tau[cI];
+    }
     {
       int64_t k = fl;
       double w_n = 0, er_n = 0, ei_n = 0;
@@ -705,40 +692,39 @@ void fit_kernel(const FitArgs a) {
         w_n = om[kn];
         er_n = epr[kn];
         ei_n = epi[kn];
-        double xv[NB], Rv[NB], Iv[NB];
-        basis_point<NB>(w, tau, Rv, Iv);
+        double Rv[NB];
+        basis_R<NB>(w * w, tau2, Rv);
         double pr = 0.0, pi = 0.0, pz = 0.0, pm = 0.0;
 #pragma unroll
         for (int cI = 0; cI < NB; ++cI) {
-          xv[cI] = w * tau[cI];
           pr = __builtin_fma(wv_[cI], Rv[cI], pr);
-          pi = __builtin_fma(wv_[cI], Iv[cI], pi);
-          pz = __builtin_fma(zc[cI], Iv[cI], pz);
-          pm = __builtin_fma(mu[cI], Iv[cI], pm);
+          pi = __builtin_fma(wt[cI], Rv[cI], pi);
+          pz = __builtin_fma(zt4[cI], Rv[cI], pz);
+          pm = __builtin_fma(mt4[cI], Rv[cI], pm);
         }
         const double rr = (er - einf) - group_sum<SP>(pr);
-        const double ri = ei - group_sum<SP>(pi);
-        const double qz = ei - group_sum<SP>(pz);
-        const double qm = group_sum<SP>(pm);
+        const double ri = __builtin_fma(-w, group_sum<SP>(pi), ei);
+        const double qz = __builtin_fma(-w, group_sum<SP>(pz), ei);
+        const double qm = w * group_sum<SP>(pm);
+        const double m2rr = -2.0 * rr;
 #pragma unroll
         for (int cI = 0; cI < NB; ++cI) {
-          const double x = xv[cI], R = Rv[cI];
-          const double R2 = R * R;
-          const double dR = -2.0 * LN10 * (x * x) * R2;
-          const double dI = LN10 * x * R2 * (1.0 - x * x);
-          T1[cI] = __builtin_fma(dR, rr, __builtin_fma(dI, ri, T1[cI]));
+          const double R = Rv[cI];
+          const double I = (w * tau[cI]) * R;
+          const double dI = I * __builtin_fma(2.0, R, -1.0);
+          T1[cI] = __builtin_fma(I * m2rr, I, __builtin_fma(dI, ri, T1[cI]));
           T2[cI] = __builtin_fma(dI, qz, T2[cI]);
           T3[cI] = __builtin_fma(dI, qm, T3[cI]);
-          T4[cI] = __builtin_fma(dI, Iv[cI], T4[cI]);
+          T4[cI] = __builtin_fma(dI, I, T4[cI]);
         }
       }
     }
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) {
-      T1[cI] = freq_sum(T1[cI], SP, SL);
-      T2[cI] = freq_sum(T2[cI], SP, SL);
-      T3[cI] = freq_sum(T3[cI], SP, SL);
-      T4[cI] = freq_sum(T4[cI], SP, SL);
+      T1[cI] = LN10 * freq_sum(T1[cI], SP, SL);
+      T2[cI] = LN10 * freq_sum(T2[cI], SP, SL);
+      T3[cI] = LN10 * freq_sum(T3[cI], SP, SL);
+      T4[cI] = LN10 * freq_sum(T4[cI], SP, SL);
     }
     if (writer) {
 #pragma unroll
