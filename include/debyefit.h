@@ -146,8 +146,9 @@ int debye_plan_autotune(debye_plan *plan, const debye_batch *b, const double *lo
  * each) it writes every wave's slots, 64 / (pole_split * freq_split) per
  * tile, candidate index or -1 and its material; xcd_off [9]: the tiles of
  * XCD x are xcd_off[x] .. xcd_off[x+1]-1; *uniform: 1 when every tile's
- * candidates belong to one material at split 1 and one pole block.  Returns
- * the number of slots (>= 0) or a negative error code. */
+ * candidates belong to one material (the kernels then read the spectra with
+ * wave-uniform addresses).  Returns the number of slots (>= 0) or a negative
+ * error code. */
 int debye_schedule_preview(const int64_t *f_off, const int64_t *cand_off, const int32_t *mats, int32_t n_mats,
                            int32_t n_poles, int32_t pole_split, int32_t freq_split, int32_t *lane_cand,
                            int32_t *lane_mat, int64_t capacity, int64_t *xcd_off, int32_t *uniform);

@@ -130,8 +130,8 @@ int pick_split(const debye_plan &p, const Bucket &b) {
 // to the XCD with the least estimated work (LPT), which keeps a material's
 // spectra in one L2 and finishes the XCDs together.  Each XCD's candidates
 // are packed into tiles in that order (a tile may span two materials of the
-// same XCD).  uni: split 1, one pole block, and every tile's candidates of
-// one material.
+// same XCD).  uni: every tile's candidates of one material (and spectra of
+// fewer than 2^29 points).
 struct Schedule {
   std::vector<int32_t> lane_cand, lane_mat;
   int64_t xcd_off[9] = {};
@@ -184,7 +184,9 @@ Schedule make_schedule(const int64_t *f_off, const int64_t *cand_off, const std:
     sc.xcd_off[x + 1] = (int64_t)lc.size() / cpw;
   }
   const int64_t n_tiles = (int64_t)lc.size() / cpw;
-  sc.uni = SP == 1 && SF == 1;
+  sc.uni = true;
+  for (int32_t m : mats)
+    if (f_off[m + 1] - f_off[m] >= ((int64_t)1 << 29)) sc.uni = false;  // 32-bit byte offsets
   for (int64_t t = 0; sc.uni && t < n_tiles; ++t)
     for (int64_t l = t * cpw; l < (t + 1) * cpw; ++l)
       if (lc[l] >= 0 && lm[l] != lm[t * cpw]) {

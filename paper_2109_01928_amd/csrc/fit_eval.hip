@@ -268,24 +268,26 @@ __device__ __forceinline__ void unpark(const double *park, int cpw, int grp, dou
 // target waves per SIMD: bounds the register budget of each instantiation
 template <int N, int SP> constexpr int waves_per_simd() { return (SP == 1 && N <= 6) ? 3 : 2; }
 
-// UNI: every active lane of every tile belongs to one material and the
-// frequency split is 1 (the plan checks); the spectra are then read with
-// wave-uniform addresses.
-template <int N, int SP, bool GRAD, bool UNI>
+// UNI (uniform tiles; the plan checks that every active lane of every tile
+// belongs to one material and that spectra hold fewer than 2^29 points):
+//   1: frequency split 1, so every lane of a wave reads the same point and
+//      the spectra are read with wave-uniform (scalar) loads;
+//   2: frequency split > 1: wave-uniform spectrum base, per-lane 32-bit
+//      byte offsets (one offset per point for the three arrays).
+template <int N, int SP, bool GRAD, int UNI>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_simd<N, SP>())))
 void fit_kernel(const FitArgs a) {
-  static_assert(!UNI || SP == 1, "uniform tiles use one lane per candidate");
   using S = Shape<N, SP>;
   constexpr int NB = S::NB, NV = S::NV, NG = S::NG, D = S::D;
   extern __shared__ double lds_all[];
 
   const int lane = threadIdx.x;
-  const int SF = UNI ? 1 : a.freq_split;
+  const int SF = UNI == 1 ? 1 : a.freq_split;
   const int SL = SP * SF;            // lanes per candidate
   const int grp = lane / SL;         // candidate slot in the wave
   const int sub = lane - grp * SL;
   const int q = sub % SP;            // pole block
-  const int fl = UNI ? 0 : sub / SP; // frequency lane
+  const int fl = UNI == 1 ? 0 : sub / SP; // frequency lane
   // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
   // block b runs on XCD b % 8 as its (b / 8)-th block.  The plan gives every
   // XCD its own list of tiles (whole materials where possible, so that a
@@ -302,7 +304,7 @@ void fit_kernel(const FitArgs a) {
   const int64_t c = active ? cand : 0;
 
   int64_t f0 = 0, F = 0;
-  if constexpr (UNI) {
+  if constexpr (UNI != 0) {
     const int32_t mu = __builtin_amdgcn_readfirstlane(a.lane_mat[tile * a.cand_per_wave]);
     f0 = a.f_off[mu];
     F = a.f_off[mu + 1] - f0;
@@ -313,6 +315,11 @@ void fit_kernel(const FitArgs a) {
   const double *om = a.omega + f0;
   const double *epr = a.eps_re + f0;
   const double *epi = a.eps_im + f0;
+  // point k of a spectrum
+  auto ld = [](const double *p, int64_t k) -> double {
+    if constexpr (UNI == 2) return *(const double *)((const char *)p + ((uint32_t)k << 3));
+    else return p[k];
+  };
   const double damping = a.damping;
   const bool flip = !(a.flags & FLAG_NO_SIGN_FLIP);
 
@@ -351,16 +358,16 @@ void fit_kernel(const FitArgs a) {
     int64_t k = fl;
     double w_n = 0, er_n = 0, ei_n = 0;
     if (k < F) {
-      w_n = om[k];
-      er_n = epr[k];
-      ei_n = epi[k];
+      w_n = ld(om, k);
+      er_n = ld(epr, k);
+      ei_n = ld(epi, k);
     }
     for (; k < F; k += SF) {
       const double w = w_n, er = er_n, ei = ei_n;
       const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
-      w_n = om[kn];
-      er_n = epr[kn];
-      ei_n = epi[kn];
+      w_n = ld(om, kn);
+      er_n = ld(epr, kn);
+      ei_n = ld(epi, kn);
       double Iv[NV], Rv[NB];
       basis_R<NB>(w * w, tau2, Rv);
 #pragma unroll
@@ -505,7 +512,7 @@ void fit_kernel(const FitArgs a) {
     // the same two points, so the error bound stays a small multiple of the
     // roundoff of the terms' magnitudes).
     auto pair = [&](int64_t k0) {
-      const double w0 = om[k0], e0 = epi[k0], w1 = om[k0 + SF], e1 = epi[k0 + SF];
+      const double w0 = ld(om, k0), e0 = ld(epi, k0), w1 = ld(om, k0 + SF), e1 = ld(epi, k0 + SF);
       double R0[NB], R1[NB];
       const double wr0 = resid(w0, e0, R0), wr1 = resid(w1, e1, R1);
 #pragma unroll
@@ -524,7 +531,7 @@ void fit_kernel(const FitArgs a) {
     }
     if (k < F) {
       double R0[NB];
-      const double wr0 = resid(om[k], epi[k], R0);
+      const double wr0 = resid(ld(om, k), ld(epi, k), R0);
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], R0[cI], wr0);
     }
@@ -580,16 +587,16 @@ void fit_kernel(const FitArgs a) {
     int64_t k = fl;
     double w_n = 0, er_n = 0, ei_n = 0;
     if (k < F) {
-      w_n = om[k];
-      er_n = epr[k];
-      ei_n = epi[k];
+      w_n = ld(om, k);
+      er_n = ld(epr, k);
+      ei_n = ld(epi, k);
     }
     for (; k < F; k += SF) {
       const double w = w_n, er = er_n, ei = ei_n;
       const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
-      w_n = om[kn];
-      er_n = epr[kn];
-      ei_n = epi[kn];
+      w_n = ld(om, kn);
+      er_n = ld(epr, kn);
+      ei_n = ld(epi, kn);
       double Rv[NB];
       basis_R<NB>(w * w, tau2, Rv);
       double pr = 0.0, pi = 0.0;
@@ -682,16 +689,16 @@ void fit_kernel(const FitArgs a) {
       int64_t k = fl;
       double w_n = 0, er_n = 0, ei_n = 0;
       if (k < F) {
-        w_n = om[k];
-        er_n = epr[k];
-        ei_n = epi[k];
+        w_n = ld(om, k);
+        er_n = ld(epr, k);
+        ei_n = ld(epi, k);
       }
       for (; k < F; k += SF) {
         const double w = w_n, er = er_n, ei = ei_n;
         const int64_t kn = (k + SF < F) ? k + SF : k;
-        w_n = om[kn];
-        er_n = epr[kn];
-        ei_n = epi[kn];
+        w_n = ld(om, kn);
+        er_n = ld(epr, kn);
+        ei_n = ld(epi, kn);
         double Rv[NB];
         basis_R<NB>(w * w, tau2, Rv);
         double pr = 0.0, pi = 0.0, pz = 0.0, pm = 0.0;
@@ -805,15 +812,13 @@ template <int N> hipError_t launch_fit_n(const FitArgs &a, int64_t n_tiles, bool
   if (longest == 0) return hipSuccess;
   const unsigned blocks = (unsigned)(longest * 8);
   if (grad)
-    hipLaunchKernelGGL((fit_kernel<N, SP, true, false>), dim3(blocks), dim3(64), lds, s, b);
-  else if constexpr (SP == 1) {
-    if (uni && a.freq_split == 1)
-      hipLaunchKernelGGL((fit_kernel<N, SP, false, true>), dim3(blocks), dim3(64), lds, s, b);
-    else
-      hipLaunchKernelGGL((fit_kernel<N, SP, false, false>), dim3(blocks), dim3(64), lds, s, b);
-  } else {
-    hipLaunchKernelGGL((fit_kernel<N, SP, false, false>), dim3(blocks), dim3(64), lds, s, b);
-  }
+    hipLaunchKernelGGL((fit_kernel<N, SP, true, 0>), dim3(blocks), dim3(64), lds, s, b);
+  else if (uni && a.freq_split == 1)
+    hipLaunchKernelGGL((fit_kernel<N, SP, false, 1>), dim3(blocks), dim3(64), lds, s, b);
+  else if (uni)
+    hipLaunchKernelGGL((fit_kernel<N, SP, false, 2>), dim3(blocks), dim3(64), lds, s, b);
+  else
+    hipLaunchKernelGGL((fit_kernel<N, SP, false, 0>), dim3(blocks), dim3(64), lds, s, b);
   return hipGetLastError();
 }
 

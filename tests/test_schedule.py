@@ -2,7 +2,7 @@
 (debye_schedule_preview, host only): every candidate sits in exactly one wave
 slot with its own material, padding only closes an XCD's last tile, the
 estimated work per XCD is balanced, and the uniform-tile form (one material
-per wave) is detected exactly when it holds."""
+per wave, at any split) is detected exactly when it holds."""
 import numpy as np
 import pytest
 
@@ -93,9 +93,12 @@ def test_uniform_detection():
     lc, lm, xo, uni = D.schedule_preview(_offsets([100] * 16), _offsets([100] * 16), range(16), 5, 1, 1)
     assert not uni
     assert any(len(set(lm[t * 64:(t + 1) * 64][lc[t * 64:(t + 1) * 64] >= 0].tolist())) > 1 for t in range(xo[8]))
-    # frequency or pole split: never the uniform form
-    assert not D.schedule_preview(f_off, _offsets([128] * 4), range(4), 5, 1, 2)[3]
-    assert not D.schedule_preview(f_off, _offsets([128] * 4), range(4), 12, 2, 1)[3]
+    # with a frequency or pole split, whole waves of one material too
+    assert D.schedule_preview(f_off, _offsets([128] * 4), range(4), 5, 1, 2)[3]
+    assert D.schedule_preview(f_off, _offsets([128] * 4), range(4), 12, 2, 1)[3]
+    assert D.schedule_preview(f_off, _offsets([48] * 4), range(4), 20, 4, 4)[3]
+    # 16 x 12 candidates at 8 per wave: pieces of 4 share waves
+    assert not D.schedule_preview(_offsets([100] * 16), _offsets([12] * 16), range(16), 20, 4, 2)[3]
     # one material padded to a whole wave is still uniform
     assert D.schedule_preview(_offsets([100]), _offsets([10]), [0], 5, 1, 1)[3]
 
