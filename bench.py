@@ -290,8 +290,9 @@ def main():
         "schedule": {f"N{i['n_poles']}": f"{i['pole_split']}x{i['freq_split']} lanes" for i in plan.info()},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
-                     "kernel": f"fit_kernel<{N},{1 if N <= 8 else (2 if N <= 12 else 4)},false>" if uniform
-                     else "fit_kernel (all pole-count buckets of one evaluation)",
+                     "kernel": (f"fit_kernel<{N},{plan.info()[0]['pole_split']},false,"
+                                f"{(1 if plan.info()[0]['freq_split'] == 1 else 2) if plan.info()[0]['uniform'] else 0}>")
+                     if uniform else "fit_kernel (all pole-count buckets of one evaluation)",
                      "avg_launch_s": avg, "flops_per_eval": wb, "evals_per_launch": P},
     }
     # fit quality of the last step: average fractional error (Sec. IV) of each material's result

@@ -154,10 +154,11 @@ int debye_schedule_preview(const int64_t *f_off, const int64_t *cand_off, const 
                            int32_t *lane_mat, int64_t capacity, int64_t *xcd_off, int32_t *uniform);
 
 /* Schedule introspection: with i < 0 returns the number of pole-count buckets;
- * otherwise fills the pole count, pole split, frequency split and number of
- * work tiles of bucket i. */
+ * otherwise fills the pole count, pole split, frequency split, number of work
+ * tiles of bucket i and whether its tiles are uniform (one material per wave;
+ * see debye_schedule_preview).  Any output pointer may be NULL. */
 int debye_plan_info(const debye_plan *plan, int32_t i, int32_t *n_poles, int32_t *pole_split, int32_t *freq_split,
-                    int64_t *n_tiles);
+                    int64_t *n_tiles, int32_t *uniform);
 
 /* Text of the last error on this thread ("" if none). */
 const char *debye_last_error(void);

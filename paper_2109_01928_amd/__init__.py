@@ -102,7 +102,7 @@ def lib():
     L.debye_plan_create.argtypes = [C.POINTER(_CBatch), _vp, _vp, _vp, u32, C.POINTER(_vp)]
     L.debye_plan_destroy.argtypes = [_vp]
     L.debye_plan_set_freq_split.argtypes = [_vp, i32, i32]
-    L.debye_plan_info.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
+    L.debye_plan_info.argtypes = [_vp, i32, _vp, _vp, _vp, _vp, _vp]
     L.debye_plan_autotune.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, i32, _vp]
     L.debye_schedule_preview.argtypes = [_vp, _vp, _vp, i32, i32, i32, i32, _vp, _vp, i64, _vp, _vp]
     L.debye_basis.argtypes = [_vp, i64, _vp, i64, i64, i32, _vp, _vp, _vp]
@@ -225,13 +225,14 @@ class Plan:
 
     def info(self):
         L = lib()
-        n = L.debye_plan_info(self.handle, -1, None, None, None, None)
+        n = L.debye_plan_info(self.handle, -1, None, None, None, None, None)
         out = []
         for i in range(n):
-            N, sp, sf = C.c_int32(), C.c_int32(), C.c_int32()
+            N, sp, sf, un = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
             nt = C.c_int64()
-            _check(L.debye_plan_info(self.handle, i, C.byref(N), C.byref(sp), C.byref(sf), C.byref(nt)))
-            out.append(dict(n_poles=N.value, pole_split=sp.value, freq_split=sf.value, tiles=nt.value))
+            _check(L.debye_plan_info(self.handle, i, C.byref(N), C.byref(sp), C.byref(sf), C.byref(nt), C.byref(un)))
+            out.append(dict(n_poles=N.value, pole_split=sp.value, freq_split=sf.value, tiles=nt.value,
+                            uniform=bool(un.value)))
         return out
 
     def __del__(self):

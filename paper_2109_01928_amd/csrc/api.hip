@@ -573,7 +573,7 @@ int debye_schedule_preview(const int64_t *f_off, const int64_t *cand_off, const 
 }
 
 int debye_plan_info(const debye_plan *p, int32_t i, int32_t *n_poles, int32_t *pole_split, int32_t *freq_split,
-                    int64_t *n_tiles) {
+                    int64_t *n_tiles, int32_t *uniform) {
   if (!p) return fail(DEBYE_EINVAL, "plan is NULL");
   if (i < 0) return (int)p->buckets.size();
   if (i >= (int)p->buckets.size()) return fail(DEBYE_ERANGE, "bucket index out of range");
@@ -582,6 +582,7 @@ int debye_plan_info(const debye_plan *p, int32_t i, int32_t *n_poles, int32_t *p
   if (pole_split) *pole_split = b.SP;
   if (freq_split) *freq_split = b.SF;
   if (n_tiles) *n_tiles = b.n_tiles;
+  if (uniform) *uniform = b.uni ? 1 : 0;
   return DEBYE_OK;
 }
 
