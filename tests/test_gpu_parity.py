@@ -134,6 +134,29 @@ def test_cost_parity_every_pole_count(D, orc, N):
         _check_eval(D, orc, wl, theta, split=split, tag=f"N{N}")
 
 
+@pytest.mark.parametrize("N", [6, 12, 20])
+def test_cost_parity_uniform_and_mixed_tiles(D, orc, N):
+    """Both tile forms at split 1 and wider splits: whole swarms of 64 (every
+    wave one material: wave-uniform spectrum addresses) and swarms of 12
+    (waves shared by two materials)."""
+    seen = set()
+    for P, M in ((64, 4), (12, 16)):
+        wl = small_uniform(M, 211, N, P, seed=300 + N + P)
+        theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=N + P)
+        er, ei = targets_oracle(orc, wl)
+        for split in (1, 2, 4):
+            plan = D.Plan(_gpu_batch(D, wl, er, ei))
+            plan.set_freq_split(split)
+            uni = plan.info()[0]["uniform"]
+            # whole waves of 64 are always uniform; 12 per material is where a
+            # wave's slots divide 12
+            assert uni or P != 64, plan.info()
+            seen.add((uni, split == 1))
+            _check_eval(D, orc, wl, theta, split=split, tag=f"N{N} P{P} split{split} uniform={uni}")
+            del plan
+    assert seen == {(True, True), (True, False), (False, True), (False, False)}
+
+
 def test_cost_parity_ragged_batch(D, orc):
     wl = small_ragged(60, seed=7)
     theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=3)
