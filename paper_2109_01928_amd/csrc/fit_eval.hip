@@ -798,7 +798,13 @@ __global__ __launch_bounds__(256) void target_grad_kernel(const TargetGradArgs a
 // --------------------------------------------------------------------------
 // dispatch tables
 // --------------------------------------------------------------------------
-constexpr int pole_split_for(int n) { return n <= 8 ? 1 : (n <= 12 ? 2 : 4); }
+// Pole split by pole count, measured per bucket on the ragged workload (each
+// pole count alone, autotuned frequency split): one lane per candidate up to
+// N = 11 (at N = 9..11 its register spills cost less than the DPP traffic and
+// the padded pole of the two-lane ring; at N = 12 they do not), two lanes up
+// to N = 16 (N = 13..16 pad to 16 on four lanes), four above (two lanes
+// spill the adjoint heavily at N = 17, 18).
+constexpr int pole_split_for(int n) { return n <= 11 ? 1 : (n <= 16 ? 2 : 4); }
 
 template <int N> int lds_bytes_per_cand() { return Shape<N, pole_split_for(N)>::LDS_DOUBLES * 8; }
 

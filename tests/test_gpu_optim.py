@@ -106,7 +106,9 @@ def test_gpu_swarm_is_deterministic_and_finds_good_fits(D, orc):
 
 
 @pytest.mark.parametrize("N,F,flags,damping", [(5, 120, 0, 1e-8), (8, 300, 0, 1e-8), (8, 300, 1, 1e-8),
-                                               (12, 400, 0, 1e-8), (20, 600, 0, 1e-8), (6, 200, 0, 1e-4)])
+                                               (10, 300, 0, 1e-8), (11, 350, 0, 1e-8), (12, 400, 0, 1e-8),
+                                               (14, 400, 0, 1e-8), (16, 500, 0, 1e-8), (20, 600, 0, 1e-8),
+                                               (6, 200, 0, 1e-4)])
 def test_adjoint_matches_oracle(D, orc, N, F, flags, damping):
     import torch
     wl = small_uniform(3, F, N, 20, seed=N * 7 + F)

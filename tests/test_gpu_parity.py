@@ -130,7 +130,8 @@ def test_cost_parity_config_shapes(D, orc, F, N, P, M, fmin, fmax):
 def test_cost_parity_every_pole_count(D, orc, N):
     wl = small_uniform(3, 173, N, 70, seed=100 + N)   # 70 candidates: ragged last tile
     theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=N)
-    for split in (None, 1, 4, 64 // {1: 1, 2: 2, 4: 4}[1 if N <= 8 else (2 if N <= 12 else 4)]):
+    sp = D.Plan(_gpu_batch(D, wl, *targets_oracle(orc, wl))).info()[0]["pole_split"]
+    for split in (None, 1, 4, 64 // sp):
         _check_eval(D, orc, wl, theta, split=split, tag=f"N{N}")
 
 
