@@ -577,13 +577,14 @@ void fit_kernel(const FitArgs a) {
   const double einf = (F > 0) ? (sum_er - group_sum<SP>(ws_part)) / (double)F : 0.0;
 
   // ---- pass 3: residuals and cost (+ g_w for the adjoint)
-  double cost = 0.0;
   double gw[GRAD ? NB : 1], gw2[GRAD ? NB : 1], wt[NB];
 #pragma unroll
   for (int cI = 0; cI < (GRAD ? NB : 1); ++cI) gw[cI] = gw2[cI] = 0.0;
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) wt[cI] = wv_[cI] * tau[cI];
-  {
+  // from the basis values of every point
+  auto pass3_basis = [&]() -> double {
+    double acc = 0.0;
     int64_t k = fl;
     double w_n = 0, er_n = 0, ei_n = 0;
     if (k < F) {
@@ -607,8 +608,8 @@ void fit_kernel(const FitArgs a) {
       }
       const double rr = (er - einf) - group_sum<SP>(pr);
       const double ri = __builtin_fma(-w, group_sum<SP>(pi), ei);
-      cost = __builtin_fma(rr, rr, cost);
-      cost = __builtin_fma(ri, ri, cost);
+      acc = __builtin_fma(rr, rr, acc);
+      acc = __builtin_fma(ri, ri, acc);
       if constexpr (GRAD) {
         // g_w = R^T r' + I^T r'' = R^T r' + tau (R^T (w r''))
         const double wri = w * ri;
@@ -619,6 +620,103 @@ void fit_kernel(const FitArgs a) {
         }
       }
     }
+    return acc;
+  };
+  double cost;
+  if constexpr (GRAD) {
+    cost = pass3_basis();
+  } else {
+    // With w >= 0 (the sign flip) the lane's model sums are rational
+    // functions of y = w^2 with positive coefficients,
+    //   sum_i w_i R_i = P(y) / Q(y),  sum_i (w_i tau_i) R_i = P'(y) / Q(y),
+    //   Q(y) = prod_i (1 + y tau_i^2),  P(y) = sum_i w_i prod_{j != i} (1 + y tau_j^2),
+    // evaluated by Horner's rule with one reciprocal per point (no
+    // cancellation: every term is positive).  The variable is scaled by the
+    // lane's largest tau^2, so every coefficient is at most binomial-sized.
+    // A wave falls back to the basis form if a lane's smallest coefficient
+    // would be subnormal, Q exceeds 1e280 at some point, or a cost is not
+    // finite.
+    double tmax = 0.0;
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) tmax = tau2[cI] > tmax ? tau2[cI] : tmax;
+    const double isc = tmax > 0.0 ? 1.0 / tmax : 1.0;
+    double tp[NB], qc[NB + 1], cr[NB], ci[NB];
+    double pnz = 1.0;   // product of the nonzero scaled tau^2: the smallest coefficient
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) {
+      tp[cI] = tau2[cI] * isc;
+      pnz *= tp[cI] > 0.0 ? tp[cI] : 1.0;
+    }
+    qc[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= NB; ++k) qc[k] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int k = i + 1; k >= 1; --k) qc[k] = __builtin_fma(tp[i], qc[k - 1], qc[k]);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) cr[k] = ci[k] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      double e[NB];
+      e[0] = 1.0;
+#pragma unroll
+      for (int k = 1; k < NB; ++k) e[k] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        if (i == j) continue;
+        const int deg = i < j ? i + 1 : i;   // factors taken so far, this one included
+#pragma unroll
+        for (int k = deg; k >= 1; --k) e[k] = __builtin_fma(tp[i], e[k - 1], e[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        cr[k] = __builtin_fma(wv_[j], e[k], cr[k]);
+        ci[k] = __builtin_fma(wt[j], e[k], ci[k]);
+      }
+    }
+    double csum = qc[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) csum += cr[k] + ci[k];
+    // (lanes whose cost is replaced by their status do not count)
+    const bool matters = active && !bad && ok;
+    const bool coef_ok = !matters || (pnz >= 1e-280 && fabs(csum) < INFINITY);
+    bool use_basis = !flip || __builtin_amdgcn_ballot_w64(!coef_ok) != 0;
+    cost = 0.0;
+    if (!use_basis) {
+      double qmax = 0.0;
+      int64_t k = fl;
+      double w_n = 0, er_n = 0, ei_n = 0;
+      if (k < F) {
+        w_n = ld(om, k);
+        er_n = ld(epr, k);
+        ei_n = ld(epi, k);
+      }
+      for (; k < F; k += SF) {
+        const double w = w_n, er = er_n, ei = ei_n;
+        const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
+        w_n = ld(om, kn);
+        er_n = ld(epr, kn);
+        ei_n = ld(epi, kn);
+        const double y = (w * w) * tmax;
+        double hq = qc[NB], hr = cr[NB - 1], hi = ci[NB - 1];
+#pragma unroll
+        for (int d = NB - 1; d >= 0; --d) hq = __builtin_fma(hq, y, qc[d]);
+#pragma unroll
+        for (int d = NB - 2; d >= 0; --d) {
+          hr = __builtin_fma(hr, y, cr[d]);
+          hi = __builtin_fma(hi, y, ci[d]);
+        }
+        qmax = hq > qmax ? hq : qmax;
+        const double r = rcp_nr(hq);
+        const double rr = (er - einf) - group_sum<SP>(hr * r);
+        const double ri = __builtin_fma(-w, group_sum<SP>(hi * r), ei);
+        cost = __builtin_fma(rr, rr, cost);
+        cost = __builtin_fma(ri, ri, cost);
+      }
+      use_basis = __builtin_amdgcn_ballot_w64(matters && (!(qmax <= 1e280) || !(fabs(cost) < INFINITY))) != 0;
+    }
+    if (use_basis) cost = pass3_basis();
   }
   cost = freq_sum(cost, SP, SL);
 
