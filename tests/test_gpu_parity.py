@@ -158,6 +158,20 @@ def test_cost_parity_uniform_and_mixed_tiles(D, orc, N):
     assert seen == {(True, True), (True, False), (False, True), (False, False)}
 
 
+@pytest.mark.parametrize("N", [8, 12])
+def test_cost_parity_extreme_relaxation_times(D, orc, N):
+    """Valid but extreme log10(tau): poles spread over 60 decades (the cost
+    pass's scaled coefficients would be subnormal) and poles far below the
+    band (w tau up to 1e19: Q(w^2) overflows), beside ordinary candidates in
+    the same waves; those waves take the basis form of the cost pass."""
+    wl = small_uniform(2, 200, N, 64, seed=40 + N)
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=N)
+    theta[3, :N] = np.linspace(-30.0, 30.0, N)               # 60 decades in one candidate
+    theta[70, :N] = np.linspace(6.0, 9.0, N)                 # w tau from 6e11 to 6e19
+    theta[71, :N] = np.linspace(-29.0, -26.0, N)             # far above the band
+    _check_eval(D, orc, wl, theta, tag=f"extreme N{N}")
+
+
 def test_cost_parity_ragged_batch(D, orc):
     wl = small_ragged(60, seed=7)
     theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=3)
