@@ -507,33 +507,50 @@ void fit_kernel(const FitArgs a) {
       for (int cI = 0; cI < NB; ++cI) part = __builtin_fma(Rv[cI], zs[cI], part);
       return w * __builtin_fma(-w, group_sum<SP>(part), ei);
     };
-    // The compensated sum takes the terms of two points at a time, their sum
-    // formed with one fused multiply-add (at most two roundings of terms of
-    // the same two points, so the error bound stays a small multiple of the
-    // roundoff of the terms' magnitudes).
-    auto pair = [&](int64_t k0) {
-      const double w0 = ld(om, k0), e0 = ld(epi, k0), w1 = ld(om, k0 + SF), e1 = ld(epi, k0 + SF);
-      double R0[NB], R1[NB];
-      const double wr0 = resid(w0, e0, R0), wr1 = resid(w1, e1, R1);
+    // The compensated sum takes the terms of four points at a time, summed
+    // plainly (at most four roundings of terms of the same four points, so
+    // the error bound stays a small multiple of the roundoff of the terms'
+    // magnitudes; a CPU emulation of the whole solve put the cost error
+    // against the 80-bit oracle at the level of single-term compensation).
+    auto block4 = [&](int64_t k0) {
+      double pb[NB], R[NB];
+      {
+        const double wr = resid(ld(om, k0), ld(epi, k0), R);
 #pragma unroll
-      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], 1.0, __builtin_fma(R1[cI], wr1, R0[cI] * wr0));
+        for (int cI = 0; cI < NB; ++cI) pb[cI] = R[cI] * wr;
+      }
+#pragma unroll
+      for (int t = 1; t < 4; ++t) {
+        const int64_t kk = k0 + t * SF;
+        const double wr = resid(ld(om, kk), ld(epi, kk), R);
+#pragma unroll
+        for (int cI = 0; cI < NB; ++cI) pb[cI] = __builtin_fma(R[cI], wr, pb[cI]);
+      }
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], 1.0, pb[cI]);
     };
-    // two pairs per trip: the compensated sums then alternate between two
+    // two blocks per trip: the compensated sums then alternate between two
     // registers instead of being copied back every update
     int64_t k = fl;
-    for (; k + 3 * SF < F; k += 4 * SF) {
-      pair(k);
-      pair(k + 2 * SF);
+    for (; k + 7 * SF < F; k += 8 * SF) {
+      block4(k);
+      block4(k + 4 * SF);
     }
-    if (k + SF < F) {
-      pair(k);
-      k += 2 * SF;
+    if (k + 3 * SF < F) {
+      block4(k);
+      k += 4 * SF;
     }
-    if (k < F) {
-      double R0[NB];
-      const double wr0 = resid(ld(om, k), ld(epi, k), R0);
+    if (k < F) {   // the last one to three points
+      double pb[NB], R[NB];
 #pragma unroll
-      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], R0[cI], wr0);
+      for (int cI = 0; cI < NB; ++cI) pb[cI] = 0.0;
+      for (; k < F; k += SF) {
+        const double wr = resid(ld(om, k), ld(epi, k), R);
+#pragma unroll
+        for (int cI = 0; cI < NB; ++cI) pb[cI] = __builtin_fma(R[cI], wr, pb[cI]);
+      }
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], 1.0, pb[cI]);
     }
   }
 #pragma unroll
