@@ -44,7 +44,7 @@ template <int N, int SP> struct Shape {
   static constexpr int NG = (SP == 1) ? N * (N + 1) / 2 : NB * (D + 1);  // Gram accumulators
   static constexpr int NT = N * (N + 1) / 2;                 // packed triangle
   // per candidate: the parked factor (SP == 1), or the whole solve (SP > 1)
-  static constexpr int LDS_DOUBLES = (SP == 1) ? N * (N + 1) / 2 : N * (N + 1) / 2 + 6 * N;
+  static constexpr int LDS_DOUBLES = (SP == 1) ? N * (N + 1) / 2 : N * (N + 1) / 2 + 5 * N;
 };
 
 constexpr __host__ __device__ int tri(int n, int i, int j) { return i * n - (i * (i - 1)) / 2 + (j - i); }
@@ -125,6 +125,20 @@ __device__ __forceinline__ void basis_R(double w2, const double *tau2, double *R
     R[c + 1] = d0 * r;
   }
   if constexpr (NB & 1) R[NB - 1] = rcp_nr(__builtin_fma(w2, tau2[NB - 1], 1.0));
+}
+
+// U = w R directly (the Gram pass needs no R): U0 = d1 (w r), U1 = d0 (w r),
+// as many roundings after the reciprocal as R0 = d1 r followed by w R0.
+template <int NB>
+__device__ __forceinline__ void basis_U(double w, double w2, const double *tau2, double *U) {
+#pragma unroll
+  for (int c = 0; c + 1 < NB; c += 2) {
+    const double d0 = __builtin_fma(w2, tau2[c], 1.0), d1 = __builtin_fma(w2, tau2[c + 1], 1.0);
+    const double rw = w * rcp_nr(d0 * d1);
+    U[c] = d1 * rw;
+    U[c + 1] = d0 * rw;
+  }
+  if constexpr (NB & 1) U[NB - 1] = w * rcp_nr(__builtin_fma(w2, tau2[NB - 1], 1.0));
 }
 
 // --------------------------------------------------------------------------
@@ -237,15 +251,15 @@ __device__ __noinline__ void lds_chol_solve(int n, const double *A, const double
   }
 }
 
-// per-candidate LDS region of the SP > 1 path: packed triangle, then six
-// vectors of N (scaling, reciprocal pivots, rhs, column sums, two work vectors)
+// per-candidate LDS region of the SP > 1 path: packed triangle, then five
+// vectors of N (scaling, reciprocal pivots, rhs, two work vectors)
 template <int N> struct LdsLayout {
   static constexpr int NT = N * (N + 1) / 2;
-  static constexpr int DOUBLES = NT + 6 * N;
-  double *A, *invd, *uinv, *vb, *vS, *vz, *vw;
+  static constexpr int DOUBLES = NT + 5 * N;
+  double *A, *invd, *uinv, *vb, *vz, *vw;
   __device__ __forceinline__ explicit LdsLayout(double *base)
-      : A(base), invd(base + NT), uinv(base + NT + N), vb(base + NT + 2 * N), vS(base + NT + 3 * N),
-        vz(base + NT + 4 * N), vw(base + NT + 5 * N) {}
+      : A(base), invd(base + NT), uinv(base + NT + N), vb(base + NT + 2 * N), vz(base + NT + 3 * N),
+        vw(base + NT + 4 * N) {}
 };
 
 // factor parked by the SP == 1 path: A (off-diagonal) and reciprocal pivots
@@ -342,9 +356,10 @@ void fit_kernel(const FitArgs a) {
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) tau2[cI] = tau[cI] * tau[cI];
 
-  // ---- pass 1: Gram, right-hand side, column sums of R, sum of eps'.
-  // Accumulated with U = w R in place of I = tau U; the factors tau are
-  // applied after the frequency sums.
+  // ---- pass 1: Gram, right-hand side, sum of eps'.  Accumulated with
+  // U = w R in place of I = tau U; the factors tau are applied after the
+  // frequency sums.  (The column sums of R, first needed for eps_inf after
+  // the refinement, are taken in pass 2, which forms every R anyway.)
   double G[NG], bv[NB], Sv[NB];
 #pragma unroll
   for (int e = 0; e < NG; ++e) G[e] = 0.0;
@@ -368,14 +383,10 @@ void fit_kernel(const FitArgs a) {
       w_n = ld(om, kn);
       er_n = ld(epr, kn);
       ei_n = ld(epi, kn);
-      double Iv[NV], Rv[NB];
-      basis_R<NB>(w * w, tau2, Rv);
+      double Iv[NV];
+      basis_U<NB>(w, w * w, tau2, Iv);
 #pragma unroll
-      for (int cI = 0; cI < NB; ++cI) {
-        Iv[cI] = w * Rv[cI];
-        Sv[cI] += Rv[cI];
-        bv[cI] = __builtin_fma(Iv[cI], ei, bv[cI]);
-      }
+      for (int cI = 0; cI < NB; ++cI) bv[cI] = __builtin_fma(Iv[cI], ei, bv[cI]);
       if constexpr (SP > 1) {
 #pragma unroll
         for (int v = NB; v < NV; ++v) Iv[v] = ring_fetch<SP>(Iv[v % NB], v / NB);
@@ -411,7 +422,6 @@ void fit_kernel(const FitArgs a) {
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) {
     bv[cI] = freq_sum(bv[cI], SP, SL) * tau[cI];
-    Sv[cI] = freq_sum(Sv[cI], SP, SL);
     bad = bad || !(fabs(bv[cI]) < INFINITY);
   }
   sum_er = freq_sum(sum_er, SP, SL);
@@ -451,7 +461,7 @@ void fit_kernel(const FitArgs a) {
     // assemble the packed triangle in LDS (all lanes of a candidate write the same values)
     L = lds_all + (int64_t)grp * S::LDS_DOUBLES;
     const LdsLayout<N> lay(L);
-    double *A = lay.A, *invd = lay.invd, *uinv = lay.uinv, *vb = lay.vb, *vS = lay.vS, *vz = lay.vz;
+    double *A = lay.A, *invd = lay.invd, *uinv = lay.uinv, *vb = lay.vb, *vz = lay.vz;
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) {
       const int p1 = q * NB + cI;
@@ -464,10 +474,7 @@ void fit_kernel(const FitArgs a) {
           A[tri(N, i, j)] = G[cI * (D + 1) + d];
         }
       }
-      if (p1 < N) {
-        vb[p1] = bv[cI];
-        vS[p1] = Sv[cI];
-      }
+      if (p1 < N) vb[p1] = bv[cI];
     }
     __syncthreads();
     ok = lds_equilibrate_factor(N, A, invd, uinv, damping, tol);
@@ -499,12 +506,15 @@ void fit_kernel(const FitArgs a) {
     double zs[NB];
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) zs[cI] = zc[cI] * tau[cI];
-    // R at point k and w_k r_k
+    // R at point k (its column sums taken on the way) and w_k r_k
     auto resid = [&](double w, double ei, double *Rv) {
       basis_R<NB>(w * w, tau2, Rv);
       double part = 0.0;
 #pragma unroll
-      for (int cI = 0; cI < NB; ++cI) part = __builtin_fma(Rv[cI], zs[cI], part);
+      for (int cI = 0; cI < NB; ++cI) {
+        Sv[cI] += Rv[cI];
+        part = __builtin_fma(Rv[cI], zs[cI], part);
+      }
       return w * __builtin_fma(-w, group_sum<SP>(part), ei);
     };
     // The compensated sum takes the terms of four points at a time, summed
@@ -554,7 +564,10 @@ void fit_kernel(const FitArgs a) {
     }
   }
 #pragma unroll
-  for (int cI = 0; cI < NB; ++cI) gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL) * tau[cI];
+  for (int cI = 0; cI < NB; ++cI) {
+    gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL) * tau[cI];
+    Sv[cI] = freq_sum(Sv[cI], SP, SL);
+  }
 
   // correction: zt += A^-1 (D^-1 g - damping zt)
   if constexpr (SP == 1) {
