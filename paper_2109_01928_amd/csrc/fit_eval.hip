@@ -19,7 +19,11 @@
 //     materials with the same pole count);
 //   - every F-reduction is a per-lane register accumulation followed by a
 //     fixed butterfly over the SF lanes, so results are deterministic;
-//   - the basis is recomputed in registers in each pass and never stored.
+//   - passes: (1) Gram and right-hand side, (2) refinement residual and the
+//     column sums S, (3) cost; passes 1 and 2 recompute the basis in
+//     registers (it is never stored), pass 3 evaluates the model sums as
+//     rational functions of w^2 (basis form as the fallback), and the adjoint
+//     adds pass 4.
 //
 // Ring split of the Gram matrix for SP > 1 poles-per-lane groups: the NP =
 // NB*SP (padded) poles are placed on a ring; lane q owns poles q*NB .. q*NB+NB-1
