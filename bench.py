@@ -49,7 +49,7 @@ def kernel_source_hash():
     import hashlib
     # the cost kernel's own source: its file and the device helpers it includes
     src = b"".join(open(os.path.join(ROOT, "paper_2109_01928_amd", "csrc", f), "rb").read()
-                   for f in ("fit_eval.hip", "common.hpp"))
+                   for f in ("fit_kernel.hpp", "fit_eval.hip", "common.hpp"))
     return hashlib.sha256(src).hexdigest()[:16]
 
 

@@ -659,7 +659,7 @@ int debye_fit_eval_grad(const debye_plan *pc, const debye_batch *b, const double
     a.grad_theta = grad_log10_tau;
     a.record = targets ? p->d_record : nullptr;
     a.rec_ld = p->rec_ld;
-    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, true, false, s), "debye_fit_eval_grad launch");
+    CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, true, bk.uni, s), "debye_fit_eval_grad launch");
     if (!targets) return DEBYE_OK;
     {
       dfit::TargetGradArgs t{};

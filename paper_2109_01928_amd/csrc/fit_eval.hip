@@ -1,893 +1,10 @@
-// Batched multi-Debye DLS cost evaluation and its variable-projection adjoint
-// for gfx950 (MI355X), FP64.
-//
-// Method (paper Sec. III-B; Eq. 7 basis with the sign of Eq. 1):
-//   tau_i = 10^theta_i, x_ki = w_k tau_i, R_ki = 1/(1+x^2), I_ki = x R_ki
-//   weights: damped least squares on the loss part with Marquardt scaling,
-//     (D^-1 G D^-1 + damping Id) zt = D^-1 b,  G = I^T I, b = I^T eps'', D = diag(G)^1/2,
-//     z = D^-1 zt, solved by Cholesky plus one corrected-semi-normal-equations
-//     step (a residual pass over the frequencies, I^T r accumulated with
-//     compensation) because log-spaced Debye columns are nearly collinear;
-//   flip: w = |z| (penalty for negative weights);
-//   eps_inf = (sum_k eps'_k - sum_i w_i S_i) / F,  S_i = sum_k R_ki;
-//   cost = sum_k (eps'_k - eps_inf - (R w)_k)^2 + (eps''_k - (I w)_k)^2.
-//
-// Work decomposition (one wavefront per work tile, one tile per 64-lane block):
-//   - a candidate is served by SP x SF lanes: SP lanes split its poles (the
-//     "ring" split below) and SF lanes split its frequency points;
-//   - the 64/(SP*SF) candidates of a wave are listed by the plan (any mix of
-//     materials with the same pole count);
-//   - every F-reduction is a per-lane register accumulation followed by a
-//     fixed butterfly over the SF lanes, so results are deterministic;
-//   - passes: (1) Gram and right-hand side, (2) refinement residual and the
-//     column sums S, (3) cost; passes 1 and 2 recompute the basis in
-//     registers (it is never stored), pass 3 evaluates the model sums as
-//     rational functions of w^2 (basis form as the fallback), and the adjoint
-//     adds pass 4.
-//
-// Ring split of the Gram matrix for SP > 1 poles-per-lane groups: the NP =
-// NB*SP (padded) poles are placed on a ring; lane q owns poles q*NB .. q*NB+NB-1
-// and accumulates, for each owned pole p and each offset d = 0..NP/2, the
-// entry G(p, (p+d) mod NP).  Every unordered pair is covered (the d = NP/2
-// entries twice, with bit-identical values), the work is balanced, and a lane
-// only needs the basis values of the next NP/2 poles on the ring, which it
-// receives from its neighbours by DPP quad permutes.  Padded poles get tau = 0,
-// so their loss column is exactly zero and they drop out.
+// Forward cost kernels of the Debye fitting library (the kernel itself is in
+// fit_kernel.hpp; the adjoint instantiations are compiled in fit_grad.hip),
+// the target-gradient kernel, and the dispatch by pole count.
 
-#include "common.hpp"
-#include "fit_eval.hpp"
+#include "fit_kernel.hpp"
 
 namespace dfit {
-
-template <int N, int SP> struct Shape {
-  static_assert(SP == 1 || SP == 2 || SP == 4, "pole split must be 1, 2 or 4");
-  static constexpr int NB = (N + SP - 1) / SP;               // poles owned per lane
-  static constexpr int NP = NB * SP;                         // padded ring size
-  static constexpr int D = (SP == 1) ? 0 : NP / 2;           // ring half width
-  static constexpr int NV = (SP == 1) ? N : NB + D;          // basis values seen by a lane
-  static constexpr int NG = (SP == 1) ? N * (N + 1) / 2 : NB * (D + 1);  // Gram accumulators
-  static constexpr int NT = N * (N + 1) / 2;                 // packed triangle
-  // per candidate: the parked factor (SP == 1), or the whole solve (SP > 1)
-  static constexpr int LDS_DOUBLES = (SP == 1) ? N * (N + 1) / 2 : N * (N + 1) / 2 + 5 * N;
-};
-
-constexpr __host__ __device__ int tri(int n, int i, int j) { return i * n - (i * (i - 1)) / 2 + (j - i); }
-
-// value of block t (owned by lane (q + t) mod SP) of a lane's ring view
-template <int SP> __device__ __forceinline__ double ring_fetch(double v, int t) {
-  if constexpr (SP == 2) {
-    return dpp_quad<QP_SWAP1>(v);
-  } else {
-    return t == 1 ? dpp_quad<QP_ROT1>(v) : dpp_quad<QP_SWAP2>(v);
-  }
-}
-
-// sum over the SP lanes of a candidate (bit-identical in all of them)
-template <int SP> __device__ __forceinline__ double group_sum(double v) {
-  if constexpr (SP == 1) {
-    return v;
-  } else if constexpr (SP == 2) {
-    return v + dpp_quad<QP_SWAP1>(v);
-  } else {
-    v = v + dpp_quad<QP_SWAP1>(v);
-    return v + dpp_quad<QP_SWAP2>(v);
-  }
-}
-
-// sum over the SF frequency lanes of a candidate (xor butterfly)
-__device__ __forceinline__ double freq_sum(double v, int sp, int s_lanes) {
-  for (int m = sp; m < s_lanes; m <<= 1) v += __shfl_xor(v, m, WAVE);
-  return v;
-}
-
-// Compensated accumulation sum += a * b (Kahan's summation with the running
-// correction c folded into the product by a fused multiply-add): the error of
-// a length-F sum stays at a few units of roundoff of the terms' magnitude
-// instead of growing with F.  The true sum is sum - c.
-__device__ __forceinline__ void kahan_fma_acc(double &sum, double &c, double a, double b) {
-  const double y = __builtin_fma(a, b, -c);
-  const double t = sum + y;
-  c = (t - sum) - y;
-  sum = t;
-}
-
-// xor-butterfly of a double-double over the SF frequency lanes; TwoSum's
-// error term does not depend on the operand order, so all lanes end with the
-// same bits
-__device__ __forceinline__ double freq_sum_dd(double hi, double lo, int sp, int s_lanes) {
-  for (int m = sp; m < s_lanes; m <<= 1) {
-    const double oh = __shfl_xor(hi, m, WAVE), ol = __shfl_xor(lo, m, WAVE);
-    const double s = hi + oh;
-    const double bv = s - hi;
-    const double se = (hi - (s - bv)) + (oh - bv);
-    hi = s;
-    lo = (lo + ol) + se;
-  }
-  return hi + lo;
-}
-
-// --------------------------------------------------------------------------
-// Debye basis of the owned poles at one frequency: R = 1/(1+x^2), I = x R.
-// Every pass needs only R: with I = w tau R, the factor tau moves out of
-// every frequency sum (applied once per candidate) and w out of every pole
-// sum (applied once per point), and 1 + x^2 is 1 + w^2 tau^2 with w^2 shared
-// by the poles and tau^2 by the points (the rounding of d is the same as
-// through x = w tau: one product rounded, then a fused add).  Two poles share
-// one reciprocal: r = 1/(d0 d1), R0 = d1 r, R1 = d0 r (within a few ulp; the
-// hardware reciprocal costs about 2.5 fused multiply-adds).  With
-// |log10 tau| <= 30 (larger values are rejected as bad input) and w < 1e45
-// rad/s, x < 1e75 and the product d0 d1 < 1e301 cannot overflow.  Padded
-// poles have tau = 0: R = 1, and their I columns vanish through tau.
-// --------------------------------------------------------------------------
-template <int NB>
-__device__ __forceinline__ void basis_R(double w2, const double *tau2, double *R) {
-#pragma unroll
-  for (int c = 0; c + 1 < NB; c += 2) {
-    const double d0 = __builtin_fma(w2, tau2[c], 1.0), d1 = __builtin_fma(w2, tau2[c + 1], 1.0);
-    const double r = rcp_nr(d0 * d1);
-    R[c] = d1 * r;
-    R[c + 1] = d0 * r;
-  }
-  if constexpr (NB & 1) R[NB - 1] = rcp_nr(__builtin_fma(w2, tau2[NB - 1], 1.0));
-}
-
-// U = w R directly (the Gram pass needs no R): U0 = d1 (w r), U1 = d0 (w r),
-// as many roundings after the reciprocal as R0 = d1 r followed by w R0.
-template <int NB>
-__device__ __forceinline__ void basis_U(double w, double w2, const double *tau2, double *U) {
-#pragma unroll
-  for (int c = 0; c + 1 < NB; c += 2) {
-    const double d0 = __builtin_fma(w2, tau2[c], 1.0), d1 = __builtin_fma(w2, tau2[c + 1], 1.0);
-    const double rw = w * rcp_nr(d0 * d1);
-    U[c] = d1 * rw;
-    U[c + 1] = d0 * rw;
-  }
-  if constexpr (NB & 1) U[NB - 1] = w * rcp_nr(__builtin_fma(w2, tau2[NB - 1], 1.0));
-}
-
-// --------------------------------------------------------------------------
-// Dense solve helpers on a packed upper triangle held in registers (SP == 1)
-// or in LDS (SP > 1).  A = U^T U, U upper, diagonal stored as reciprocals in uinv.
-// --------------------------------------------------------------------------
-template <int N, class MAT>
-__device__ __forceinline__ bool equilibrate_factor(MAT &A, double *invd, double *uinv, double damping,
-                                                   double tol) {
-  bool ok = true;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    double g = A[tri(N, i, i)];
-    ok = ok && (g > 0.0) && (g < INFINITY);
-    invd[i] = 1.0 / sqrt(g);
-  }
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-#pragma unroll
-    for (int j = i + 1; j < N; ++j) A[tri(N, i, j)] = A[tri(N, i, j)] * invd[i] * invd[j];
-    A[tri(N, i, i)] = 1.0 + damping;
-  }
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    double s = A[tri(N, j, j)];
-#pragma unroll
-    for (int l = 0; l < j; ++l) s = __builtin_fma(-A[tri(N, l, j)], A[tri(N, l, j)], s);
-    ok = ok && (s > tol);
-    double u = sqrt(s);
-    double ui = 1.0 / u;
-    uinv[j] = ui;
-    A[tri(N, j, j)] = u;
-#pragma unroll
-    for (int k = j + 1; k < N; ++k) {
-      double t = A[tri(N, j, k)];
-#pragma unroll
-      for (int l = 0; l < j; ++l) t = __builtin_fma(-A[tri(N, l, j)], A[tri(N, l, k)], t);
-      A[tri(N, j, k)] = t * ui;
-    }
-  }
-  return ok;
-}
-
-// x <- A^-1 x with A = U^T U (x overwritten)
-template <int N, class MAT, class VEC>
-__device__ __forceinline__ void chol_solve(const MAT &A, const double *uinv, VEC &x) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    double s = x[i];
-#pragma unroll
-    for (int l = 0; l < i; ++l) s = __builtin_fma(-A[tri(N, l, i)], x[l], s);
-    x[i] = s * uinv[i];
-  }
-#pragma unroll
-  for (int i = N - 1; i >= 0; --i) {
-    double s = x[i];
-#pragma unroll
-    for (int l = i + 1; l < N; ++l) s = __builtin_fma(-A[tri(N, i, l)], x[l], s);
-    x[i] = s * uinv[i];
-  }
-}
-
-// The same factorisation and solves for a matrix in LDS (SP > 1): plain
-// loops, so that the compiler does not pull the whole matrix into registers.
-// Every lane of a candidate runs them on that candidate's region.
-__device__ __noinline__ bool lds_equilibrate_factor(int n, double *A, double *invd, double *uinv, double damping,
-                                                    double tol) {
-  bool ok = true;
-  for (int i = 0; i < n; ++i) {
-    const double g = A[tri(n, i, i)];
-    ok = ok && (g > 0.0) && (g < INFINITY);
-    invd[i] = 1.0 / sqrt(g);
-  }
-  for (int i = 0; i < n; ++i) {
-    const int row = tri(n, i, i);
-    for (int j = i + 1; j < n; ++j) A[row + (j - i)] = A[row + (j - i)] * invd[i] * invd[j];
-    A[row] = 1.0 + damping;
-  }
-  for (int j = 0; j < n; ++j) {
-    double s = A[tri(n, j, j)];
-    for (int l = 0; l < j; ++l) {
-      const double u = A[tri(n, l, j)];
-      s = __builtin_fma(-u, u, s);
-    }
-    ok = ok && (s > tol);
-    const double u = sqrt(s);
-    const double ui = 1.0 / u;
-    uinv[j] = ui;
-    A[tri(n, j, j)] = u;
-    for (int k = j + 1; k < n; ++k) {
-      double t = A[tri(n, j, k)];
-      for (int l = 0; l < j; ++l) t = __builtin_fma(-A[tri(n, l, j)], A[tri(n, l, k)], t);
-      A[tri(n, j, k)] = t * ui;
-    }
-  }
-  return ok;
-}
-
-__device__ __noinline__ void lds_chol_solve(int n, const double *A, const double *uinv, double *x) {
-  for (int i = 0; i < n; ++i) {
-    double s = x[i];
-    for (int l = 0; l < i; ++l) s = __builtin_fma(-A[tri(n, l, i)], x[l], s);
-    x[i] = s * uinv[i];
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double s = x[i];
-    const int row = tri(n, i, i);
-    for (int l = i + 1; l < n; ++l) s = __builtin_fma(-A[row + (l - i)], x[l], s);
-    x[i] = s * uinv[i];
-  }
-}
-
-// per-candidate LDS region of the SP > 1 path: packed triangle, then five
-// vectors of N (scaling, reciprocal pivots, rhs, two work vectors)
-template <int N> struct LdsLayout {
-  static constexpr int NT = N * (N + 1) / 2;
-  static constexpr int DOUBLES = NT + 5 * N;
-  double *A, *invd, *uinv, *vb, *vz, *vw;
-  __device__ __forceinline__ explicit LdsLayout(double *base)
-      : A(base), invd(base + NT), uinv(base + NT + N), vb(base + NT + 2 * N), vz(base + NT + 3 * N),
-        vw(base + NT + 4 * N) {}
-};
-
-// factor parked by the SP == 1 path: A (off-diagonal) and reciprocal pivots
-template <int N>
-__device__ __forceinline__ void unpark(const double *park, int cpw, int grp, double *A, double *uinv) {
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = i; j < N; ++j) {
-      const double v = park[tri(N, i, j) * cpw + grp];
-      if (i == j) uinv[i] = v;
-      else A[tri(N, i, j)] = v;
-    }
-}
-
-// --------------------------------------------------------------------------
-// The kernel.  GRAD adds the adjoint (grad w.r.t. log10 tau, and per-candidate
-// records for the target gradient).
-// --------------------------------------------------------------------------
-// target waves per SIMD: bounds the register budget of each instantiation
-template <int N, int SP> constexpr int waves_per_simd() { return (SP == 1 && N <= 6) ? 3 : 2; }
-
-// UNI (uniform tiles; the plan checks that every active lane of every tile
-// belongs to one material and that spectra hold fewer than 2^29 points):
-//   1: frequency split 1, so every lane of a wave reads the same point and
-//      the spectra are read with wave-uniform (scalar) loads;
-//   2: frequency split > 1: wave-uniform spectrum base, per-lane 32-bit
-//      byte offsets (one offset per point for the three arrays).
-template <int N, int SP, bool GRAD, int UNI>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_simd<N, SP>())))
-void fit_kernel(const FitArgs a) {
-  using S = Shape<N, SP>;
-  constexpr int NB = S::NB, NV = S::NV, NG = S::NG, D = S::D;
-  extern __shared__ double lds_all[];
-
-  const int lane = threadIdx.x;
-  const int SF = UNI == 1 ? 1 : a.freq_split;
-  const int SL = SP * SF;            // lanes per candidate
-  const int grp = lane / SL;         // candidate slot in the wave
-  const int sub = lane - grp * SL;
-  const int q = sub % SP;            // pole block
-  const int fl = UNI == 1 ? 0 : sub / SP; // frequency lane
-  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
-  // block b runs on XCD b % 8 as its (b / 8)-th block.  The plan gives every
-  // XCD its own list of tiles (whole materials where possible, so that a
-  // material's spectra stay in one L2; the lists balanced by work, each
-  // longest first).  The grid covers the longest list; surplus blocks exit.
-  const int xcd = blockIdx.x & 7;
-  const int64_t j = blockIdx.x >> 3;
-  if (j >= a.xcd_off[xcd + 1] - a.xcd_off[xcd]) return;
-  const int64_t tile = a.xcd_off[xcd] + j;
-  const int64_t slot = tile * a.cand_per_wave + grp;
-  const int32_t cand = a.lane_cand[slot];
-  const bool active = cand >= 0;
-  const int32_t mat = active ? a.lane_mat[slot] : 0;
-  const int64_t c = active ? cand : 0;
-
-  int64_t f0 = 0, F = 0;
-  if constexpr (UNI != 0) {
-    const int32_t mu = __builtin_amdgcn_readfirstlane(a.lane_mat[tile * a.cand_per_wave]);
-    f0 = a.f_off[mu];
-    F = a.f_off[mu + 1] - f0;
-  } else if (active) {
-    f0 = a.f_off[mat];
-    F = a.f_off[mat + 1] - f0;
-  }
-  const double *om = a.omega + f0;
-  const double *epr = a.eps_re + f0;
-  const double *epi = a.eps_im + f0;
-  // point k of a spectrum
-  auto ld = [](const double *p, int64_t k) -> double {
-    if constexpr (UNI == 2) return *(const double *)((const char *)p + ((uint32_t)k << 3));
-    else return p[k];
-  };
-  const double damping = a.damping;
-  const bool flip = !(a.flags & FLAG_NO_SIGN_FLIP);
-
-  // ---- relaxation times of the owned poles
-  double tau[NB], th[NB];
-  bool bad = false;
-#pragma unroll
-  for (int cI = 0; cI < NB; ++cI) {
-    const int p = q * NB + cI;
-    th[cI] = 0.0;
-    tau[cI] = 0.0;
-    if (p < N && active) {
-      const double t = a.theta[c * a.ld + p];
-      th[cI] = t;
-      bad = bad || !(fabs(t) <= THETA_LIMIT);
-      tau[cI] = exp10(t);
-    }
-  }
-  double tau2[NB];
-#pragma unroll
-  for (int cI = 0; cI < NB; ++cI) tau2[cI] = tau[cI] * tau[cI];
-
-  // ---- pass 1: Gram, right-hand side, sum of eps'.  Accumulated with
-  // U = w R in place of I = tau U; the factors tau are applied after the
-  // frequency sums.  (The column sums of R, first needed for eps_inf after
-  // the refinement, are taken in pass 2, which forms every R anyway.)
-  double G[NG], bv[NB], Sv[NB];
-#pragma unroll
-  for (int e = 0; e < NG; ++e) G[e] = 0.0;
-#pragma unroll
-  for (int cI = 0; cI < NB; ++cI) {
-    bv[cI] = 0.0;
-    Sv[cI] = 0.0;
-  }
-  double sum_er = 0.0;
-  {
-    int64_t k = fl;
-    double w_n = 0, er_n = 0, ei_n = 0;
-    if (k < F) {
-      w_n = ld(om, k);
-      er_n = ld(epr, k);
-      ei_n = ld(epi, k);
-    }
-    for (; k < F; k += SF) {
-      const double w = w_n, er = er_n, ei = ei_n;
-      const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
-      w_n = ld(om, kn);
-      er_n = ld(epr, kn);
-      ei_n = ld(epi, kn);
-      double Iv[NV];
-      basis_U<NB>(w, w * w, tau2, Iv);
-#pragma unroll
-      for (int cI = 0; cI < NB; ++cI) bv[cI] = __builtin_fma(Iv[cI], ei, bv[cI]);
-      if constexpr (SP > 1) {
-#pragma unroll
-        for (int v = NB; v < NV; ++v) Iv[v] = ring_fetch<SP>(Iv[v % NB], v / NB);
-#pragma unroll
-        for (int cI = 0; cI < NB; ++cI)
-#pragma unroll
-          for (int d = 0; d <= D; ++d) G[cI * (D + 1) + d] = __builtin_fma(Iv[cI], Iv[cI + d], G[cI * (D + 1) + d]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-#pragma unroll
-          for (int j = i; j < N; ++j) G[tri(N, i, j)] = __builtin_fma(Iv[i], Iv[j], G[tri(N, i, j)]);
-      }
-      sum_er += er;
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < NG; ++e) G[e] = freq_sum(G[e], SP, SL);
-  if constexpr (SP > 1) {
-    double tv[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) tv[v] = v < NB ? tau[v] : ring_fetch<SP>(tau[v % NB], v / NB);
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI)
-#pragma unroll
-      for (int d = 0; d <= D; ++d) G[cI * (D + 1) + d] *= tau[cI] * tv[cI + d];
-  } else {
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = i; j < N; ++j) G[tri(N, i, j)] *= tau[i] * tau[j];
-  }
-#pragma unroll
-  for (int cI = 0; cI < NB; ++cI) {
-    bv[cI] = freq_sum(bv[cI], SP, SL) * tau[cI];
-    bad = bad || !(fabs(bv[cI]) < INFINITY);
-  }
-  sum_er = freq_sum(sum_er, SP, SL);
-  bad = bad || !(fabs(sum_er) < INFINITY);
-  bad = group_sum<SP>(bad ? 1.0 : 0.0) != 0.0;
-
-  // ---- DLS solve (equilibrated, damped Cholesky)
-  const double tol = 8.0 * (double)(F > N ? F : N) * 0x1.0p-53;
-  double zt[NB], zc[NB], invd_own[NB];
-  bool ok;
-  double *L = nullptr;
-  double uinv_r[SP == 1 ? N : 1], invd_r[SP == 1 ? N : 1];
-  if constexpr (SP == 1) {
-    ok = equilibrate_factor<N>(G, invd_r, uinv_r, damping, tol);
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      zt[i] = bv[i] * invd_r[i];
-      invd_own[i] = invd_r[i];
-    }
-    chol_solve<N>(G, uinv_r, zt);
-    // Park the factor in LDS (reciprocal pivots in place of its diagonal,
-    // which the solves never read), element-major so that a wave's lanes touch
-    // consecutive addresses.  The later solves read it back; meanwhile its
-    // registers serve the frequency passes.
-    {
-      double *park = lds_all;
-      const int cpw = WAVE / SL;
-      if (fl == 0) {
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-#pragma unroll
-          for (int j = i; j < N; ++j) park[tri(N, i, j) * cpw + grp] = (i == j) ? uinv_r[i] : G[tri(N, i, j)];
-      }
-      __syncthreads();
-    }
-  } else {
-    // assemble the packed triangle in LDS (all lanes of a candidate write the same values)
-    L = lds_all + (int64_t)grp * S::LDS_DOUBLES;
-    const LdsLayout<N> lay(L);
-    double *A = lay.A, *invd = lay.invd, *uinv = lay.uinv, *vb = lay.vb, *vz = lay.vz;
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      const int p1 = q * NB + cI;
-#pragma unroll
-      for (int d = 0; d <= D; ++d) {
-        int p2 = p1 + d;
-        if (p2 >= S::NP) p2 -= S::NP;
-        if (p1 < N && p2 < N) {
-          const int i = p1 < p2 ? p1 : p2, j = p1 < p2 ? p2 : p1;
-          A[tri(N, i, j)] = G[cI * (D + 1) + d];
-        }
-      }
-      if (p1 < N) vb[p1] = bv[cI];
-    }
-    __syncthreads();
-    ok = lds_equilibrate_factor(N, A, invd, uinv, damping, tol);
-    for (int i = 0; i < N; ++i) vz[i] = vb[i] * invd[i];
-    lds_chol_solve(N, A, uinv, vz);
-    __syncthreads();
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      const int p = q * NB + cI;
-      zt[cI] = p < N ? vz[p] : 0.0;
-      invd_own[cI] = p < N ? invd[p] : 0.0;
-    }
-  }
-#pragma unroll
-  for (int cI = 0; cI < NB; ++cI) zc[cI] = zt[cI] * invd_own[cI];
-
-  // ---- pass 2: corrected semi-normal equations, g = I^T (eps'' - I z).
-  // The residual is nearly orthogonal to the columns of I, so g is a sum with
-  // heavy cancellation; it is accumulated with compensation (residual
-  // refinement with the residual products summed in extra precision).
-  double gv[NB], gl[NB];
-#pragma unroll
-  for (int cI = 0; cI < NB; ++cI) {
-    gv[cI] = 0.0;
-    gl[cI] = 0.0;
-  }
-  {
-    // I z = w sum_i (tau_i z_i) R_i, and I^T r = tau (R^T (w r))
-    double zs[NB];
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) zs[cI] = zc[cI] * tau[cI];
-    // R at point k (its column sums taken on the way) and w_k r_k
-    auto resid = [&](double w, double ei, double *Rv) {
-      basis_R<NB>(w * w, tau2, Rv);
-      double part = 0.0;
-#pragma unroll
-      for (int cI = 0; cI < NB; ++cI) {
-        Sv[cI] += Rv[cI];
-        part = __builtin_fma(Rv[cI], zs[cI], part);
-      }
-      return w * __builtin_fma(-w, group_sum<SP>(part), ei);
-    };
-    // The compensated sum takes the terms of four points at a time, summed
-    // plainly (at most four roundings of terms of the same four points, so
-    // the error bound stays a small multiple of the roundoff of the terms'
-    // magnitudes; a CPU emulation of the whole solve put the cost error
-    // against the 80-bit oracle at the level of single-term compensation).
-    auto block4 = [&](int64_t k0) {
-      double pb[NB], R[NB];
-      {
-        const double wr = resid(ld(om, k0), ld(epi, k0), R);
-#pragma unroll
-        for (int cI = 0; cI < NB; ++cI) pb[cI] = R[cI] * wr;
-      }
-#pragma unroll
-      for (int t = 1; t < 4; ++t) {
-        const int64_t kk = k0 + t * SF;
-        const double wr = resid(ld(om, kk), ld(epi, kk), R);
-#pragma unroll
-        for (int cI = 0; cI < NB; ++cI) pb[cI] = __builtin_fma(R[cI], wr, pb[cI]);
-      }
-#pragma unroll
-      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], 1.0, pb[cI]);
-    };
-    // two blocks per trip: the compensated sums then alternate between two
-    // registers instead of being copied back every update
-    int64_t k = fl;
-    for (; k + 7 * SF < F; k += 8 * SF) {
-      block4(k);
-      block4(k + 4 * SF);
-    }
-    if (k + 3 * SF < F) {
-      block4(k);
-      k += 4 * SF;
-    }
-    if (k < F) {   // the last one to three points
-      double pb[NB], R[NB];
-#pragma unroll
-      for (int cI = 0; cI < NB; ++cI) pb[cI] = 0.0;
-      for (; k < F; k += SF) {
-        const double wr = resid(ld(om, k), ld(epi, k), R);
-#pragma unroll
-        for (int cI = 0; cI < NB; ++cI) pb[cI] = __builtin_fma(R[cI], wr, pb[cI]);
-      }
-#pragma unroll
-      for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], 1.0, pb[cI]);
-    }
-  }
-#pragma unroll
-  for (int cI = 0; cI < NB; ++cI) {
-    gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL) * tau[cI];
-    Sv[cI] = freq_sum(Sv[cI], SP, SL);
-  }
-
-  // correction: zt += A^-1 (D^-1 g - damping zt)
-  if constexpr (SP == 1) {
-    double dz[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) dz[i] = __builtin_fma(gv[i], invd_r[i], -damping * zt[i]);
-    double Af[S::NT], uf[N];
-    unpark<N>(lds_all, WAVE / SL, grp, Af, uf);
-    chol_solve<N>(Af, uf, dz);
-#pragma unroll
-    for (int i = 0; i < N; ++i) zt[i] += dz[i];
-  } else {
-    const LdsLayout<N> lay(L);
-    double *A = lay.A, *uinv = lay.uinv, *vw = lay.vw;
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      const int p = q * NB + cI;
-      if (p < N) vw[p] = __builtin_fma(gv[cI], invd_own[cI], -damping * zt[cI]);
-    }
-    __syncthreads();
-    lds_chol_solve(N, A, uinv, vw);
-    __syncthreads();
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      const int p = q * NB + cI;
-      zt[cI] += p < N ? vw[p] : 0.0;
-    }
-  }
-  double wv_[NB];
-  double ws_part = 0.0;
-#pragma unroll
-  for (int cI = 0; cI < NB; ++cI) {
-    zc[cI] = zt[cI] * invd_own[cI];
-    wv_[cI] = flip ? fabs(zc[cI]) : zc[cI];
-    ws_part = __builtin_fma(wv_[cI], Sv[cI], ws_part);
-  }
-  const double einf = (F > 0) ? (sum_er - group_sum<SP>(ws_part)) / (double)F : 0.0;
-
-  // ---- pass 3: residuals and cost (+ g_w for the adjoint)
-  double gw[GRAD ? NB : 1], gw2[GRAD ? NB : 1], wt[NB];
-#pragma unroll
-  for (int cI = 0; cI < (GRAD ? NB : 1); ++cI) gw[cI] = gw2[cI] = 0.0;
-#pragma unroll
-  for (int cI = 0; cI < NB; ++cI) wt[cI] = wv_[cI] * tau[cI];
-  // from the basis values of every point
-  auto pass3_basis = [&]() -> double {
-    double acc = 0.0;
-    int64_t k = fl;
-    double w_n = 0, er_n = 0, ei_n = 0;
-    if (k < F) {
-      w_n = ld(om, k);
-      er_n = ld(epr, k);
-      ei_n = ld(epi, k);
-    }
-    for (; k < F; k += SF) {
-      const double w = w_n, er = er_n, ei = ei_n;
-      const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
-      w_n = ld(om, kn);
-      er_n = ld(epr, kn);
-      ei_n = ld(epi, kn);
-      double Rv[NB];
-      basis_R<NB>(w * w, tau2, Rv);
-      double pr = 0.0, pi = 0.0;
-#pragma unroll
-      for (int cI = 0; cI < NB; ++cI) {
-        pr = __builtin_fma(wv_[cI], Rv[cI], pr);
-        pi = __builtin_fma(wt[cI], Rv[cI], pi);
-      }
-      const double rr = (er - einf) - group_sum<SP>(pr);
-      const double ri = __builtin_fma(-w, group_sum<SP>(pi), ei);
-      acc = __builtin_fma(rr, rr, acc);
-      acc = __builtin_fma(ri, ri, acc);
-      if constexpr (GRAD) {
-        // g_w = R^T r' + I^T r'' = R^T r' + tau (R^T (w r''))
-        const double wri = w * ri;
-#pragma unroll
-        for (int cI = 0; cI < NB; ++cI) {
-          gw[cI] = __builtin_fma(Rv[cI], rr, gw[cI]);
-          gw2[cI] = __builtin_fma(Rv[cI], wri, gw2[cI]);
-        }
-      }
-    }
-    return acc;
-  };
-  double cost;
-  if constexpr (GRAD) {
-    cost = pass3_basis();
-  } else {
-    // With w >= 0 (the sign flip) the lane's model sums are rational
-    // functions of y = w^2 with positive coefficients,
-    //   sum_i w_i R_i = P(y) / Q(y),  sum_i (w_i tau_i) R_i = P'(y) / Q(y),
-    //   Q(y) = prod_i (1 + y tau_i^2),  P(y) = sum_i w_i prod_{j != i} (1 + y tau_j^2),
-    // evaluated by Horner's rule with one reciprocal per point (no
-    // cancellation: every term is positive).  The variable is scaled by the
-    // lane's largest tau^2, so every coefficient is at most binomial-sized.
-    // A wave falls back to the basis form if a lane's smallest coefficient
-    // would be subnormal, Q exceeds 1e280 at some point, or a cost is not
-    // finite.
-    double tmax = 0.0;
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) tmax = tau2[cI] > tmax ? tau2[cI] : tmax;
-    const double isc = tmax > 0.0 ? 1.0 / tmax : 1.0;
-    double tp[NB], qc[NB + 1], cr[NB], ci[NB];
-    double pnz = 1.0;   // product of the nonzero scaled tau^2: the smallest coefficient
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      tp[cI] = tau2[cI] * isc;
-      pnz *= tp[cI] > 0.0 ? tp[cI] : 1.0;
-    }
-    qc[0] = 1.0;
-#pragma unroll
-    for (int k = 1; k <= NB; ++k) qc[k] = 0.0;
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int k = i + 1; k >= 1; --k) qc[k] = __builtin_fma(tp[i], qc[k - 1], qc[k]);
-#pragma unroll
-    for (int k = 0; k < NB; ++k) cr[k] = ci[k] = 0.0;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      double e[NB];
-      e[0] = 1.0;
-#pragma unroll
-      for (int k = 1; k < NB; ++k) e[k] = 0.0;
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        if (i == j) continue;
-        const int deg = i < j ? i + 1 : i;   // factors taken so far, this one included
-#pragma unroll
-        for (int k = deg; k >= 1; --k) e[k] = __builtin_fma(tp[i], e[k - 1], e[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        cr[k] = __builtin_fma(wv_[j], e[k], cr[k]);
-        ci[k] = __builtin_fma(wt[j], e[k], ci[k]);
-      }
-    }
-    double csum = qc[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) csum += cr[k] + ci[k];
-    // (lanes whose cost is replaced by their status do not count)
-    const bool matters = active && !bad && ok;
-    const bool coef_ok = !matters || (pnz >= 1e-280 && fabs(csum) < INFINITY);
-    bool use_basis = !flip || __builtin_amdgcn_ballot_w64(!coef_ok) != 0;
-    cost = 0.0;
-    if (!use_basis) {
-      double qmax = 0.0;
-      int64_t k = fl;
-      double w_n = 0, er_n = 0, ei_n = 0;
-      if (k < F) {
-        w_n = ld(om, k);
-        er_n = ld(epr, k);
-        ei_n = ld(epi, k);
-      }
-      for (; k < F; k += SF) {
-        const double w = w_n, er = er_n, ei = ei_n;
-        const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
-        w_n = ld(om, kn);
-        er_n = ld(epr, kn);
-        ei_n = ld(epi, kn);
-        const double y = (w * w) * tmax;
-        double hq = qc[NB], hr = cr[NB - 1], hi = ci[NB - 1];
-#pragma unroll
-        for (int d = NB - 1; d >= 0; --d) hq = __builtin_fma(hq, y, qc[d]);
-#pragma unroll
-        for (int d = NB - 2; d >= 0; --d) {
-          hr = __builtin_fma(hr, y, cr[d]);
-          hi = __builtin_fma(hi, y, ci[d]);
-        }
-        qmax = hq > qmax ? hq : qmax;
-        const double r = rcp_nr(hq);
-        const double rr = (er - einf) - group_sum<SP>(hr * r);
-        const double ri = __builtin_fma(-w, group_sum<SP>(hi * r), ei);
-        cost = __builtin_fma(rr, rr, cost);
-        cost = __builtin_fma(ri, ri, cost);
-      }
-      use_basis = __builtin_amdgcn_ballot_w64(matters && (!(qmax <= 1e280) || !(fabs(cost) < INFINITY))) != 0;
-    }
-    if (use_basis) cost = pass3_basis();
-  }
-  cost = freq_sum(cost, SP, SL);
-
-  const bool sing = !ok;
-  const int st = bad ? ST_BADINPUT : (sing ? ST_SINGULAR : ST_OK);
-  const bool writer = active && fl == 0;
-  double gc = 1.0;
-  if (writer && q == 0) {
-    a.cost[c] = st == ST_OK ? cost : (st == ST_SINGULAR ? INFINITY : NAN);
-    if (a.eps_inf) a.eps_inf[c] = st == ST_OK ? einf : NAN;
-    if (a.status) a.status[c] = (int8_t)st;
-  }
-  if (writer && a.weights) {
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      const int p = q * NB + cI;
-      if (p < N) a.weights[c * a.ld + p] = st == ST_OK ? wv_[cI] : NAN;
-    }
-  }
-  if constexpr (!GRAD) {
-    return;
-  } else {
-    // ---- adjoint: mu = M^-1 (s o g_w), M = D A D
-    if (a.grad_cost) gc = active ? a.grad_cost[c] : 0.0;
-    double mt[NB], mu[NB];
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      gw[cI] = -2.0 * __builtin_fma(tau[cI], freq_sum(gw2[cI], SP, SL), freq_sum(gw[cI], SP, SL));
-      const double s = (flip && zc[cI] < 0.0) ? -1.0 : 1.0;
-      mt[cI] = s * gw[cI] * invd_own[cI];
-    }
-    if constexpr (SP == 1) {
-      double Af[S::NT], uf[N];
-      unpark<N>(lds_all, WAVE / SL, grp, Af, uf);
-      chol_solve<N>(Af, uf, mt);
-    } else {
-      const LdsLayout<N> lay(L);
-      double *A = lay.A, *uinv = lay.uinv, *vw = lay.vw;
-#pragma unroll
-      for (int cI = 0; cI < NB; ++cI) {
-        const int p = q * NB + cI;
-        if (p < N) vw[p] = mt[cI];
-      }
-      __syncthreads();
-      lds_chol_solve(N, A, uinv, vw);
-      __syncthreads();
-#pragma unroll
-      for (int cI = 0; cI < NB; ++cI) {
-        const int p = q * NB + cI;
-        mt[cI] = p < N ? vw[p] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) mu[cI] = mt[cI] * invd_own[cI];
-
-    // ---- pass 4: basis derivatives against the residuals.  With x^2 R = 1 - R,
-    // dR/dtheta = -2 ln10 I^2 and dI/dtheta = ln10 I (2R - 1); ln10 is applied
-    // after the sums, and the dot products run over R with tau-scaled weights
-    // as in the forward passes.
-    double T1[NB], T2[NB], T3[NB], T4[NB], zt4[NB], mt4[NB];
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      T1[cI] = T2[cI] = T3[cI] = T4[cI] = 0.0;
-      zt4[cI] = zc[cI] * tau[cI];
-      mt4[cI] = mu[cI] * tau[cI];
-    }
-    {
-      int64_t k = fl;
-      double w_n = 0, er_n = 0, ei_n = 0;
-      if (k < F) {
-        w_n = ld(om, k);
-        er_n = ld(epr, k);
-        ei_n = ld(epi, k);
-      }
-      for (; k < F; k += SF) {
-        const double w = w_n, er = er_n, ei = ei_n;
-        const int64_t kn = (k + SF < F) ? k + SF : k;
-        w_n = ld(om, kn);
-        er_n = ld(epr, kn);
-        ei_n = ld(epi, kn);
-        double Rv[NB];
-        basis_R<NB>(w * w, tau2, Rv);
-        double pr = 0.0, pi = 0.0, pz = 0.0, pm = 0.0;
-#pragma unroll
-        for (int cI = 0; cI < NB; ++cI) {
-          pr = __builtin_fma(wv_[cI], Rv[cI], pr);
-          pi = __builtin_fma(wt[cI], Rv[cI], pi);
-          pz = __builtin_fma(zt4[cI], Rv[cI], pz);
-          pm = __builtin_fma(mt4[cI], Rv[cI], pm);
-        }
-        const double rr = (er - einf) - group_sum<SP>(pr);
-        const double ri = __builtin_fma(-w, group_sum<SP>(pi), ei);
-        const double qz = __builtin_fma(-w, group_sum<SP>(pz), ei);
-        const double qm = w * group_sum<SP>(pm);
-        const double m2rr = -2.0 * rr;
-#pragma unroll
-        for (int cI = 0; cI < NB; ++cI) {
-          const double R = Rv[cI];
-          const double I = (w * tau[cI]) * R;
-          const double dI = I * __builtin_fma(2.0, R, -1.0);
-          T1[cI] = __builtin_fma(I * m2rr, I, __builtin_fma(dI, ri, T1[cI]));
-          T2[cI] = __builtin_fma(dI, qz, T2[cI]);
-          T3[cI] = __builtin_fma(dI, qm, T3[cI]);
-          T4[cI] = __builtin_fma(dI, I, T4[cI]);
-        }
-      }
-    }
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      T1[cI] = LN10 * freq_sum(T1[cI], SP, SL);
-      T2[cI] = LN10 * freq_sum(T2[cI], SP, SL);
-      T3[cI] = LN10 * freq_sum(T3[cI], SP, SL);
-      T4[cI] = LN10 * freq_sum(T4[cI], SP, SL);
-    }
-    if (writer) {
-#pragma unroll
-      for (int cI = 0; cI < NB; ++cI) {
-        const int p = q * NB + cI;
-        if (p >= N) continue;
-        double g = -2.0 * wv_[cI] * T1[cI] + mu[cI] * T2[cI] - zc[cI] * T3[cI] -
-                   2.0 * damping * mu[cI] * zc[cI] * T4[cI];
-        if (a.grad_theta) a.grad_theta[c * a.ld + p] = st == ST_OK ? gc * g : NAN;
-        // per-candidate record for the target gradient: [w | z | mu | eps_inf, gc]
-        if (a.record) {
-          double *rec = a.record + c * a.rec_ld;
-          rec[p] = wv_[cI];
-          rec[N + p] = zc[cI];
-          rec[2 * N + p] = mu[cI];
-          if (p == 0) {
-            rec[3 * N] = einf;
-            rec[3 * N + 1] = st == ST_OK ? gc : 0.0;
-          }
-        }
-      }
-    }
-  }
-}
 
 // --------------------------------------------------------------------------
 // Target gradient: for each material and frequency point, the sum over its
@@ -930,35 +47,7 @@ __global__ __launch_bounds__(256) void target_grad_kernel(const TargetGradArgs a
 // --------------------------------------------------------------------------
 // dispatch tables
 // --------------------------------------------------------------------------
-// Pole split by pole count, measured per bucket on the ragged workload (each
-// pole count alone, autotuned frequency split): one lane per candidate up to
-// N = 11 (at N = 9..11 its register spills cost less than the DPP traffic and
-// the padded pole of the two-lane ring; at N = 12 they do not), two lanes up
-// to N = 16 (N = 13..16 pad to 16 on four lanes), four above (two lanes
-// spill the adjoint heavily at N = 17, 18).
-constexpr int pole_split_for(int n) { return n <= 11 ? 1 : (n <= 16 ? 2 : 4); }
-
 template <int N> int lds_bytes_per_cand() { return Shape<N, pole_split_for(N)>::LDS_DOUBLES * 8; }
-
-template <int N> hipError_t launch_fit_n(const FitArgs &a, int64_t n_tiles, bool grad, bool uni, hipStream_t s) {
-  constexpr int SP = pole_split_for(N);
-  const size_t lds = (size_t)Shape<N, SP>::LDS_DOUBLES * 8 * a.cand_per_wave;
-  FitArgs b = a;
-  b.n_tiles = n_tiles;
-  int64_t longest = 0;
-  for (int x = 0; x < 8; ++x) longest = a.xcd_off[x + 1] - a.xcd_off[x] > longest ? a.xcd_off[x + 1] - a.xcd_off[x] : longest;
-  if (longest == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)(longest * 8);
-  if (grad)
-    hipLaunchKernelGGL((fit_kernel<N, SP, true, 0>), dim3(blocks), dim3(64), lds, s, b);
-  else if (uni && a.freq_split == 1)
-    hipLaunchKernelGGL((fit_kernel<N, SP, false, 1>), dim3(blocks), dim3(64), lds, s, b);
-  else if (uni)
-    hipLaunchKernelGGL((fit_kernel<N, SP, false, 2>), dim3(blocks), dim3(64), lds, s, b);
-  else
-    hipLaunchKernelGGL((fit_kernel<N, SP, false, 0>), dim3(blocks), dim3(64), lds, s, b);
-  return hipGetLastError();
-}
 
 template <int N> hipError_t launch_target_n(const TargetGradArgs &a, int64_t max_f, int32_t n_mats, hipStream_t s) {
   dim3 grid((unsigned)((max_f + 255) / 256), (unsigned)(n_mats < 65535 ? n_mats : 65535));
@@ -977,9 +66,9 @@ template <int... Ns> struct Table {
     ((n == Ns ? (r = lds_bytes_per_cand<Ns>()) : 0), ...);
     return r;
   }
-  static hipError_t fit(int n, const FitArgs &a, int64_t tiles, bool grad, bool uni, hipStream_t s) {
+  static hipError_t fit(int n, const FitArgs &a, int64_t tiles, bool uni, hipStream_t s) {
     hipError_t e = hipErrorInvalidValue;
-    ((n == Ns ? (e = launch_fit_n<Ns>(a, tiles, grad, uni, s)) : hipSuccess), ...);
+    ((n == Ns ? (e = launch_fit_variant<Ns, false>(a, tiles, uni, s)) : hipSuccess), ...);
     return e;
   }
   static hipError_t target(int n, const TargetGradArgs &a, int64_t max_f, int32_t n_mats, hipStream_t s) {
@@ -993,7 +82,7 @@ using AllN = Table<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18
 int pole_split(int n) { return AllN::pole_split(n); }
 int lds_bytes_per_candidate(int n) { return AllN::lds(n); }
 hipError_t launch_fit(int n, const FitArgs &a, int64_t n_tiles, bool grad, bool uni, hipStream_t s) {
-  return AllN::fit(n, a, n_tiles, grad, uni, s);
+  return grad ? launch_fit_grad(n, a, n_tiles, uni, s) : AllN::fit(n, a, n_tiles, uni, s);
 }
 hipError_t launch_target_grad(int n, const TargetGradArgs &a, int64_t max_f, int32_t n_mats, hipStream_t s) {
   return AllN::target(n, a, max_f, n_mats, s);
