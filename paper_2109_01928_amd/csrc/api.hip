@@ -639,7 +639,7 @@ int debye_fit_eval_grad(const debye_plan *pc, const debye_batch *b, const double
   debye_plan *p = const_cast<debye_plan *>(pc);
   const bool targets = grad_eps_re != nullptr;
   if (targets && !p->d_record) {
-    p->rec_ld = 3 * p->max_poles + 2;
+    p->rec_ld = 4 * p->max_poles + 2;   // [w | z | mu | tau | eps_inf, gc]
     if (hipMalloc(&p->d_record, (size_t)std::max<int64_t>(p->n_cand, 1) * p->rec_ld * 8) != hipSuccess) {
       p->d_record = nullptr;
       return fail(DEBYE_ENOMEM, "adjoint workspace allocation failed");

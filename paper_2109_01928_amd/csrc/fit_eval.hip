@@ -9,7 +9,8 @@ namespace dfit {
 // --------------------------------------------------------------------------
 // Target gradient: for each material and frequency point, the sum over its
 // candidates (in index order) of gc * (2 r'_k) and gc * (2 r''_k + (I mu)_k),
-// recomputed from the per-candidate records of the adjoint kernel.
+// recomputed from the per-candidate records of the adjoint kernel (weights,
+// mu, tau, eps_inf and the upstream gradient of each candidate).
 // --------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(256) void target_grad_kernel(const TargetGradArgs a, int32_t n_mats) {
@@ -22,19 +23,19 @@ __global__ __launch_bounds__(256) void target_grad_kernel(const TargetGradArgs a
   double sr = 0.0, si = 0.0;
   for (int64_t c = a.cand_off[m]; c < a.cand_off[m + 1]; ++c) {
     const double *rec = a.record + c * a.rec_ld;
-    const double gc = rec[3 * N + 1];
+    const double gc = rec[4 * N + 1];
     if (gc == 0.0) continue;
     double pr = 0.0, pi = 0.0, pm = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const double x = w * exp10(a.theta[c * a.ld + i]);
+      const double x = w * rec[3 * N + i];
       const double R = rcp_nr(__builtin_fma(x, x, 1.0));
       const double I = x * R;
       pr = __builtin_fma(rec[i], R, pr);
       pi = __builtin_fma(rec[i], I, pi);
       pm = __builtin_fma(rec[2 * N + i], I, pm);
     }
-    const double rr = (er - rec[3 * N]) - pr;
+    const double rr = (er - rec[4 * N]) - pr;
     const double ri = ei - pi;
     sr = __builtin_fma(gc, 2.0 * rr, sr);
     si = __builtin_fma(gc, __builtin_fma(2.0, ri, pm), si);

@@ -875,15 +875,16 @@ void fit_kernel(const FitArgs a) {
         double g = -2.0 * wv_[cI] * T1[cI] + mu[cI] * T2[cI] - zc[cI] * T3[cI] -
                    2.0 * damping * mu[cI] * zc[cI] * T4[cI];
         if (a.grad_theta) a.grad_theta[c * a.ld + p] = st == ST_OK ? gc * g : NAN;
-        // per-candidate record for the target gradient: [w | z | mu | eps_inf, gc]
+        // per-candidate record for the target gradient: [w | z | mu | tau | eps_inf, gc]
         if (a.record) {
           double *rec = a.record + c * a.rec_ld;
           rec[p] = wv_[cI];
           rec[N + p] = zc[cI];
           rec[2 * N + p] = mu[cI];
+          rec[3 * N + p] = tau[cI];
           if (p == 0) {
-            rec[3 * N] = einf;
-            rec[3 * N + 1] = st == ST_OK ? gc : 0.0;
+            rec[4 * N] = einf;
+            rec[4 * N + 1] = st == ST_OK ? gc : 0.0;
           }
         }
       }
