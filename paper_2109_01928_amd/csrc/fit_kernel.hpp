@@ -512,13 +512,13 @@ void fit_kernel(const FitArgs a) {
     double zs[NB];
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) zs[cI] = zc[cI] * tau[cI];
-    // R at point k (its column sums taken on the way) and w_k r_k
+    // R at point k (for the adjoint its column sums taken on the way) and w_k r_k
     auto resid = [&](double w, double ei, double *Rv) {
       basis_R<NB>(w * w, tau2, Rv);
       double part = 0.0;
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
-        Sv[cI] += Rv[cI];
+        if constexpr (GRAD) Sv[cI] += Rv[cI];
         part = __builtin_fma(Rv[cI], zs[cI], part);
       }
       return w * __builtin_fma(-w, group_sum<SP>(part), ei);
@@ -572,7 +572,7 @@ void fit_kernel(const FitArgs a) {
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) {
     gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL) * tau[cI];
-    Sv[cI] = freq_sum(Sv[cI], SP, SL);
+    if constexpr (GRAD) Sv[cI] = freq_sum(Sv[cI], SP, SL);
   }
 
   // correction: zt += A^-1 (D^-1 g - damping zt)
@@ -608,9 +608,27 @@ void fit_kernel(const FitArgs a) {
   for (int cI = 0; cI < NB; ++cI) {
     zc[cI] = zt[cI] * invd_own[cI];
     wv_[cI] = flip ? fabs(zc[cI]) : zc[cI];
-    ws_part = __builtin_fma(wv_[cI], Sv[cI], ws_part);
+    if constexpr (GRAD) ws_part = __builtin_fma(wv_[cI], Sv[cI], ws_part);
   }
-  const double einf = (F > 0) ? (sum_er - group_sum<SP>(ws_part)) / (double)F : 0.0;
+  // eps_inf: the adjoint takes it from the column sums before its pass 3.
+  // The forward kernels take it from the cost pass: with v_k = eps'_k -
+  // (R w)_k, eps_inf is the mean of v and the real part of the cost is
+  // sum (v - mean)^2 = sum (v - K)^2 - (sum (v - K))^2 / F for any shift K.
+  // K = v_0 (the first point) differs from the mean by about one residual,
+  // so the subtraction loses at most a few digits of the cost's last bits.
+  double einf = 0.0, shift = 0.0;
+  if constexpr (GRAD) {
+    einf = (F > 0) ? (sum_er - group_sum<SP>(ws_part)) / (double)F : 0.0;
+    shift = einf;
+  } else if (F > 0) {
+    const double w0 = ld(om, 0);
+    double Rv[NB];
+    basis_R<NB>(w0 * w0, tau2, Rv);
+    double pr = 0.0;
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) pr = __builtin_fma(wv_[cI], Rv[cI], pr);
+    shift = ld(epr, 0) - group_sum<SP>(pr);
+  }
 
   // ---- pass 3: residuals and cost (+ g_w for the adjoint)
   double gw[GRAD ? NB : 1], gw2[GRAD ? NB : 1], wt[NB];
@@ -618,9 +636,11 @@ void fit_kernel(const FitArgs a) {
   for (int cI = 0; cI < (GRAD ? NB : 1); ++cI) gw[cI] = gw2[cI] = 0.0;
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) wt[cI] = wv_[cI] * tau[cI];
-  // from the basis values of every point
-  auto pass3_basis = [&]() -> double {
+  // from the basis values of every point; rr is eps' - shift - R w, and sa
+  // collects its sum (the forward kernels' shifted mean)
+  auto pass3_basis = [&](double &sa) -> double {
     double acc = 0.0;
+    sa = 0.0;
     int64_t k = fl;
     double w_n = 0, er_n = 0, ei_n = 0;
     if (k < F) {
@@ -642,8 +662,9 @@ void fit_kernel(const FitArgs a) {
         pr = __builtin_fma(wv_[cI], Rv[cI], pr);
         pi = __builtin_fma(wt[cI], Rv[cI], pi);
       }
-      const double rr = (er - einf) - group_sum<SP>(pr);
+      const double rr = (er - shift) - group_sum<SP>(pr);
       const double ri = __builtin_fma(-w, group_sum<SP>(pi), ei);
+      if constexpr (!GRAD) sa += rr;
       acc = __builtin_fma(rr, rr, acc);
       acc = __builtin_fma(ri, ri, acc);
       if constexpr (GRAD) {
@@ -658,9 +679,9 @@ void fit_kernel(const FitArgs a) {
     }
     return acc;
   };
-  double cost;
+  double cost, sa = 0.0;
   if constexpr (GRAD) {
-    cost = pass3_basis();
+    cost = pass3_basis(sa);
   } else {
     // With w >= 0 (the sign flip) the lane's model sums are rational
     // functions of y = w^2 with positive coefficients,
@@ -745,16 +766,25 @@ void fit_kernel(const FitArgs a) {
         }
         qmax = hq > qmax ? hq : qmax;
         const double r = rcp_nr(hq);
-        const double rr = (er - einf) - group_sum<SP>(hr * r);
+        const double rr = (er - shift) - group_sum<SP>(hr * r);
         const double ri = __builtin_fma(-w, group_sum<SP>(hi * r), ei);
+        sa += rr;
         cost = __builtin_fma(rr, rr, cost);
         cost = __builtin_fma(ri, ri, cost);
       }
-      use_basis = __builtin_amdgcn_ballot_w64(matters && (!(qmax <= 1e280) || !(fabs(cost) < INFINITY))) != 0;
+      use_basis =
+          __builtin_amdgcn_ballot_w64(matters && (!(qmax <= 1e280) || !(fabs(cost) + fabs(sa) < INFINITY))) != 0;
     }
-    if (use_basis) cost = pass3_basis();
+    if (use_basis) cost = pass3_basis(sa);
   }
   cost = freq_sum(cost, SP, SL);
+  if constexpr (!GRAD) {
+    sa = freq_sum(sa, SP, SL);
+    if (F > 0) {
+      cost -= sa * (sa / (double)F);
+      einf = shift + sa / (double)F;
+    }
+  }
 
   const bool sing = !ok;
   const int st = bad ? ST_BADINPUT : (sing ? ST_SINGULAR : ST_OK);
