@@ -128,7 +128,7 @@ int debye_plan_set_freq_split(debye_plan *plan, int32_t n_poles, int32_t split);
  * override, time `reps` launches (1..100) of the cost kernel at each frequency
  * split (1, 2, 4, ... up to 64 / pole split, while spectra keep at least 8
  * points per lane) with HIP events on `stream`, after about 30 ms of warm-up
- * launches and in two rounds (the best time of each split counts), and keep
+ * launches and in three rounds (the best time of each split counts), and keep
  * the fastest (a wider split must be at least 3 % faster than the best
  * narrower one).  The
  * arguments are those of debye_fit_eval (log10_tau: a representative set of

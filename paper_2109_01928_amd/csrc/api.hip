@@ -531,9 +531,10 @@ int debye_plan_autotune(debye_plan *p, const debye_batch *b, const double *log10
     if ((rc = build_tiles(*p, bk)) || (rc = time_bucket(bk, 1, &ms))) return cleanup(rc);
     const int warm = std::min(200, std::max(1, (int)(30.0f / std::max(ms, 0.01f))));
     if ((rc = time_bucket(bk, warm, &ms))) return cleanup(rc);
-    // two rounds over the splits, the best time of each
+    // three rounds over the splits, the best time of each (box-to-box and
+    // run-to-run spread is a few percent, about the margin between splits)
     std::vector<float> best(splits.size(), INFINITY);
-    for (int round = 0; round < 2; ++round)
+    for (int round = 0; round < 3; ++round)
       for (size_t i = 0; i < splits.size(); ++i) {
         p->sf_tuned[bk.N] = splits[i];
         if ((rc = build_tiles(*p, bk)) || (rc = time_bucket(bk, reps, &ms))) return cleanup(rc);
