@@ -19,11 +19,11 @@
 //     materials with the same pole count);
 //   - every F-reduction is a per-lane register accumulation followed by a
 //     fixed butterfly over the SF lanes, so results are deterministic;
-//   - passes: (1) Gram and right-hand side, (2) refinement residual and the
-//     column sums S, (3) cost; passes 1 and 2 recompute the basis in
-//     registers (it is never stored), pass 3 evaluates the model sums as
-//     rational functions of w^2 (basis form as the fallback), and the adjoint
-//     adds pass 4.
+//   - passes: (1) Gram and right-hand side, (2) refinement residual (and,
+//     for the adjoint, the column sums S), (3) cost; passes 1 and 2
+//     recompute the basis in registers (it is never stored; four poles share
+//     one reciprocal), pass 3 evaluates the model sums as rational functions
+//     of w^2 (basis form as the fallback), and the adjoint adds pass 4.
 //
 // Ring split of the Gram matrix for SP > 1 poles-per-lane groups: the NP =
 // NB*SP (padded) poles are placed on a ring; lane q owns poles q*NB .. q*NB+NB-1
@@ -114,12 +114,13 @@ __device__ __forceinline__ double freq_sum_dd(double hi, double lo, int sp, int 
 // every frequency sum (applied once per candidate) and w out of every pole
 // sum (applied once per point), and 1 + x^2 is 1 + w^2 tau^2 with w^2 shared
 // by the poles and tau^2 by the points (the rounding of d is the same as
-// through x = w tau: one product rounded, then a fused add).  Two poles share
-// one reciprocal: r = 1/(d0 d1), R0 = d1 r, R1 = d0 r (within a few ulp; the
-// hardware reciprocal costs about 2.5 fused multiply-adds).  With
-// |log10 tau| <= 30 (larger values are rejected as bad input) and w < 1e45
-// rad/s, x < 1e75 and the product d0 d1 < 1e301 cannot overflow.  Padded
-// poles have tau = 0: R = 1, and their I columns vanish through tau.
+// through x = w tau: one product rounded, then a fused add).  Padded poles
+// have tau = 0: R = 1, and their I columns vanish through tau.
+//
+// Paired form (basis_R): two poles share one reciprocal, r = 1/(d0 d1),
+// R0 = d1 r, R1 = d0 r (within a few ulp).  With |log10 tau| <= 30 (larger
+// values are rejected as bad input) and w < 1e45 rad/s, x < 1e75 and the
+// product d0 d1 < 1e301 cannot overflow.
 // --------------------------------------------------------------------------
 template <int NB>
 __device__ __forceinline__ void basis_R(double w2, const double *tau2, double *R) {
@@ -133,18 +134,117 @@ __device__ __forceinline__ void basis_R(double w2, const double *tau2, double *R
   if constexpr (NB & 1) R[NB - 1] = rcp_nr(__builtin_fma(w2, tau2[NB - 1], 1.0));
 }
 
-// U = w R directly (the Gram pass needs no R): U0 = d1 (w r), U1 = d0 (w r),
-// as many roundings after the reciprocal as R0 = d1 r followed by w R0.
+// Grouped form (the frequency passes of the cost): four poles share one
+// reciprocal, r = 1/(p01 p23) with p01 = d0 d1, p23 = d2 d3, and
+// 1/d0 = d1 (r p23), 1/d1 = d0 (r p23), 1/d2 = d3 (r p01), 1/d3 = d2 (r p01):
+// three products and one reciprocal per four poles in place of two
+// reciprocals (a reciprocal occupies the FP64 pipe for four issue cycles and
+// its Newton step for three more).  Poles beyond the last full group of four
+// are paired as above.
+//
+// The product of four d can leave the double range (each d < 1e150), so a
+// group works on d scaled by a power of two s, fixed from the bound
+// w < 1e45: s^4 prod d(1e45) <= 2^990 and s >= 2^-253, so every intermediate
+// product lies in [2^-1012, 2^990] at every admissible frequency and every
+// reciprocal is a normal number.  With tau^2 s in place of tau^2 and s in
+// place of 1, every intermediate is the unscaled value times an exact power
+// of two (the same roundings); the group's basis values come out divided by
+// s, and s is applied with tau after the frequency sums.  Any smaller s of
+// the same form keeps these bounds, so a wave takes, per group index, the
+// smallest s of its lanes: s is then wave-uniform and the fused add reads it
+// from a scalar register (a third vector operand of a 64-bit FMA costs issue
+// bandwidth), and each lane's results are still exactly its unscaled ones.
+// --------------------------------------------------------------------------
+constexpr double OMEGA_BOUND = 1e45;   // admissible angular frequencies: 0 < w < OMEGA_BOUND
+
+template <int NB> struct Groups {
+  static constexpr int NQ = NB / 4;              // groups of four owned poles
+  static constexpr int NS = NQ > 0 ? NQ : 1;     // (array size)
+};
+
+// scale s = 2^-k of each group (from tau^2 of its poles), the same in every
+// lane of the wave (all lanes call this together)
 template <int NB>
-__device__ __forceinline__ void basis_U(double w, double w2, const double *tau2, double *U) {
+__device__ __forceinline__ void group_scales(const double *tau2, int *kq, double *sq) {
+  kq[0] = 0;
+  sq[0] = 1.0;
 #pragma unroll
-  for (int c = 0; c + 1 < NB; c += 2) {
-    const double d0 = __builtin_fma(w2, tau2[c], 1.0), d1 = __builtin_fma(w2, tau2[c + 1], 1.0);
+  for (int g = 0; g < Groups<NB>::NQ; ++g) {
+    int e = 0;   // sum of the binary exponents: prod d(1e45) < 2^e
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      e += __builtin_amdgcn_frexp_exp(__builtin_fma(OMEGA_BOUND * OMEGA_BOUND, tau2[4 * g + t], 1.0));
+    int k = e > 990 ? (e - 990 + 3) >> 2 : 0;   // 0 <= k <= 253
+#pragma unroll
+    for (int m = 1; m < WAVE; m <<= 1) {
+      const int o = __shfl_xor(k, m, WAVE);
+      k = o > k ? o : k;
+    }
+    k = __builtin_amdgcn_readfirstlane(k);
+    kq[g] = k;
+    sq[g] = __hiloint2double((1023 - k) << 20, 0);   // 2^-k
+  }
+}
+
+// scale of owned pole i (1 outside the groups)
+template <int NB> __device__ __forceinline__ double pole_scale(const double *sq, int i) {
+  return i < 4 * Groups<NB>::NQ ? sq[i / 4] : 1.0;
+}
+
+// x * 2^(+-k) of owned pole i's group (exact)
+template <int NB> __device__ __forceinline__ double group_unscale(const int *kq, int i, double x) {
+  return i < 4 * Groups<NB>::NQ ? __builtin_amdgcn_ldexp(x, kq[i / 4]) : x;
+}
+template <int NB> __device__ __forceinline__ double group_scale(const int *kq, int i, double x) {
+  return i < 4 * Groups<NB>::NQ ? __builtin_amdgcn_ldexp(x, -kq[i / 4]) : x;
+}
+
+// R / s of the owned poles (tau2s = tau^2 s)
+template <int NB>
+__device__ __forceinline__ void basis_Rs(double w2, const double *tau2s, const double *sq, double *R) {
+#pragma unroll
+  for (int g = 0; g < Groups<NB>::NQ; ++g) {
+    const int c = 4 * g;
+    const double d0 = __builtin_fma(w2, tau2s[c], sq[g]), d1 = __builtin_fma(w2, tau2s[c + 1], sq[g]);
+    const double d2 = __builtin_fma(w2, tau2s[c + 2], sq[g]), d3 = __builtin_fma(w2, tau2s[c + 3], sq[g]);
+    const double p01 = d0 * d1, p23 = d2 * d3;
+    const double r = rcp_nr(p01 * p23);
+    const double r01 = r * p23, r23 = r * p01;
+    R[c] = d1 * r01;
+    R[c + 1] = d0 * r01;
+    R[c + 2] = d3 * r23;
+    R[c + 3] = d2 * r23;
+  }
+  basis_R<NB - 4 * Groups<NB>::NQ>(w2, tau2s + 4 * Groups<NB>::NQ, R + 4 * Groups<NB>::NQ);
+}
+
+// U / s with U = w R directly (the Gram pass needs no R): the factor w enters
+// once per group after the reciprocal (U0 = d1 ((w r) p23), ...), and once per
+// pair for the paired poles (U0 = d1 (w r)).
+template <int NB>
+__device__ __forceinline__ void basis_Us(double w, double w2, const double *tau2s, const double *sq, double *U) {
+#pragma unroll
+  for (int g = 0; g < Groups<NB>::NQ; ++g) {
+    const int c = 4 * g;
+    const double d0 = __builtin_fma(w2, tau2s[c], sq[g]), d1 = __builtin_fma(w2, tau2s[c + 1], sq[g]);
+    const double d2 = __builtin_fma(w2, tau2s[c + 2], sq[g]), d3 = __builtin_fma(w2, tau2s[c + 3], sq[g]);
+    const double p01 = d0 * d1, p23 = d2 * d3;
+    const double rw = w * rcp_nr(p01 * p23);
+    const double r01 = rw * p23, r23 = rw * p01;
+    U[c] = d1 * r01;
+    U[c + 1] = d0 * r01;
+    U[c + 2] = d3 * r23;
+    U[c + 3] = d2 * r23;
+  }
+  constexpr int C = 4 * Groups<NB>::NQ;
+#pragma unroll
+  for (int c = C; c + 1 < NB; c += 2) {
+    const double d0 = __builtin_fma(w2, tau2s[c], 1.0), d1 = __builtin_fma(w2, tau2s[c + 1], 1.0);
     const double rw = w * rcp_nr(d0 * d1);
     U[c] = d1 * rw;
     U[c + 1] = d0 * rw;
   }
-  if constexpr (NB & 1) U[NB - 1] = w * rcp_nr(__builtin_fma(w2, tau2[NB - 1], 1.0));
+  if constexpr ((NB - C) & 1) U[NB - 1] = w * rcp_nr(__builtin_fma(w2, tau2s[NB - 1], 1.0));
 }
 
 // --------------------------------------------------------------------------
@@ -286,7 +386,11 @@ __device__ __forceinline__ void unpark(const double *park, int cpw, int grp, dou
 // records for the target gradient).
 // --------------------------------------------------------------------------
 // target waves per SIMD: bounds the register budget of each instantiation
-template <int N, int SP> constexpr int waves_per_simd() { return (SP == 1 && N <= 6) ? 3 : 2; }
+// (three for the small one-lane kernels and for the uniform-tile forward
+// N = 12 two-lane kernels, which fit 168 registers; two elsewhere)
+template <int N, int SP, bool GRAD, int UNI> constexpr int waves_per_simd() {
+  return ((SP == 1 && N <= 6) || (SP == 2 && N == 12 && !GRAD && UNI != 0)) ? 3 : 2;
+}
 
 // UNI (uniform tiles; the plan checks that every active lane of every tile
 // belongs to one material and that spectra hold fewer than 2^29 points):
@@ -295,7 +399,7 @@ template <int N, int SP> constexpr int waves_per_simd() { return (SP == 1 && N <
 //   2: frequency split > 1: wave-uniform spectrum base, per-lane 32-bit
 //      byte offsets (one offset per point for the three arrays).
 template <int N, int SP, bool GRAD, int UNI>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_simd<N, SP>())))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_simd<N, SP, GRAD, UNI>())))
 void fit_kernel(const FitArgs a) {
   using S = Shape<N, SP>;
   constexpr int NB = S::NB, NV = S::NV, NG = S::NG, D = S::D;
@@ -340,6 +444,18 @@ void fit_kernel(const FitArgs a) {
     if constexpr (UNI == 2) return *(const double *)((const char *)p + ((uint32_t)k << 3));
     else return p[k];
   };
+  // The first point of a pass that prefetches one point ahead, read through
+  // the constant address space (the spectra are read-only during a launch).
+  // Loads from two address spaces are not merged, so the compiler keeps the
+  // loop's loads one point ahead instead of folding them with this one into a
+  // single load at the top of every trip (which would expose the load
+  // latency at each point).
+  auto ld_first = [](const double *p, int64_t k) -> double {
+    using cptr = const __attribute__((address_space(4))) double *;
+    if constexpr (UNI == 2) return *(cptr)((const char *)p + ((uint32_t)k << 3));
+    else return ((cptr)p)[k];
+  };
+
   const double damping = a.damping;
   const bool flip = !(a.flags & FLAG_NO_SIGN_FLIP);
 
@@ -358,13 +474,28 @@ void fit_kernel(const FitArgs a) {
       tau[cI] = exp10(t);
     }
   }
-  double tau2[NB];
+  // Grouped basis of the frequency passes: group scales s = 2^-k, tau^2 s,
+  // and tau s (the factor applied after the sums).  Only these are kept;
+  // tau and tau^2 are recovered exactly where needed (ldexp by k).
+  int kq[Groups<NB>::NS];
+  double sq[Groups<NB>::NS], tau2s[NB], ts[NB];
+  {
+    double tau2[NB];
 #pragma unroll
-  for (int cI = 0; cI < NB; ++cI) tau2[cI] = tau[cI] * tau[cI];
+    for (int cI = 0; cI < NB; ++cI) tau2[cI] = tau[cI] * tau[cI];
+    group_scales<NB>(tau2, kq, sq);
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) {
+      tau2s[cI] = group_scale<NB>(kq, cI, tau2[cI]);
+      ts[cI] = group_scale<NB>(kq, cI, tau[cI]);
+    }
+  }
+  auto tau_of = [&](int cI) { return group_unscale<NB>(kq, cI, ts[cI]); };
+  auto tau2_of = [&](int cI) { return group_unscale<NB>(kq, cI, tau2s[cI]); };
 
   // ---- pass 1: Gram, right-hand side, sum of eps'.  Accumulated with
-  // U = w R in place of I = tau U; the factors tau are applied after the
-  // frequency sums.  (The column sums of R, first needed for eps_inf after
+  // U / s = w R / s in place of I = tau U; the factors tau s are applied
+  // after the frequency sums.  (The column sums of R, first needed for eps_inf after
   // the refinement, are taken in pass 2, which forms every R anyway.)
   double G[NG], bv[NB], Sv[NB];
 #pragma unroll
@@ -379,9 +510,9 @@ void fit_kernel(const FitArgs a) {
     int64_t k = fl;
     double w_n = 0, er_n = 0, ei_n = 0;
     if (k < F) {
-      w_n = ld(om, k);
-      er_n = ld(epr, k);
-      ei_n = ld(epi, k);
+      w_n = ld_first(om, k);
+      er_n = ld_first(epr, k);
+      ei_n = ld_first(epi, k);
     }
     for (; k < F; k += SF) {
       const double w = w_n, er = er_n, ei = ei_n;
@@ -390,7 +521,7 @@ void fit_kernel(const FitArgs a) {
       er_n = ld(epr, kn);
       ei_n = ld(epi, kn);
       double Iv[NV];
-      basis_U<NB>(w, w * w, tau2, Iv);
+      basis_Us<NB>(w, w * w, tau2s, sq, Iv);
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) bv[cI] = __builtin_fma(Iv[cI], ei, bv[cI]);
       if constexpr (SP > 1) {
@@ -414,20 +545,20 @@ void fit_kernel(const FitArgs a) {
   if constexpr (SP > 1) {
     double tv[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) tv[v] = v < NB ? tau[v] : ring_fetch<SP>(tau[v % NB], v / NB);
+    for (int v = 0; v < NV; ++v) tv[v] = v < NB ? ts[v] : ring_fetch<SP>(ts[v % NB], v / NB);
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI)
 #pragma unroll
-      for (int d = 0; d <= D; ++d) G[cI * (D + 1) + d] *= tau[cI] * tv[cI + d];
+      for (int d = 0; d <= D; ++d) G[cI * (D + 1) + d] *= ts[cI] * tv[cI + d];
   } else {
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
-      for (int j = i; j < N; ++j) G[tri(N, i, j)] *= tau[i] * tau[j];
+      for (int j = i; j < N; ++j) G[tri(N, i, j)] *= ts[i] * ts[j];
   }
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) {
-    bv[cI] = freq_sum(bv[cI], SP, SL) * tau[cI];
+    bv[cI] = freq_sum(bv[cI], SP, SL) * ts[cI];
     bad = bad || !(fabs(bv[cI]) < INFINITY);
   }
   sum_er = freq_sum(sum_er, SP, SL);
@@ -508,13 +639,13 @@ void fit_kernel(const FitArgs a) {
     gl[cI] = 0.0;
   }
   {
-    // I z = w sum_i (tau_i z_i) R_i, and I^T r = tau (R^T (w r))
+    // I z = w sum_i (tau_i s_i z_i) (R_i / s_i), and I^T r = tau s ((R / s)^T (w r))
     double zs[NB];
 #pragma unroll
-    for (int cI = 0; cI < NB; ++cI) zs[cI] = zc[cI] * tau[cI];
-    // R at point k (for the adjoint its column sums taken on the way) and w_k r_k
+    for (int cI = 0; cI < NB; ++cI) zs[cI] = zc[cI] * ts[cI];
+    // R / s at point k (for the adjoint its column sums taken on the way) and w_k r_k
     auto resid = [&](double w, double ei, double *Rv) {
-      basis_R<NB>(w * w, tau2, Rv);
+      basis_Rs<NB>(w * w, tau2s, sq, Rv);
       double part = 0.0;
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
@@ -571,8 +702,8 @@ void fit_kernel(const FitArgs a) {
   }
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) {
-    gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL) * tau[cI];
-    if constexpr (GRAD) Sv[cI] = freq_sum(Sv[cI], SP, SL);
+    gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL) * ts[cI];
+    if constexpr (GRAD) Sv[cI] = freq_sum(Sv[cI], SP, SL) * pole_scale<NB>(sq, cI);
   }
 
   // correction: zt += A^-1 (D^-1 g - damping zt)
@@ -623,10 +754,10 @@ void fit_kernel(const FitArgs a) {
   } else if (F > 0) {
     const double w0 = ld(om, 0);
     double Rv[NB];
-    basis_R<NB>(w0 * w0, tau2, Rv);
+    basis_Rs<NB>(w0 * w0, tau2s, sq, Rv);
     double pr = 0.0;
 #pragma unroll
-    for (int cI = 0; cI < NB; ++cI) pr = __builtin_fma(wv_[cI], Rv[cI], pr);
+    for (int cI = 0; cI < NB; ++cI) pr = __builtin_fma(wv_[cI] * pole_scale<NB>(sq, cI), Rv[cI], pr);
     shift = ld(epr, 0) - group_sum<SP>(pr);
   }
 
@@ -635,18 +766,26 @@ void fit_kernel(const FitArgs a) {
 #pragma unroll
   for (int cI = 0; cI < (GRAD ? NB : 1); ++cI) gw[cI] = gw2[cI] = 0.0;
 #pragma unroll
-  for (int cI = 0; cI < NB; ++cI) wt[cI] = wv_[cI] * tau[cI];
-  // from the basis values of every point; rr is eps' - shift - R w, and sa
-  // collects its sum (the forward kernels' shifted mean)
+  for (int cI = 0; cI < NB; ++cI) wt[cI] = wv_[cI] * tau_of(cI);
+  // from the basis values of every point (grouped form: the weights carry the
+  // scales, and the adjoint's sums g_w get theirs afterwards); rr is
+  // eps' - shift - R w, and sa collects its sum (the forward kernels' shifted
+  // mean)
   auto pass3_basis = [&](double &sa) -> double {
     double acc = 0.0;
+    double wvs[NB], wts[NB];
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) {
+      wvs[cI] = wv_[cI] * pole_scale<NB>(sq, cI);
+      wts[cI] = wv_[cI] * ts[cI];
+    }
     sa = 0.0;
     int64_t k = fl;
     double w_n = 0, er_n = 0, ei_n = 0;
     if (k < F) {
-      w_n = ld(om, k);
-      er_n = ld(epr, k);
-      ei_n = ld(epi, k);
+      w_n = ld_first(om, k);
+      er_n = ld_first(epr, k);
+      ei_n = ld_first(epi, k);
     }
     for (; k < F; k += SF) {
       const double w = w_n, er = er_n, ei = ei_n;
@@ -655,12 +794,12 @@ void fit_kernel(const FitArgs a) {
       er_n = ld(epr, kn);
       ei_n = ld(epi, kn);
       double Rv[NB];
-      basis_R<NB>(w * w, tau2, Rv);
+      basis_Rs<NB>(w * w, tau2s, sq, Rv);
       double pr = 0.0, pi = 0.0;
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
-        pr = __builtin_fma(wv_[cI], Rv[cI], pr);
-        pi = __builtin_fma(wt[cI], Rv[cI], pi);
+        pr = __builtin_fma(wvs[cI], Rv[cI], pr);
+        pi = __builtin_fma(wts[cI], Rv[cI], pi);
       }
       const double rr = (er - shift) - group_sum<SP>(pr);
       const double ri = __builtin_fma(-w, group_sum<SP>(pi), ei);
@@ -668,7 +807,7 @@ void fit_kernel(const FitArgs a) {
       acc = __builtin_fma(rr, rr, acc);
       acc = __builtin_fma(ri, ri, acc);
       if constexpr (GRAD) {
-        // g_w = R^T r' + I^T r'' = R^T r' + tau (R^T (w r''))
+        // g_w = R^T r' + I^T r'' = s ((R/s)^T r' + tau ((R/s)^T (w r'')))
         const double wri = w * ri;
 #pragma unroll
         for (int cI = 0; cI < NB; ++cI) {
@@ -695,13 +834,13 @@ void fit_kernel(const FitArgs a) {
     // finite.
     double tmax = 0.0;
 #pragma unroll
-    for (int cI = 0; cI < NB; ++cI) tmax = tau2[cI] > tmax ? tau2[cI] : tmax;
+    for (int cI = 0; cI < NB; ++cI) tmax = tau2_of(cI) > tmax ? tau2_of(cI) : tmax;
     const double isc = tmax > 0.0 ? 1.0 / tmax : 1.0;
     double tp[NB], qc[NB + 1], cr[NB], ci[NB];
     double pnz = 1.0;   // product of the nonzero scaled tau^2: the smallest coefficient
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) {
-      tp[cI] = tau2[cI] * isc;
+      tp[cI] = tau2_of(cI) * isc;
       pnz *= tp[cI] > 0.0 ? tp[cI] : 1.0;
     }
     qc[0] = 1.0;
@@ -745,9 +884,9 @@ void fit_kernel(const FitArgs a) {
       int64_t k = fl;
       double w_n = 0, er_n = 0, ei_n = 0;
       if (k < F) {
-        w_n = ld(om, k);
-        er_n = ld(epr, k);
-        ei_n = ld(epi, k);
+        w_n = ld_first(om, k);
+        er_n = ld_first(epr, k);
+        ei_n = ld_first(epi, k);
       }
       for (; k < F; k += SF) {
         const double w = w_n, er = er_n, ei = ei_n;
@@ -810,7 +949,7 @@ void fit_kernel(const FitArgs a) {
     double mt[NB], mu[NB];
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) {
-      gw[cI] = -2.0 * __builtin_fma(tau[cI], freq_sum(gw2[cI], SP, SL), freq_sum(gw[cI], SP, SL));
+      gw[cI] = -2.0 * pole_scale<NB>(sq, cI) * __builtin_fma(tau_of(cI), freq_sum(gw2[cI], SP, SL), freq_sum(gw[cI], SP, SL));
       const double s = (flip && zc[cI] < 0.0) ? -1.0 : 1.0;
       mt[cI] = s * gw[cI] * invd_own[cI];
     }
@@ -842,20 +981,22 @@ void fit_kernel(const FitArgs a) {
     // dR/dtheta = -2 ln10 I^2 and dI/dtheta = ln10 I (2R - 1); ln10 is applied
     // after the sums, and the dot products run over R with tau-scaled weights
     // as in the forward passes.
-    double T1[NB], T2[NB], T3[NB], T4[NB], zt4[NB], mt4[NB];
+    double T1[NB], T2[NB], T3[NB], T4[NB], zt4[NB], mt4[NB], tv4[NB], tv4s[NB];
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) {
       T1[cI] = T2[cI] = T3[cI] = T4[cI] = 0.0;
-      zt4[cI] = zc[cI] * tau[cI];
-      mt4[cI] = mu[cI] * tau[cI];
+      tv4[cI] = tau_of(cI);
+      tv4s[cI] = tau2_of(cI);
+      zt4[cI] = zc[cI] * tv4[cI];
+      mt4[cI] = mu[cI] * tv4[cI];
     }
     {
       int64_t k = fl;
       double w_n = 0, er_n = 0, ei_n = 0;
       if (k < F) {
-        w_n = ld(om, k);
-        er_n = ld(epr, k);
-        ei_n = ld(epi, k);
+        w_n = ld_first(om, k);
+        er_n = ld_first(epr, k);
+        ei_n = ld_first(epi, k);
       }
       for (; k < F; k += SF) {
         const double w = w_n, er = er_n, ei = ei_n;
@@ -864,7 +1005,7 @@ void fit_kernel(const FitArgs a) {
         er_n = ld(epr, kn);
         ei_n = ld(epi, kn);
         double Rv[NB];
-        basis_R<NB>(w * w, tau2, Rv);
+        basis_R<NB>(w * w, tv4s, Rv);
         double pr = 0.0, pi = 0.0, pz = 0.0, pm = 0.0;
 #pragma unroll
         for (int cI = 0; cI < NB; ++cI) {
@@ -881,7 +1022,7 @@ void fit_kernel(const FitArgs a) {
 #pragma unroll
         for (int cI = 0; cI < NB; ++cI) {
           const double R = Rv[cI];
-          const double I = (w * tau[cI]) * R;
+          const double I = (w * tv4[cI]) * R;
           const double dI = I * __builtin_fma(2.0, R, -1.0);
           T1[cI] = __builtin_fma(I * m2rr, I, __builtin_fma(dI, ri, T1[cI]));
           T2[cI] = __builtin_fma(dI, qz, T2[cI]);
@@ -911,7 +1052,7 @@ void fit_kernel(const FitArgs a) {
           rec[p] = wv_[cI];
           rec[N + p] = zc[cI];
           rec[2 * N + p] = mu[cI];
-          rec[3 * N + p] = tau[cI];
+          rec[3 * N + p] = tv4[cI];
           if (p == 0) {
             rec[4 * N] = einf;
             rec[4 * N + 1] = st == ST_OK ? gc : 0.0;

@@ -172,6 +172,26 @@ def test_cost_parity_extreme_relaxation_times(D, orc, N):
     _check_eval(D, orc, wl, theta, tag=f"extreme N{N}")
 
 
+@pytest.mark.parametrize("N", [4, 8, 13, 20])
+def test_cost_parity_scaled_pole_groups(D, orc, N):
+    """The frequency passes share one reciprocal among four poles, on factors
+    1 + (w tau)^2 scaled per group by a power of two fixed from the largest
+    admissible frequency.  The same HN-family spectra and candidates on the
+    ordinary band, on the band moved down by 33 decades (tau near 1e22..1e26:
+    every group scaled by about 2^-200) and moved up by 18 decades (w up to
+    6e28 rad/s, tau near 1e-29: no group scaled)."""
+    import dataclasses
+    base = small_uniform(2, 150, N, 64, seed=70 + N, kinds=[W.KIND_HN, W.KIND_CC, W.KIND_CD])
+    theta0 = W.draw_theta(base.cand_off, base.n_poles, base.lb, base.ub, base.ld, seed=N)
+    for shift in (0, -33, 18):
+        params = base.params.copy()
+        params[:, 2] *= 10.0 ** -shift          # tau0 of the HN family
+        wl = dataclasses.replace(base, name=f"{base.name} band x1e{shift}", params=params,
+                                 omega=base.omega * 10.0 ** shift, lb=base.lb - shift, ub=base.ub - shift)
+        theta = theta0.copy()
+        theta[:, :N] -= shift
+        _check_eval(D, orc, wl, theta, tag=f"groups N{N} band x1e{shift}")
+
 def test_cost_parity_ragged_batch(D, orc):
     wl = small_ragged(60, seed=7)
     theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=3)
