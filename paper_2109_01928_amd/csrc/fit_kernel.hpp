@@ -514,6 +514,8 @@ void fit_kernel(const FitArgs a) {
       er_n = ld_first(epr, k);
       ei_n = ld_first(epi, k);
     }
+    // two points per trip: the reciprocal chains of their bases interleave
+#pragma unroll 2
     for (; k < F; k += SF) {
       const double w = w_n, er = er_n, ei = ei_n;
       const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
@@ -888,6 +890,8 @@ void fit_kernel(const FitArgs a) {
         er_n = ld_first(epr, k);
         ei_n = ld_first(epi, k);
       }
+      // two points per trip: their Horner and reciprocal chains interleave
+#pragma unroll 2
       for (; k < F; k += SF) {
         const double w = w_n, er = er_n, ei = ei_n;
         const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
