@@ -148,12 +148,14 @@ __device__ __forceinline__ void basis_R(double w2, const double *tau2, double *R
 // product lies in [2^-1012, 2^990] at every admissible frequency and every
 // reciprocal is a normal number.  With tau^2 s in place of tau^2 and s in
 // place of 1, every intermediate is the unscaled value times an exact power
-// of two (the same roundings); the group's basis values come out divided by
+// of two (the same roundings, barring underflow of tiny products, which the
+// scaled form suffers less); the group's basis values come out divided by
 // s, and s is applied with tau after the frequency sums.  Any smaller s of
-// the same form keeps these bounds, so a wave takes, per group index, the
-// smallest s of its lanes: s is then wave-uniform and the fused add reads it
-// from a scalar register (a third vector operand of a 64-bit FMA costs issue
-// bandwidth), and each lane's results are still exactly its unscaled ones.
+// the same form down to 2^-253 keeps these bounds, so a wave takes, per
+// group index, the smallest s of its lanes: s is then wave-uniform and the
+// fused add reads it from a scalar register (a third vector operand of a
+// 64-bit FMA costs issue bandwidth), and each lane's results do not depend
+// on the other lanes of its wave.
 // --------------------------------------------------------------------------
 constexpr double OMEGA_BOUND = 1e45;   // admissible angular frequencies: 0 < w < OMEGA_BOUND
 
@@ -174,7 +176,11 @@ __device__ __forceinline__ void group_scales(const double *tau2, int *kq, double
 #pragma unroll
     for (int t = 0; t < 4; ++t)
       e += __builtin_amdgcn_frexp_exp(__builtin_fma(OMEGA_BOUND * OMEGA_BOUND, tau2[4 * g + t], 1.0));
-    int k = e > 990 ? (e - 990 + 3) >> 2 : 0;   // 0 <= k <= 253
+    int k = e > 990 ? (e - 990 + 3) >> 2 : 0;
+    // |log10 tau| <= 30 gives e <= 1996, k <= 252; the cap keeps a lane with
+    // rejected input (its results are discarded) from scaling its wave's
+    // valid lanes out of range
+    k = k < 253 ? k : 253;
 #pragma unroll
     for (int m = 1; m < WAVE; m <<= 1) {
       const int o = __shfl_xor(k, m, WAVE);
@@ -219,8 +225,10 @@ __device__ __forceinline__ void basis_Rs(double w2, const double *tau2s, const d
 }
 
 // U / s with U = w R directly (the Gram pass needs no R): the factor w enters
-// once per group after the reciprocal (U0 = d1 ((w r) p23), ...), and once per
-// pair for the paired poles (U0 = d1 (w r)).
+// after the group's reciprocal is split, U0 = d1 (w (r p23)), ... (r p23 =
+// 1/p01 <= 2^506, so no intermediate overflows even where the wave's scale is
+// far below the lane's own and r is near 2^1012), and once per pair for the
+// paired poles (U0 = d1 (w r)).
 template <int NB>
 __device__ __forceinline__ void basis_Us(double w, double w2, const double *tau2s, const double *sq, double *U) {
 #pragma unroll
@@ -229,8 +237,8 @@ __device__ __forceinline__ void basis_Us(double w, double w2, const double *tau2
     const double d0 = __builtin_fma(w2, tau2s[c], sq[g]), d1 = __builtin_fma(w2, tau2s[c + 1], sq[g]);
     const double d2 = __builtin_fma(w2, tau2s[c + 2], sq[g]), d3 = __builtin_fma(w2, tau2s[c + 3], sq[g]);
     const double p01 = d0 * d1, p23 = d2 * d3;
-    const double rw = w * rcp_nr(p01 * p23);
-    const double r01 = rw * p23, r23 = rw * p01;
+    const double r = rcp_nr(p01 * p23);
+    const double r01 = w * (r * p23), r23 = w * (r * p01);
     U[c] = d1 * r01;
     U[c + 1] = d0 * r01;
     U[c + 2] = d3 * r23;

@@ -179,7 +179,8 @@ def test_cost_parity_scaled_pole_groups(D, orc, N):
     admissible frequency.  The same HN-family spectra and candidates on the
     ordinary band, on the band moved down by 33 decades (tau near 1e22..1e26:
     every group scaled by about 2^-200) and moved up by 18 decades (w up to
-    6e28 rad/s, tau near 1e-29: no group scaled)."""
+    6e28 rad/s, tau near 1e-29: no group scaled); on each, a rejected
+    candidate sets its wave's scale to the cap, 2^-253."""
     import dataclasses
     base = small_uniform(2, 150, N, 64, seed=70 + N, kinds=[W.KIND_HN, W.KIND_CC, W.KIND_CD])
     theta0 = W.draw_theta(base.cand_off, base.n_poles, base.lb, base.ub, base.ld, seed=N)
@@ -190,6 +191,10 @@ def test_cost_parity_scaled_pole_groups(D, orc, N):
                                  omega=base.omega * 10.0 ** shift, lb=base.lb - shift, ub=base.ub - shift)
         theta = theta0.copy()
         theta[:, :N] -= shift
+        # one rejected candidate (|log10 tau| > 30) among valid ones: its group
+        # scale is capped at 2^-253, and the wave's valid lanes then work far
+        # below their own scale (their reciprocals near 2^1012)
+        theta[5, :N] = 100.0
         _check_eval(D, orc, wl, theta, tag=f"groups N{N} band x1e{shift}")
 
 def test_cost_parity_ragged_batch(D, orc):
@@ -205,6 +210,7 @@ def test_edge_cases_and_status(D, orc):
     theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=1)
     theta[1, 2] = np.nan          # BADINPUT
     theta[2, 0] = 70.0            # |log10 tau| > 30: rejected
+    theta[6, :] = 100.0           # rejected, and its group scale must not reach the valid lanes of its wave
     theta[3, 1] = theta[3, 0]     # duplicate tau: singular without damping
     theta[4, :] = [-11.0, -10.0, -9.0, -8.0]
     _check_eval(D, orc, wl, theta, damping=1e-8, tag="edge")
