@@ -468,16 +468,14 @@ void fit_kernel(const FitArgs a) {
   const bool flip = !(a.flags & FLAG_NO_SIGN_FLIP);
 
   // ---- relaxation times of the owned poles
-  double tau[NB], th[NB];
+  double tau[NB];
   bool bad = false;
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) {
     const int p = q * NB + cI;
-    th[cI] = 0.0;
     tau[cI] = 0.0;
     if (p < N && active) {
       const double t = a.theta[c * a.ld + p];
-      th[cI] = t;
       bad = bad || !(fabs(t) <= THETA_LIMIT);
       tau[cI] = exp10(t);
     }
