@@ -84,7 +84,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the fit shards by material with no communication, "
-              "and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
+              "so the per-GPU rate is the figure; run it with --gpus 1 on a single MI355X.", file=sys.stderr)
         sys.exit(2)
 
     import torch
