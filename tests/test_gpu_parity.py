@@ -197,6 +197,28 @@ def test_cost_parity_scaled_pole_groups(D, orc, N):
         theta[5, :N] = 100.0
         _check_eval(D, orc, wl, theta, tag=f"groups N{N} band x1e{shift}")
 
+@pytest.mark.parametrize("N", [4, 5, 8, 9, 12, 13, 16, 17, 20, 24])
+def test_cost_parity_mixed_scale_waves(D, orc, N):
+    """Two materials with the same HN-family spectrum shape, one on the
+    ordinary band and one on the band moved down by 33 decades (tau near
+    1e22..1e26, group scales near 2^-200), with 37 candidates each, so that
+    tiles mix the two: the ordinary lanes run at the other material's scale,
+    far below their own.  Every candidate is in band (well posed), so weights
+    are compared too."""
+    import dataclasses
+    a = small_uniform(1, 150, N, 37, seed=400 + N, kinds=[W.KIND_HN, W.KIND_CC, W.KIND_CD])
+    shift = -33
+    params_b = a.params.copy()
+    params_b[:, 2] *= 10.0 ** -shift
+    wl = dataclasses.replace(
+        a, name=f"{a.name} + band x1e{shift}", kind=np.concatenate([a.kind, a.kind]),
+        params=np.concatenate([a.params, params_b]), f_off=W.offsets([150, 150]),
+        omega=np.concatenate([a.omega, a.omega * 10.0 ** shift]), n_poles=np.concatenate([a.n_poles, a.n_poles]),
+        cand_off=W.offsets([37, 37]), lb=np.concatenate([a.lb, a.lb - shift]), ub=np.concatenate([a.ub, a.ub - shift]))
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=N)
+    _check_eval(D, orc, wl, theta, tag=f"mixed-scale N{N}")
+    _check_eval(D, orc, wl, theta, split=1, tag=f"mixed-scale N{N}")
+
 def test_cost_parity_ragged_batch(D, orc):
     wl = small_ragged(60, seed=7)
     theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=3)
