@@ -501,8 +501,9 @@ void fit_kernel(const FitArgs a) {
 
   // ---- pass 1: Gram, right-hand side, sum of eps'.  Accumulated with
   // U / s = w R / s in place of I = tau U; the factors tau s are applied
-  // after the frequency sums.  (The column sums of R, first needed for eps_inf after
-  // the refinement, are taken in pass 2, which forms every R anyway.)
+  // after the frequency sums.  (The adjoint's column sums of R, which it needs
+  // for eps_inf before its pass 3, are taken in pass 2, which forms every R
+  // anyway; the forward kernels take eps_inf from the cost pass.)
   double G[NG], bv[NB], Sv[NB];
 #pragma unroll
   for (int e = 0; e < NG; ++e) G[e] = 0.0;
