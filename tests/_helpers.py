@@ -75,6 +75,21 @@ def small_uniform(M, F, N, P, seed, fmin=1e6, fmax=1e10, kinds=None):
                       np.full(M, N, np.int32), W.offsets([P] * M), np.full(M, lb), np.full(M, ub), 1, seed=seed)
 
 
+def mixed_scale_workload(N, F=150, P=37, seed=400, shift=-33):
+    """Two materials with the same HN-family spectrum shape: one on the
+    ordinary band, one on the band moved by `shift` decades (tau0 and the tau
+    search box moved the other way).  With P not a multiple of the candidates
+    per wave, tiles hold candidates of both."""
+    import dataclasses
+    a = small_uniform(1, F, N, P, seed=seed + N, kinds=[W.KIND_HN, W.KIND_CC, W.KIND_CD])
+    params_b = a.params.copy()
+    params_b[:, 2] *= 10.0 ** -shift
+    return dataclasses.replace(
+        a, name=f"{a.name} + band x1e{shift}", kind=np.concatenate([a.kind, a.kind]),
+        params=np.concatenate([a.params, params_b]), f_off=W.offsets([F, F]),
+        omega=np.concatenate([a.omega, a.omega * 10.0 ** shift]), n_poles=np.concatenate([a.n_poles, a.n_poles]),
+        cand_off=W.offsets([P, P]), lb=np.concatenate([a.lb, a.lb - shift]), ub=np.concatenate([a.ub, a.ub - shift]))
+
 def small_ragged(M, seed, Fr=(20, 700), Nr=(1, 24), Pr=(0, 150)):
     kind, params = W.draw_mixed(M, seed, 1e6, 1e10)
     g = W.rng(seed, 9)

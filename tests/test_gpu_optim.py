@@ -5,8 +5,8 @@ import numpy as np
 import pytest
 
 import workloads as W
-from _helpers import (COST_RTOL, attributed_cost_err, cost_floor, cost_rel_err, small_ragged, small_uniform,
-                      targets_oracle)
+from _helpers import (COST_RTOL, attributed_cost_err, cost_floor, cost_rel_err, mixed_scale_workload, small_ragged,
+                      small_uniform, targets_oracle)
 
 pytestmark = pytest.mark.gpu
 
@@ -136,6 +136,38 @@ def test_adjoint_matches_oracle(D, orc, N, F, flags, damping):
             s, e = wl.f_off[m], wl.f_off[m + 1]
             assert np.max(np.abs(a[s:e] - o[s:e])) <= 1e-6 * np.max(np.abs(o[s:e]))
 
+
+
+@pytest.mark.parametrize("N", [4, 8, 12, 20])
+def test_adjoint_mixed_scale_waves(D, orc, N):
+    """The adjoint where the ordinary band and a band 33 decades down share
+    waves (the frequency passes then run the ordinary lanes at group scales
+    near 2^-200): costs, theta-gradients and target gradients against the
+    oracle."""
+    import torch
+    wl = mixed_scale_workload(N)
+    er, ei = targets_oracle(orc, wl)
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=5)
+    gc = np.linspace(0.5, 2.0, wl.P)
+    ob = orc.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, er, ei)
+    oc, og, ogr, ogi, ost = orc.fit_grad(ob, theta, grad_cost=gc)
+    b = _batch(D, wl, er, ei)
+    plan = D.Plan(b)
+    c, g, gr, gi, st = D.fit_eval_grad(plan, b, _t(theta), grad_cost=_t(gc), targets=True)
+    torch.cuda.synchronize()
+    print(f"[adjoint mixed-scale N{N}] plan={plan.info()}", flush=True)
+    np.testing.assert_array_equal(st.cpu().numpy(), ost)
+    rel = cost_rel_err(c.cpu().numpy(), oc, cost_floor(wl, er, ei))
+    rel, _ = attributed_cost_err(orc, ob, theta, c.cpu().numpy(), cost_floor(wl, er, ei), 1e-8, 0, rel)
+    assert rel.max() <= COST_RTOL
+    g = g.cpu().numpy()
+    gerr = np.max(np.abs(g - og), axis=1) / np.max(np.abs(og), axis=1)
+    print(f"[adjoint mixed-scale N{N}] max theta-gradient rel err {gerr.max():.2e}", flush=True)
+    assert np.all(gerr <= 1e-6)
+    for a, o in ((gr.cpu().numpy(), ogr), (gi.cpu().numpy(), ogi)):
+        for m in range(wl.M):
+            s, e = wl.f_off[m], wl.f_off[m + 1]
+            assert np.max(np.abs(a[s:e] - o[s:e])) <= 1e-6 * np.max(np.abs(o[s:e]))
 
 def test_adjoint_ragged_matches_oracle(D, orc):
     """Several pole counts at once (their buckets run on concurrent streams),

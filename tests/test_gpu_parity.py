@@ -10,7 +10,7 @@ import pytest
 
 import workloads as W
 from _helpers import (COST_RTOL, WEIGHT_RTOL, attributed_cost_err, attributed_weight_err, cost_floor, cost_rel_err,
-                      poles_per_cand, small_ragged, small_uniform, targets_oracle)
+                      mixed_scale_workload, poles_per_cand, small_ragged, small_uniform, targets_oracle)
 
 pytestmark = pytest.mark.gpu
 
@@ -205,16 +205,7 @@ def test_cost_parity_mixed_scale_waves(D, orc, N):
     tiles mix the two: the ordinary lanes run at the other material's scale,
     far below their own.  Every candidate is in band (well posed), so weights
     are compared too."""
-    import dataclasses
-    a = small_uniform(1, 150, N, 37, seed=400 + N, kinds=[W.KIND_HN, W.KIND_CC, W.KIND_CD])
-    shift = -33
-    params_b = a.params.copy()
-    params_b[:, 2] *= 10.0 ** -shift
-    wl = dataclasses.replace(
-        a, name=f"{a.name} + band x1e{shift}", kind=np.concatenate([a.kind, a.kind]),
-        params=np.concatenate([a.params, params_b]), f_off=W.offsets([150, 150]),
-        omega=np.concatenate([a.omega, a.omega * 10.0 ** shift]), n_poles=np.concatenate([a.n_poles, a.n_poles]),
-        cand_off=W.offsets([37, 37]), lb=np.concatenate([a.lb, a.lb - shift]), ub=np.concatenate([a.ub, a.ub - shift]))
+    wl = mixed_scale_workload(N)
     theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=N)
     _check_eval(D, orc, wl, theta, tag=f"mixed-scale N{N}")
     _check_eval(D, orc, wl, theta, split=1, tag=f"mixed-scale N{N}")
