@@ -123,9 +123,20 @@ __global__ __launch_bounds__(256) void pso_step_kernel(const PsoArgs a) {
 
   const bool social = a.gbest_idx[m] >= 0;
   const double lo = a.lb[m], hi = a.ub[m];
+  // one element (particle, dimension) per thread; the index split in 32-bit
+  // arithmetic when the material's elements fit (always, at practical sizes)
+  const bool idx32 = P * N < ((int64_t)1 << 31);
   for (int64_t e = tid; e < P * N; e += blockDim.x) {
-    const int64_t p = e / N;
-    const int d = (int)(e - p * N);
+    int64_t p;
+    int d;
+    if (idx32) {
+      const uint32_t q = (uint32_t)e / (uint32_t)N;
+      p = q;
+      d = (int)((uint32_t)e - q * (uint32_t)N);
+    } else {
+      p = e / N;
+      d = (int)(e - p * N);
+    }
     const int64_t c = c0 + p;
     const U64x4 r = philox4x64((uint64_t)d, (uint64_t)p, (uint64_t)t, STREAM_PSO_STEP, a.seed, (uint64_t)m);
     const double r1 = unit53(r.w[0]), r2 = unit53(r.w[1]);
