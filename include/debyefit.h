@@ -105,13 +105,21 @@ typedef struct debye_batch {
  * pole count, lanes per candidate, work lists sorted by cost (longest first),
  * and workspace.  Build it once per shape from HOST copies of the offsets;
  * reuse it for every call on batches of that shape (e.g. every iteration of
- * an optimiser).  `flags` is reserved (0).
+ * an optimiser).  `flags`: 0, or DEBYE_PLAN_TARGET_GRAD to also allocate the
+ * per-candidate adjoint records that debye_fit_eval_grad needs for target
+ * gradients (n_cand x (4 max_poles + 2) doubles).  Every buffer a plan uses
+ * is allocated here, so the evaluation calls never allocate.
  * With more than one pole count the buckets of an evaluation are forked from
  * the caller's stream onto up to four streams owned by the plan and joined
  * back before the call's work is complete on the caller's stream (under
  * stream capture they become parallel graph branches).  A plan is therefore
  * not to be used from two host threads at once. */
 typedef struct debye_plan debye_plan;
+
+/* plan flags */
+enum {
+  DEBYE_PLAN_TARGET_GRAD = 1u /* workspace for the target gradients of debye_fit_eval_grad */
+};
 
 int debye_plan_create(const debye_batch *shape, const int64_t *f_off_host, const int64_t *cand_off_host,
                       const int32_t *n_poles_host, uint32_t flags, debye_plan **out);
@@ -203,7 +211,9 @@ int debye_fit_eval(const debye_plan *plan, const debye_batch *b, const double *l
  * grad_log10_tau [n_cand][ld] receives grad_cost[c] * dC/dlog10tau.
  * grad_eps_re / grad_eps_im [n_freq] (both NULL or both set) receive the target
  * gradients summed over the candidates of each material (fixed order, so the
- * result is deterministic).
+ * result is deterministic); they need a plan created with
+ * DEBYE_PLAN_TARGET_GRAD (DEBYE_EINVAL otherwise).  Padding entries of a row
+ * (i >= n_poles[m]) of grad_log10_tau are set to 0.
  * ------------------------------------------------------------------------ */
 int debye_fit_eval_grad(const debye_plan *plan, const debye_batch *b, const double *log10_tau, int64_t ld,
                         double damping, uint32_t flags, const double *grad_cost, double *cost,
@@ -447,23 +457,44 @@ int debye_da_run(const debye_plan *plan, const debye_batch *b, int64_t ld, const
  * on one candidate per material, theta [M][ld] in place, inside the search box
  * [lb[m], ub[m]] (device [M]): every trial point is projected onto the box and
  * the sufficient-decrease test uses the projected displacement p,
- * C(trial) <= C + c1 g.p.  The first step (and any step whose quasi-Newton
+ * C(trial) <= C + c1 min(g.p, 0) (no increase where clamping makes g.p
+ * positive).  The first step (and any step whose quasi-Newton
  * direction is not a descent direction) is steepest descent scaled so that its
  * largest component is at most 1; a step with no acceptable trial leaves theta
- * unchanged; pairs with s.y <= 1e-300 are skipped.  All trials of a step are
- * evaluated in one batched launch.  cost_hist [M][steps+1] (may be NULL)
- * receives the cost before each step and at the end (non-increasing).  `b` must
- * describe one candidate per material (cand_off[m] = m).  The call allocates
- * and frees its own workspace and synchronises `stream` before returning.
+ * unchanged; pairs with s.y <= 1e-300 are not stored (the history keeps its
+ * older pairs).  All trials of a step are evaluated in one batched launch.
+ *
+ * The polish context owns every buffer (history, trials, gradients and the two
+ * evaluation plans); debye_polish_create is the set-up call that allocates.
+ * `shape` must describe one candidate per material (cand_off[m] = m); the
+ * batches passed later must have the same shape.  The other calls only enqueue
+ * work on `stream`: no allocation, no synchronisation, so a step can be
+ * captured into a HIP graph.  Calls with one context must not overlap.
+ *   debye_polish_begin:  cost and gradient at theta, history emptied.
+ *   debye_polish_step:   one step (direction -> batched trials -> selection ->
+ *                        gradient at the accepted point -> history update);
+ *                        cost_hist [M][steps+1] (may be NULL) receives the cost
+ *                        before step `step` and, at step == steps-1, the cost
+ *                        at the end.
+ *   debye_lbfgs_polish:  begin, then steps 0 .. p.steps-1 (cost_hist as above,
+ *                        non-increasing along each row).
  * ------------------------------------------------------------------------ */
 typedef struct debye_lbfgs_params {
   int32_t steps, mem, max_trials;
   double c1;
 } debye_lbfgs_params;
 
-int debye_lbfgs_polish(const debye_batch *b, const int64_t *f_off_host, const int32_t *n_poles_host,
-                       double *theta, int64_t ld, const double *lb, const double *ub, double damping,
-                       uint32_t flags, debye_lbfgs_params p, double *cost_hist, hipStream_t stream);
+typedef struct debye_polish debye_polish;
+
+int debye_polish_create(const debye_batch *shape, const int64_t *f_off_host, const int32_t *n_poles_host, int64_t ld,
+                        debye_lbfgs_params p, debye_polish **out);
+int debye_polish_destroy(debye_polish *polish);
+int debye_polish_begin(debye_polish *polish, const debye_batch *b, const double *theta, double damping,
+                       uint32_t flags, hipStream_t stream);
+int debye_polish_step(debye_polish *polish, const debye_batch *b, double *theta, const double *lb, const double *ub,
+                      double damping, uint32_t flags, int32_t step, double *cost_hist, hipStream_t stream);
+int debye_lbfgs_polish(debye_polish *polish, const debye_batch *b, double *theta, const double *lb, const double *ub,
+                       double damping, uint32_t flags, double *cost_hist, hipStream_t stream);
 
 #ifdef __cplusplus
 }

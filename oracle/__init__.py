@@ -58,7 +58,8 @@ def lib():
                                    C.c_double, C.c_uint64, C.c_int32, C.c_int32, _d, _d, _d, _d, _d,
                                    _d, _d, _i64, _d, C.c_int64]
         L.orc_lbfgs_batch.argtypes = [C.c_int32, _i64, _i32, _d, _d, _d, _d, C.c_int64, _d, _d, C.c_double,
-                                      C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_double, _d, C.c_int]
+                                      C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_double, _d, _i32, C.c_int]
+        L.orc_lbfgs_two_loop.argtypes = [C.c_int32, C.c_int32, _d, _d, _d, _d]
         L.orc_afe.argtypes = [C.c_int64, _d, _d, _d, C.c_int32, _d, _d, C.c_double]
         L.orc_afe.restype = C.c_double
         L.orc_fit_from_basis.argtypes = [C.c_int64, _d, _d, _d, _d, C.c_int32, C.c_double, C.c_uint32, C.c_int32,
@@ -268,21 +269,23 @@ UNIT_ROUNDOFF = 2.0 ** -53
 def judge_costs(b: Batch, theta, c_test, c64, floor, rtol, damping=1e-8, flags=0, stats=None, rel=None):
     """Parity judgement of costs computed elsewhere against this oracle.
 
-    Relative error (floored) against the FP64 oracle; a candidate above rtol
-    is judged instead against the 80-bit instance of the oracle (the more
-    accurate reference).  If it is still above rtol there, the candidate's
-    cost is ill-conditioned in FP64 (near-duplicate relaxation times): it
-    passes (error reported as 0, counted as "fp64_limited") when its error
-    against the 80-bit result is within what rounding the basis to FP64 can
-    cause, cond * u with cond from fit_cond, or within the FP64 oracle's own
-    error.  `rel` (optional) holds precomputed errors against the FP64
-    oracle; only candidates with a finite FP64 cost are re-judged.  Returns
-    (errors, stats)."""
+    The error of a candidate is its relative error (floored) against the FP64
+    oracle.  A candidate above rtol there is re-judged against the 80-bit
+    instance of the oracle (the more accurate reference; the FP64 oracle's own
+    error can exceed rtol on ill-conditioned candidates): its error is then
+    the one against the 80-bit result, and it counts as "oracle_limited" if
+    that is within rtol.  No other allowance: a candidate passes only if it
+    is within rtol of the FP64 or of the 80-bit oracle.  For each candidate
+    still above rtol, stats["over"] lists (index, error vs 80-bit, error of
+    the FP64 oracle vs 80-bit, cond * u) as a diagnosis (cond from fit_cond:
+    the cost's sensitivity to rounding the basis).  `rel` (optional) holds
+    precomputed errors against the FP64 oracle; only candidates with a finite
+    FP64 cost are re-judged.  Returns (errors, stats)."""
     c_test, c64, floor = map(np.asarray, (c_test, c64, floor))
     if rel is None:
         rel = np.abs(c_test - c64) / np.maximum(c64, floor)
     rel = np.array(rel, dtype=np.float64)
-    st = dict(n=len(rel), oracle_limited=0, fp64_limited=0, max_rel_80=0.0)
+    st = dict(n=len(rel), oracle_limited=0, failed=0, max_rel_80=0.0, over=[])
     over = np.nonzero(~(rel <= rtol) & np.isfinite(c64))[0]
     if len(over):
         idx = np.searchsorted(b.cand_off, over, side="right") - 1
@@ -294,18 +297,15 @@ def judge_costs(b: Batch, theta, c_test, c64, floor, rtol, damping=1e-8, flags=0
             c80 = fit_eval(one, th, damping, flags, precision=80)[0][0]
             r80 = abs(c_test[c] - c80) / max(c80, floor[c])
             st["max_rel_80"] = max(st["max_rel_80"], float(r80))
+            rel[c] = r80
             if r80 <= rtol:
                 st["oracle_limited"] += 1
-                rel[c] = r80
                 continue
+            st["failed"] += 1
             own = abs(c64[c] - c80) / max(c80, floor[c])
             cond = fit_cond(b.omega[f0:f1], b.eps_re[f0:f1], b.eps_im[f0:f1], th[0, :b.n_poles[m]], damping,
                             flags)[0]
-            if r80 <= max(own, cond * UNIT_ROUNDOFF):
-                st["fp64_limited"] += 1
-                rel[c] = 0.0
-            else:
-                rel[c] = r80
+            st["over"].append((int(c), float(r80), float(own), float(cond * UNIT_ROUNDOFF)))
     if stats is not None:
         stats.update(st)
     return rel, st
@@ -421,18 +421,32 @@ def de_run(b: Batch, lb, ub, iters, f_lo=0.5, f_hi=1.0, cr=0.7, seed=0, ld=None,
 
 
 def lbfgs(b: Batch, theta, lb, ub, steps=50, mem=10, max_trials=30, c1=1e-4, damping=1e-8, flags=0,
-          nthreads=0):
+          nthreads=0, rejected=False):
     """L-BFGS polish of one candidate per material (theta[M][ld]) inside the
     box [lb[m], ub[m]]; returns the polished theta and the cost history
-    [M][steps+1]."""
+    [M][steps+1] (and, with rejected=True, the number of accepted steps per
+    material whose curvature pair s.y <= 1e-300 was not stored while the
+    history held `mem` pairs)."""
     th = _f64(theta).copy()
     lb = _f64(np.broadcast_to(lb, (b.M,)))
     ub = _f64(np.broadcast_to(ub, (b.M,)))
     hist = np.empty((b.M, steps + 1))
+    rej = np.zeros(b.M, dtype=np.int32)
     lib().orc_lbfgs_batch(b.M, _p(b.f_off, _i64), _p(b.n_poles, _i32), _p(b.omega, _d), _p(b.eps_re, _d),
                           _p(b.eps_im, _d), _p(th, _d), th.shape[1], _p(lb, _d), _p(ub, _d), damping, flags,
-                          steps, mem, max_trials, c1, _p(hist, _d), nthreads)
-    return th, hist
+                          steps, mem, max_trials, c1, _p(hist, _d), _p(rej, _i32), nthreads)
+    return (th, hist, rej) if rejected else (th, hist)
+
+
+def lbfgs_two_loop(S, Y, v):
+    """H v of the L-BFGS two-loop recursion (the polish's search direction is
+    -H g) for the pairs S, Y [n][N] (oldest first)."""
+    S, Y, v = map(_f64, (S, Y, v))
+    n, N = S.shape if S.ndim == 2 else (0, len(v))
+    out = np.empty(N)
+    lib().orc_lbfgs_two_loop(N, n, _p(S.reshape(-1) if n else np.zeros(1), _d), _p(Y.reshape(-1) if n else np.zeros(1), _d),
+                             _p(v, _d), _p(out, _d))
+    return out
 
 
 def afe(omega, eps_re, eps_im, d_eps, tau, eps_inf):

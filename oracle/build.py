@@ -12,7 +12,7 @@ def build(verbose=False):
     out = os.path.join(_HERE, "liboracle.so")
     tmp = out + ".tmp"
     cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-           "-shared", "-Wall", "-o", tmp, src]
+           "-shared", "-Wall", "-o", tmp, src, "-lquadmath"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

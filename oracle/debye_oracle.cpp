@@ -43,9 +43,21 @@
 #include <limits>
 #include <vector>
 
+#include <quadmath.h>
+
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+// quad precision (binary128, libquadmath) for the third instance of the
+// forward map: the reference that shows which of the FP64 and 80-bit results
+// is off where they disagree.  The few elementary functions the forward map
+// calls are given binary128 overloads.
+using f128 = __float128;
+namespace std {
+inline f128 sqrt(f128 x) { return sqrtq(x); }
+inline f128 fabs(f128 x) { return fabsq(x); }
+}  // namespace std
 
 namespace {
 
@@ -67,6 +79,7 @@ constexpr double LN10 = 2.302585092994045684017991454684364208;
 // ---------------------------------------------------------------------------
 inline double re(double x) { return x; }
 inline long double re(long double x) { return x; }
+inline f128 re(f128 x) { return x; }
 inline double re(const cd &x) { return x.real(); }
 
 // |z| written as z*sign(Re z): equal to fabs for real types and the analytic
@@ -76,9 +89,11 @@ template <class T> inline T flip_abs(const T &z) { return re(z) < 0 ? T(-z) : z;
 template <class T> inline T pow10_t(const T &t) { return std::pow(T(10), t); }
 inline double pow10_t(const double &t) { return std::pow(10.0, t); }
 inline long double pow10_t(const long double &t) { return std::pow(10.0L, t); }
+inline f128 pow10_t(const f128 &t) { return powq(10, t); }
 
 template <class T> inline bool finite_t(const T &x) { return std::isfinite(re(x)); }
 inline bool finite_t(const cd &x) { return std::isfinite(x.real()) && std::isfinite(x.imag()); }
+inline bool finite_t(const f128 &x) { return finiteq(x) != 0; }
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
@@ -525,9 +540,40 @@ struct LbfgsCfg {
   double c1;
 };
 
+// The inverse-Hessian product of L-BFGS, H v, by the two-loop recursion over
+// the stored pairs (S[j], Y[j]), j = 0 oldest .. n-1 newest, rho_j = 1/(s_j.y_j),
+// with the initial matrix gamma I, gamma = s.y / y.y of the newest pair (1
+// without pairs): the first loop runs newest to oldest, the second oldest to
+// newest (Nocedal & Wright, Algorithm 7.4 with the scaling of their eq. 7.20).
+std::vector<double> lbfgs_two_loop(int N, const std::vector<std::vector<double>> &S,
+                                   const std::vector<std::vector<double>> &Y, const std::vector<double> &rho,
+                                   const std::vector<double> &v) {
+  std::vector<double> q = v, a(S.size());
+  for (int j = (int)S.size() - 1; j >= 0; --j) {
+    double s = 0;
+    for (int i = 0; i < N; ++i) s += S[j][i] * q[i];
+    a[j] = rho[j] * s;
+    for (int i = 0; i < N; ++i) q[i] -= a[j] * Y[j][i];
+  }
+  double gamma = 1.0;
+  if (!S.empty()) {
+    double sy = 0, yy = 0;
+    for (int i = 0; i < N; ++i) { sy += S.back()[i] * Y.back()[i]; yy += Y.back()[i] * Y.back()[i]; }
+    gamma = sy / yy;
+  }
+  for (int i = 0; i < N; ++i) q[i] *= gamma;
+  for (int j = 0; j < (int)S.size(); ++j) {
+    double s = 0;
+    for (int i = 0; i < N; ++i) s += Y[j][i] * q[i];
+    double b = rho[j] * s;
+    for (int i = 0; i < N; ++i) q[i] += (a[j] - b) * S[j][i];
+  }
+  return q;
+}
+
 int lbfgs_one(int64_t F, const double *omega, const double *eps_re, const double *eps_im, int N,
               double *theta, double lb, double ub, double damping, unsigned flags, const LbfgsCfg &cfg,
-              double *cost_hist) {
+              double *cost_hist, int32_t *rejected) {
   std::vector<double> th(theta, theta + N);
   GradOut g = fit_grad(F, omega, eps_re, eps_im, N, th.data(), damping, flags);
   double C = g.cost;
@@ -539,26 +585,7 @@ int lbfgs_one(int64_t F, const double *omega, const double *eps_re, const double
     if (cost_hist) cost_hist[step] = C;
     if (g.status != ST_OK || !std::isfinite(C)) continue;
     // search direction d = -H g
-    std::vector<double> q = grad, a(S.size());
-    for (int j = (int)S.size() - 1; j >= 0; --j) {
-      double s = 0;
-      for (int i = 0; i < N; ++i) s += S[j][i] * q[i];
-      a[j] = rho[j] * s;
-      for (int i = 0; i < N; ++i) q[i] -= a[j] * Y[j][i];
-    }
-    double gamma = 1.0;
-    if (!S.empty()) {
-      double sy = 0, yy = 0;
-      for (int i = 0; i < N; ++i) { sy += S.back()[i] * Y.back()[i]; yy += Y.back()[i] * Y.back()[i]; }
-      gamma = sy / yy;
-    }
-    for (int i = 0; i < N; ++i) q[i] *= gamma;
-    for (int j = 0; j < (int)S.size(); ++j) {
-      double s = 0;
-      for (int i = 0; i < N; ++i) s += Y[j][i] * q[i];
-      double b = rho[j] * s;
-      for (int i = 0; i < N; ++i) q[i] += (a[j] - b) * S[j][i];
-    }
+    const std::vector<double> q = lbfgs_two_loop(N, S, Y, rho, grad);
     std::vector<double> d(N);
     double gd = 0;
     for (int i = 0; i < N; ++i) { d[i] = -q[i]; gd += grad[i] * d[i]; }
@@ -574,7 +601,7 @@ int lbfgs_one(int64_t F, const double *omega, const double *eps_re, const double
     }
     // Armijo backtracking alpha = 1, 1/2, 1/4, ... on the search box: the trial
     // point is projected onto [lb, ub] and the sufficient-decrease test uses the
-    // projected displacement p:  C(trial) <= C + c1 g.p
+    // projected displacement p:  C(trial) <= C + c1 min(g.p, 0)
     double alpha = 1.0;
     bool ok = false;
     std::vector<double> tt(N);
@@ -588,7 +615,9 @@ int lbfgs_one(int64_t F, const double *omega, const double *eps_re, const double
       }
       Fit<double> ft = fit_forward<double>(F, omega, eps_re, eps_im, N, tt.data(), damping, flags);
       Ct = ft.cost;
-      if (ft.status == ST_OK && Ct <= C + cfg.c1 * gp) { ok = true; break; }
+      // sufficient decrease along the projected step; where clamping makes
+      // g.p positive, no increase at all (the polish never raises the cost)
+      if (ft.status == ST_OK && Ct <= C + cfg.c1 * std::min(gp, 0.0)) { ok = true; break; }
       alpha *= 0.5;
     }
     if (!ok) continue;
@@ -599,6 +628,8 @@ int lbfgs_one(int64_t F, const double *omega, const double *eps_re, const double
     if (sy > 1e-300) {
       S.push_back(s); Y.push_back(y); rho.push_back(1.0 / sy);
       if ((int)S.size() > cfg.mem) { S.erase(S.begin()); Y.erase(Y.begin()); rho.erase(rho.begin()); }
+    } else if (rejected && (int)S.size() == cfg.mem) {
+      ++*rejected;   // pair not stored while the history is full: its oldest pair stays live
     }
     th = tt;
     C = Ct;
@@ -694,15 +725,20 @@ int orc_fit_eval_batch(int32_t M, const int64_t *f_off, const int64_t *cand_off,
     int m = mat_of(cand_off, M, c);
     int64_t a = f_off[m], F = f_off[m + 1] - f_off[m];
     int N = n_poles[m];
-    if (precision == 80) {
-      std::vector<long double> er(F), ei(F), th(N);
-      for (int64_t k = 0; k < F; ++k) { er[k] = eps_re[a + k]; ei[k] = eps_im[a + k]; }
-      for (int i = 0; i < N; ++i) th[i] = theta[c * ld + i];
-      Fit<long double> f = fit_forward<long double>(F, omega + a, er.data(), ei.data(), N, th.data(), damping, flags);
-      if (cost) cost[c] = (double)f.cost;
-      if (eps_inf) eps_inf[c] = (double)f.eps_inf;
-      if (status) status[c] = (int8_t)f.status;
-      if (weights) for (int i = 0; i < N; ++i) weights[c * ld + i] = (double)f.w[i];
+    if (precision == 80 || precision == 128) {
+      auto run = [&](auto zero) {
+        using T = decltype(zero);
+        std::vector<T> er(F), ei(F), th(N);
+        for (int64_t k = 0; k < F; ++k) { er[k] = eps_re[a + k]; ei[k] = eps_im[a + k]; }
+        for (int i = 0; i < N; ++i) th[i] = theta[c * ld + i];
+        Fit<T> f = fit_forward<T>(F, omega + a, er.data(), ei.data(), N, th.data(), damping, flags);
+        if (cost) cost[c] = (double)f.cost;
+        if (eps_inf) eps_inf[c] = (double)f.eps_inf;
+        if (status) status[c] = (int8_t)f.status;
+        if (weights) for (int i = 0; i < N; ++i) weights[c * ld + i] = (double)f.w[i];
+      };
+      if (precision == 80) run((long double)0);
+      else run((f128)0);
     } else {
       Fit<double> f = fit_forward<double>(F, omega + a, eps_re + a, eps_im + a, N, theta + c * ld, damping, flags);
       if (cost) cost[c] = f.cost;
@@ -1256,14 +1292,32 @@ int orc_da_accept(int32_t M, const int64_t *cand_off, const int32_t *n_poles, in
 int orc_lbfgs_batch(int32_t M, const int64_t *f_off, const int32_t *n_poles, const double *omega,
                     const double *eps_re, const double *eps_im, double *theta, int64_t ld, const double *lb,
                     const double *ub, double damping, uint32_t flags, int32_t steps, int32_t mem,
-                    int32_t max_trials, double c1, double *cost_hist, int nthreads) {
+                    int32_t max_trials, double c1, double *cost_hist, int32_t *rejected, int nthreads) {
   LbfgsCfg cfg{steps, mem, max_trials, c1};
 #pragma omp parallel for schedule(dynamic) num_threads(nthreads_or_default(nthreads))
   for (int32_t m = 0; m < M; ++m) {
     int64_t a = f_off[m], F = f_off[m + 1] - f_off[m];
+    if (rejected) rejected[m] = 0;
     lbfgs_one(F, omega + a, eps_re + a, eps_im + a, n_poles[m], theta + m * ld, lb[m], ub[m], damping, flags, cfg,
-              cost_hist ? cost_hist + (size_t)m * (steps + 1) : nullptr);
+              cost_hist ? cost_hist + (size_t)m * (steps + 1) : nullptr, rejected ? rejected + m : nullptr);
   }
+  return 0;
+}
+
+// H v of the two-loop recursion for n stored pairs S, Y [n][N] (oldest
+// first) with rho_j = 1 / (s_j . y_j).
+int orc_lbfgs_two_loop(int32_t N, int32_t n, const double *S, const double *Y, const double *v, double *out) {
+  std::vector<std::vector<double>> Sv(n), Yv(n);
+  std::vector<double> rho(n);
+  for (int j = 0; j < n; ++j) {
+    Sv[j].assign(S + (size_t)j * N, S + (size_t)(j + 1) * N);
+    Yv[j].assign(Y + (size_t)j * N, Y + (size_t)(j + 1) * N);
+    double sy = 0;
+    for (int i = 0; i < N; ++i) sy += Sv[j][i] * Yv[j][i];
+    rho[j] = 1.0 / sy;
+  }
+  const std::vector<double> q = lbfgs_two_loop(N, Sv, Yv, rho, std::vector<double>(v, v + N));
+  for (int i = 0; i < N; ++i) out[i] = q[i];
   return 0;
 }
 

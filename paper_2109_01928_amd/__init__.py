@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libdebyefit.so")
 OK, EINVAL, ERANGE, EHIP, ENOMEM = 0, -1, -2, -3, -4
 ST_OK, ST_BADINPUT, ST_SINGULAR = 0, 1, 2
 FLAG_NO_SIGN_FLIP = 1
+PLAN_TARGET_GRAD = 1
 MAX_POLES = 24
 PARAM_STRIDE = 16
 DEFAULT_DAMPING = 1e-8
@@ -36,7 +37,8 @@ EXPORTED = ["debye_plan_create", "debye_plan_destroy", "debye_plan_set_freq_spli
             "debye_last_error", "debye_version", "debye_basis", "debye_fit_eval", "debye_fit_eval_grad",
             "debye_material_eval", "debye_material_vjp", "debye_pso_init", "debye_pso_step",
             "debye_pso_run", "debye_afe", "debye_fit_auto", "debye_de_init", "debye_de_trial", "debye_de_select", "debye_de_run",
-            "debye_da_init", "debye_da_visit", "debye_da_accept", "debye_da_run", "debye_lbfgs_polish"]
+            "debye_da_init", "debye_da_visit", "debye_da_accept", "debye_da_run", "debye_polish_create",
+            "debye_polish_destroy", "debye_polish_begin", "debye_polish_step", "debye_lbfgs_polish"]
 
 
 class DebyeError(RuntimeError):
@@ -126,7 +128,11 @@ def lib():
     L.debye_da_visit.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CDa, i32, _vp, _vp, _vp]
     L.debye_da_accept.argtypes = [C.POINTER(_CBatch), i64, _CDa, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, i64, _vp]
     L.debye_da_run.argtypes = [_vp, C.POINTER(_CBatch), i64, _vp, _vp, _CDa, i32, dbl, u32, C.POINTER(_CPop), i32, _vp]
-    L.debye_lbfgs_polish.argtypes = [C.POINTER(_CBatch), _vp, _vp, _vp, i64, _vp, _vp, dbl, u32, _CLbfgs, _vp, _vp]
+    L.debye_polish_create.argtypes = [C.POINTER(_CBatch), _vp, _vp, i64, _CLbfgs, C.POINTER(_vp)]
+    L.debye_polish_destroy.argtypes = [_vp]
+    L.debye_polish_begin.argtypes = [_vp, C.POINTER(_CBatch), _vp, dbl, u32, _vp]
+    L.debye_polish_step.argtypes = [_vp, C.POINTER(_CBatch), _vp, _vp, _vp, dbl, u32, i32, _vp, _vp]
+    L.debye_lbfgs_polish.argtypes = [_vp, C.POINTER(_CBatch), _vp, _vp, _vp, dbl, u32, _vp, _vp]
     _lib = L
     return L
 
@@ -204,13 +210,17 @@ def schedule_preview(f_off, cand_off, mats, n_poles, pole_split, freq_split):
 
 
 class Plan:
-    """Launch schedule for one batch shape (see debye_plan_create)."""
+    """Launch schedule for one batch shape (see debye_plan_create).  With
+    target_grads the plan also holds the adjoint records that target gradients
+    (fit_eval_grad(..., targets=True), DebyeCost with eps gradients) need."""
 
-    def __init__(self, b: Batch):
+    def __init__(self, b: Batch, target_grads=False):
         self.handle = _vp()
+        self.target_grads = bool(target_grads)
         cb = b.cstruct()
         _check(lib().debye_plan_create(C.byref(cb), b.f_off_h.ctypes.data_as(_vp), b.cand_off_h.ctypes.data_as(_vp),
-                                       b.n_poles_h.ctypes.data_as(_vp), 0, C.byref(self.handle)))
+                                       b.n_poles_h.ctypes.data_as(_vp), PLAN_TARGET_GRAD if target_grads else 0,
+                                       C.byref(self.handle)))
 
     def set_freq_split(self, split, n_poles=0):
         _check(lib().debye_plan_set_freq_split(self.handle, n_poles, split))
@@ -476,15 +486,48 @@ def da_run(plan: Plan, b: Batch, lb, ub, pop: Population, iters, qv=DA_QV, qa=DA
                               int(iters), float(damping), flags, C.byref(cp), 1 if use_graph else 0, _stream()))
 
 
+class Polish:
+    """L-BFGS polish context for one candidate per material (debye_polish_create):
+    owns the history, the trial buffers and the evaluation plans, so that
+    begin/step/run only enqueue work (no allocation, no synchronisation)."""
+
+    def __init__(self, b1: Batch, ld, steps=50, mem=10, max_trials=30, c1=1e-4):
+        self.handle = _vp()
+        self.steps = int(steps)
+        cb = b1.cstruct()
+        _check(lib().debye_polish_create(C.byref(cb), b1.f_off_h.ctypes.data_as(_vp), b1.n_poles_h.ctypes.data_as(_vp),
+                                         int(ld), _CLbfgs(steps, mem, max_trials, c1), C.byref(self.handle)))
+
+    def begin(self, b1: Batch, theta, damping=DEFAULT_DAMPING, flags=0):
+        cb = b1.cstruct()
+        _check(lib().debye_polish_begin(self.handle, C.byref(cb), _ptr(theta), float(damping), flags, _stream()))
+
+    def step(self, b1: Batch, theta, lb, ub, step, damping=DEFAULT_DAMPING, flags=0, cost_hist=None):
+        cb = b1.cstruct()
+        _check(lib().debye_polish_step(self.handle, C.byref(cb), _ptr(theta), _ptr(lb), _ptr(ub), float(damping), flags,
+                                       int(step), _ptr(cost_hist), _stream()))
+
+    def run(self, b1: Batch, theta, lb, ub, damping=DEFAULT_DAMPING, flags=0, cost_hist=None):
+        cb = b1.cstruct()
+        _check(lib().debye_lbfgs_polish(self.handle, C.byref(cb), _ptr(theta), _ptr(lb), _ptr(ub), float(damping),
+                                        flags, _ptr(cost_hist), _stream()))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.debye_polish_destroy(self.handle)
+            self.handle = None
+
+
 def lbfgs_polish(b1: Batch, theta, lb, ub, steps=50, mem=10, max_trials=30, c1=1e-4, damping=DEFAULT_DAMPING,
-                 flags=0, history=True):
+                 flags=0, history=True, polish=None):
     """L-BFGS polish of one candidate per material (theta [M][ld], in place)
-    inside the box [lb[m], ub[m]] (device tensors [M])."""
-    hist = torch.empty((b1.M, steps + 1), dtype=torch.float64, device=theta.device) if history else None
-    cb = b1.cstruct()
-    _check(lib().debye_lbfgs_polish(C.byref(cb), b1.f_off_h.ctypes.data_as(_vp), b1.n_poles_h.ctypes.data_as(_vp),
-                                    _ptr(theta), theta.shape[1], _ptr(lb), _ptr(ub), float(damping), flags,
-                                    _CLbfgs(steps, mem, max_trials, c1), _ptr(hist), _stream()))
+    inside the box [lb[m], ub[m]] (device tensors [M]).  Creates a Polish
+    context unless one (made for `steps`) is passed; returns the cost history
+    [M][steps+1] (or None)."""
+    if polish is None:
+        polish = Polish(b1, theta.shape[1], steps, mem, max_trials, c1)
+    hist = torch.empty((b1.M, polish.steps + 1), dtype=torch.float64, device=theta.device) if history else None
+    polish.run(b1, theta, lb, ub, damping, flags, hist)
     return hist
 
 
@@ -506,6 +549,8 @@ class DebyeCost(torch.autograd.Function):
         theta, eps_re, eps_im = ctx.saved_tensors
         b = ctx.batch.with_targets(eps_re.detach(), eps_im.detach())
         want_t = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        if want_t and not getattr(ctx.plan, "target_grads", False):
+            raise ValueError("gradients for eps', eps'' need a Plan(batch, target_grads=True)")
         _, g, gr, gi, _ = fit_eval_grad(ctx.plan, b, theta.detach().contiguous(), ctx.damping, ctx.flags,
                                         grad_cost=grad_cost.contiguous(), targets=want_t)
         return g, gr, gi, None, None, None, None

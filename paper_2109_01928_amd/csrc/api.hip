@@ -380,7 +380,7 @@ int debye_plan_create(const debye_batch *shape, const int64_t *f_off_host, const
   int rc = check_batch(shape);
   if (rc) return rc;
   if (!f_off_host || !cand_off_host || !n_poles_host) return fail(DEBYE_EINVAL, "host shape arrays are NULL");
-  if (flags) return fail(DEBYE_EINVAL, "plan flags must be 0");
+  if (flags & ~(uint32_t)DEBYE_PLAN_TARGET_GRAD) return fail(DEBYE_EINVAL, "unknown plan flag bits 0x%x", flags);
   const int32_t M = shape->n_mat;
   if (f_off_host[0] != 0 || cand_off_host[0] != 0) return fail(DEBYE_EINVAL, "offsets must start at 0");
   int32_t maxN = 0;
@@ -421,6 +421,16 @@ int debye_plan_create(const debye_batch *shape, const int64_t *f_off_host, const
     b.flops += (double)P * ((double)F * (b.N * b.N + 13.0 * b.N + 5.0) + b.N * b.N * (b.N / 3.0 + 2.0));
   }
   for (auto &kv : by_n) p->buckets.push_back(std::move(kv.second));
+  // per-candidate adjoint records for the target gradient (set-up, so that
+  // debye_fit_eval_grad itself never allocates)
+  if (flags & DEBYE_PLAN_TARGET_GRAD) {
+    p->rec_ld = 4 * p->max_poles + 2;   // [w | z | mu | tau | eps_inf, gc]
+    if (hipMalloc(&p->d_record, (size_t)std::max<int64_t>(p->n_cand, 1) * p->rec_ld * 8) != hipSuccess) {
+      p->d_record = nullptr;
+      debye_plan_destroy(p);
+      return fail(DEBYE_ENOMEM, "plan: adjoint record allocation failed");
+    }
+  }
   // largest work first
   std::stable_sort(p->buckets.begin(), p->buckets.end(), [](const Bucket &x, const Bucket &y) { return x.flops > y.flops; });
   for (auto &b : p->buckets) {
@@ -627,61 +637,102 @@ int debye_fit_eval(const debye_plan *p, const debye_batch *b, const double *log1
   });
 }
 
-int debye_fit_eval_grad(const debye_plan *pc, const debye_batch *b, const double *log10_tau, int64_t ld,
-                        double damping, uint32_t flags, const double *grad_cost, double *cost,
-                        double *grad_log10_tau, double *grad_eps_re, double *grad_eps_im, int8_t *status,
-                        hipStream_t stream) {
-  int rc = check_plan_batch(pc, b, ld);
-  if (rc) return rc;
-  if ((rc = check_damping(damping, flags))) return rc;
-  if (!log10_tau || !cost) return fail(DEBYE_EINVAL, "log10_tau and cost must not be NULL");
-  if ((grad_eps_re == nullptr) != (grad_eps_im == nullptr))
-    return fail(DEBYE_EINVAL, "grad_eps_re and grad_eps_im must both be set or both be NULL");
-  debye_plan *p = const_cast<debye_plan *>(pc);
+}  // extern "C"
+
+namespace {
+// cost + adjoint launches of every bucket; `record` ([n_cand][rec_ld]
+// doubles) holds the per-candidate adjoint records the target-gradient
+// kernel reads back (NULL without target gradients)
+int fit_eval_grad_launch(const debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld,
+                         double damping, uint32_t flags, const double *grad_cost, double *cost,
+                         double *grad_log10_tau, double *grad_eps_re, double *grad_eps_im, int8_t *status,
+                         double *record, int64_t rec_ld, hipStream_t stream) {
   const bool targets = grad_eps_re != nullptr;
-  if (targets && !p->d_record) {
-    p->rec_ld = 4 * p->max_poles + 2;   // [w | z | mu | tau | eps_inf, gc]
-    if (hipMalloc(&p->d_record, (size_t)std::max<int64_t>(p->n_cand, 1) * p->rec_ld * 8) != hipSuccess) {
-      p->d_record = nullptr;
-      return fail(DEBYE_ENOMEM, "adjoint workspace allocation failed");
-    }
-  }
   if (targets) {
     // materials without candidates get zero target gradients (a fill kernel,
     // not a memset, so that the call can be captured into a graph)
     CHECK_HIP(dfit::launch_fill(grad_eps_re, p->n_freq, 0.0, stream), "fill");
     CHECK_HIP(dfit::launch_fill(grad_eps_im, p->n_freq, 0.0, stream), "fill");
   }
-  rc = for_buckets(p, stream, [&](const Bucket &bk, hipStream_t s) -> int {
+  return for_buckets(p, stream, [&](const Bucket &bk, hipStream_t s) -> int {
     dfit::FitArgs a = fit_args(p, bk, b, log10_tau, ld, damping, flags);
     a.cost = cost;
     a.status = status;
     a.grad_cost = grad_cost;
     a.grad_theta = grad_log10_tau;
-    a.record = targets ? p->d_record : nullptr;
-    a.rec_ld = p->rec_ld;
+    a.record = targets ? record : nullptr;
+    a.rec_ld = rec_ld;
     CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, true, bk.uni, s), "debye_fit_eval_grad launch");
     if (!targets) return DEBYE_OK;
-    {
-      dfit::TargetGradArgs t{};
-      t.f_off = b->f_off;
-      t.cand_off = b->cand_off;
-      t.omega = b->omega;
-      t.eps_re = b->eps_re;
-      t.eps_im = b->eps_im;
-      t.theta = log10_tau;
-      t.ld = ld;
-      t.record = p->d_record;
-      t.rec_ld = p->rec_ld;
-      t.mat_list = bk.d_mats;
-      t.grad_re = grad_eps_re;
-      t.grad_im = grad_eps_im;
-      // the bucket's materials only: disjoint from the other buckets' points
-      CHECK_HIP(dfit::launch_target_grad(bk.N, t, bk.max_f, (int32_t)bk.mats.size(), s), "target gradient launch");
-    }
+    dfit::TargetGradArgs t{};
+    t.f_off = b->f_off;
+    t.cand_off = b->cand_off;
+    t.omega = b->omega;
+    t.eps_re = b->eps_re;
+    t.eps_im = b->eps_im;
+    t.theta = log10_tau;
+    t.ld = ld;
+    t.record = record;
+    t.rec_ld = rec_ld;
+    t.mat_list = bk.d_mats;
+    t.grad_re = grad_eps_re;
+    t.grad_im = grad_eps_im;
+    // the bucket's materials only: disjoint from the other buckets' points
+    CHECK_HIP(dfit::launch_target_grad(bk.N, t, bk.max_f, (int32_t)bk.mats.size(), s), "target gradient launch");
     return DEBYE_OK;
   });
-  return rc;
+}
+
+int fit_eval_grad_check(const debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld,
+                        double damping, uint32_t flags, const double *cost, const double *grad_eps_re,
+                        const double *grad_eps_im) {
+  int rc = check_plan_batch(p, b, ld);
+  if (rc) return rc;
+  if ((rc = check_damping(damping, flags))) return rc;
+  if (!log10_tau || !cost) return fail(DEBYE_EINVAL, "log10_tau and cost must not be NULL");
+  if ((grad_eps_re == nullptr) != (grad_eps_im == nullptr))
+    return fail(DEBYE_EINVAL, "grad_eps_re and grad_eps_im must both be set or both be NULL");
+  return DEBYE_OK;
+}
+
+}  // namespace
+
+namespace dfit {
+// debye_fit_eval_grad with the target-gradient records in a buffer the caller
+// provides: after the argument checks, and only when target gradients are
+// requested, `record_buffer` is asked for a device buffer of at least the
+// bytes the batch needs ([n_cand][4 max_poles + 2] doubles); it returns
+// DEBYE_OK and the address, or an error code (e.g. DEBYE_ERANGE when it is
+// too small).  Nothing is allocated here.
+int fit_eval_grad_external(const debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld,
+                           double damping, uint32_t flags, const double *grad_cost, double *cost,
+                           double *grad_log10_tau, double *grad_eps_re, double *grad_eps_im, int8_t *status,
+                           int (*record_buffer)(size_t bytes, double **out), hipStream_t stream) {
+  int rc = fit_eval_grad_check(p, b, log10_tau, ld, damping, flags, cost, grad_eps_re, grad_eps_im);
+  if (rc) return rc;
+  if (!grad_eps_re)
+    return fit_eval_grad_launch(p, b, log10_tau, ld, damping, flags, grad_cost, cost, grad_log10_tau, nullptr,
+                                nullptr, status, nullptr, 0, stream);
+  const int64_t rec_ld = 4 * (int64_t)p->max_poles + 2;
+  double *rec = nullptr;
+  if ((rc = record_buffer((size_t)std::max<int64_t>(p->n_cand, 1) * (size_t)rec_ld * 8, &rec))) return rc;
+  return fit_eval_grad_launch(p, b, log10_tau, ld, damping, flags, grad_cost, cost, grad_log10_tau, grad_eps_re,
+                              grad_eps_im, status, rec, rec_ld, stream);
+}
+}  // namespace dfit
+
+extern "C" {
+
+int debye_fit_eval_grad(const debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld,
+                        double damping, uint32_t flags, const double *grad_cost, double *cost,
+                        double *grad_log10_tau, double *grad_eps_re, double *grad_eps_im, int8_t *status,
+                        hipStream_t stream) {
+  int rc = fit_eval_grad_check(p, b, log10_tau, ld, damping, flags, cost, grad_eps_re, grad_eps_im);
+  if (rc) return rc;
+  if (grad_eps_re && !p->d_record)
+    return fail(DEBYE_EINVAL, "target gradients need a plan created with DEBYE_PLAN_TARGET_GRAD");
+  return fit_eval_grad_launch(p, b, log10_tau, ld, damping, flags, grad_cost, cost, grad_log10_tau, grad_eps_re,
+                              grad_eps_im, status, p->d_record, p->rec_ld, stream);
 }
 
 int debye_material_eval(int32_t M, const int8_t *kind, const double *params, const int64_t *f_off, int64_t n_freq,
@@ -1141,121 +1192,205 @@ int debye_da_run(const debye_plan *pc, const debye_batch *b, int64_t ld, const d
   return graph_leave(g, stream);
 }
 
-int debye_lbfgs_polish(const debye_batch *b, const int64_t *f_off_host, const int32_t *n_poles_host, double *theta,
-                       int64_t ld, const double *lb, const double *ub, double damping, uint32_t flags,
-                       debye_lbfgs_params lp, double *cost_hist, hipStream_t stream) {
+// ---- L-BFGS polish: a context that owns the workspace and the two plans
+// (one candidate per material for the gradient, max_trials per material for
+// the batched line search), so that the calls below only enqueue work
+struct debye_polish {
+  int32_t M = 0, max_poles = 0, mem = 0, max_trials = 0, steps = 0;
+  int64_t ld = 0, n_freq = 0;
+  double c1 = 0;
+  debye_plan *p1 = nullptr, *pT = nullptr;
+  void *ws = nullptr;         // one allocation for every buffer below
+  int64_t *trial_off = nullptr;
+  double *grad, *S, *Y, *rho, *dir, *gd, *trial_theta, *trial_cost, *new_theta, *new_cost, *new_grad, *cost, *acc_cost;
+  int32_t *hist_n, *hist_head, *accepted;
+  int8_t *trial_status, *new_status;
+};
+
+namespace {
+int polish_check(const debye_polish *pp, const debye_batch *b, double damping, uint32_t flags) {
+  if (!pp) return fail(DEBYE_EINVAL, "polish context is NULL");
   int rc = check_batch(b);
   if (rc) return rc;
-  if ((rc = check_damping(damping, flags))) return rc;
-  if (!theta || !f_off_host || !n_poles_host || !lb || !ub) return fail(DEBYE_EINVAL, "NULL pointer");
-  if (ld < b->max_poles) return fail(DEBYE_ERANGE, "ld < max_poles");
-  if (b->n_cand != b->n_mat) return fail(DEBYE_EINVAL, "polish needs exactly one candidate per material");
+  if (b->n_mat != pp->M || b->n_cand != pp->M || b->n_freq != pp->n_freq || b->max_poles != pp->max_poles)
+    return fail(DEBYE_EINVAL, "batch does not match the polish context (one candidate per material)");
+  return check_damping(damping, flags);
+}
+
+dfit::LbfgsArgs polish_args(const debye_polish *pp, const debye_batch *b, double *theta, const double *lb,
+                            const double *ub, double *cost_hist) {
+  dfit::LbfgsArgs la{};
+  la.M = pp->M;
+  la.n_poles = b->n_poles;
+  la.ld = pp->ld;
+  la.mem = pp->mem;
+  la.max_trials = pp->max_trials;
+  la.c1 = pp->c1;
+  la.lb = lb;
+  la.ub = ub;
+  la.theta = theta;
+  la.cost = pp->cost;
+  la.acc_cost = pp->acc_cost;
+  la.grad = pp->grad;
+  la.S = pp->S;
+  la.Y = pp->Y;
+  la.rho = pp->rho;
+  la.hist_n = pp->hist_n;
+  la.hist_head = pp->hist_head;
+  la.dir = pp->dir;
+  la.gd = pp->gd;
+  la.trial_theta = pp->trial_theta;
+  la.trial_cost = pp->trial_cost;
+  la.trial_status = pp->trial_status;
+  la.new_theta = pp->new_theta;
+  la.accepted = pp->accepted;
+  la.new_cost = pp->new_cost;
+  la.new_grad = pp->new_grad;
+  la.new_status = pp->new_status;
+  la.cost_hist = cost_hist;
+  la.steps = pp->steps;
+  return la;
+}
+}  // namespace
+
+int debye_polish_create(const debye_batch *shape, const int64_t *f_off_host, const int32_t *n_poles_host, int64_t ld,
+                        debye_lbfgs_params lp, debye_polish **out) {
+  if (!out) return fail(DEBYE_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_batch(shape);
+  if (rc) return rc;
+  if (!f_off_host || !n_poles_host) return fail(DEBYE_EINVAL, "host shape arrays are NULL");
+  if (ld < shape->max_poles) return fail(DEBYE_ERANGE, "ld < max_poles");
+  if (shape->n_cand != shape->n_mat) return fail(DEBYE_EINVAL, "polish needs exactly one candidate per material");
   if (lp.steps < 0 || lp.mem < 1 || lp.mem > DFIT_MAX_MEM || lp.max_trials < 1 || lp.max_trials > 64 ||
       !(lp.c1 > 0.0 && lp.c1 < 1.0))
     return fail(DEBYE_ERANGE, "L-BFGS parameters out of range (steps >= 0, mem 1..%d, trials 1..64, 0 < c1 < 1)",
                 DFIT_MAX_MEM);
-  if (lp.steps == 0) return DEBYE_OK;
-  const int32_t M = b->n_mat;
+  const int32_t M = shape->n_mat;
   const int T = lp.max_trials;
   std::vector<int64_t> one(M + 1), trials(M + 1);
   for (int32_t m = 0; m <= M; ++m) {
     one[m] = m;
     trials[m] = (int64_t)m * T;
   }
-  // device workspace
-  struct Buf {
-    void *p = nullptr;
-    ~Buf() {
-      if (p) (void)hipFree(p);
-    }
+  debye_polish *pp = new debye_polish();
+  pp->M = M;
+  pp->max_poles = shape->max_poles;
+  pp->mem = lp.mem;
+  pp->max_trials = T;
+  pp->steps = lp.steps;
+  pp->c1 = lp.c1;
+  pp->ld = ld;
+  pp->n_freq = shape->n_freq;
+  auto bail = [&](int r) {
+    debye_polish_destroy(pp);
+    return r;
   };
-  Buf w_trial_off, w_ws;
   const int64_t n1 = (int64_t)M * ld, nT = (int64_t)M * T;
   const size_t doubles = (size_t)(n1 /*grad*/ + 2 * (int64_t)M * lp.mem * ld /*S,Y*/ + (int64_t)M * lp.mem /*rho*/ +
                                   n1 /*dir*/ + M /*gd*/ + nT * ld /*trial theta*/ + nT /*trial cost*/ + n1 /*new theta*/ +
                                   M /*new cost*/ + n1 /*new grad*/ + M /*cost*/ + M /*accepted cost*/);
-  const size_t ints = (size_t)(3 * M);  // hist_n, hist_head, accepted
-  const size_t bytes = doubles * 8 + ints * 4 + (size_t)nT /*trial status*/ + (size_t)M /*new status*/ + 64;
-  if (hipMalloc(&w_ws.p, bytes) != hipSuccess) return fail(DEBYE_ENOMEM, "polish workspace allocation failed");
-  if (hipMalloc(&w_trial_off.p, (size_t)(M + 1) * 8) != hipSuccess) return fail(DEBYE_ENOMEM, "polish workspace allocation failed");
-  double *dp = (double *)w_ws.p;
+  const size_t bytes = (size_t)(M + 1) * 8 + doubles * 8 + (size_t)3 * M * 4 + (size_t)nT + (size_t)M + 64;
+  if (hipMalloc(&pp->ws, bytes) != hipSuccess) {
+    pp->ws = nullptr;
+    return bail(fail(DEBYE_ENOMEM, "polish workspace allocation failed"));
+  }
+  pp->trial_off = (int64_t *)pp->ws;
+  double *dp = (double *)(pp->trial_off + M + 1);
   auto take = [&](int64_t n) {
     double *r = dp;
     dp += n;
     return r;
   };
-  double *grad = take(n1), *S = take((int64_t)M * lp.mem * ld), *Y = take((int64_t)M * lp.mem * ld),
-         *rho = take((int64_t)M * lp.mem), *dir = take(n1), *gd = take(M), *trial_theta = take(nT * ld),
-         *trial_cost = take(nT), *new_theta = take(n1), *new_cost = take(M), *new_grad = take(n1), *cost = take(M),
-         *acc_cost = take(M);
+  pp->grad = take(n1);
+  pp->S = take((int64_t)M * lp.mem * ld);
+  pp->Y = take((int64_t)M * lp.mem * ld);
+  pp->rho = take((int64_t)M * lp.mem);
+  pp->dir = take(n1);
+  pp->gd = take(M);
+  pp->trial_theta = take(nT * ld);
+  pp->trial_cost = take(nT);
+  pp->new_theta = take(n1);
+  pp->new_cost = take(M);
+  pp->new_grad = take(n1);
+  pp->cost = take(M);
+  pp->acc_cost = take(M);
   int32_t *ip = (int32_t *)dp;
-  int32_t *hist_n = ip, *hist_head = ip + M, *accepted = ip + 2 * M;
-  int8_t *trial_status = (int8_t *)(ip + 3 * M);
-  int8_t *new_status = trial_status + nT;
-  CHECK_HIP(hipMemcpyAsync(w_trial_off.p, trials.data(), (M + 1) * 8, hipMemcpyHostToDevice, stream), "upload");
-  CHECK_HIP(hipMemsetAsync(hist_n, 0, (size_t)2 * M * 4, stream), "memset");
-
-  debye_batch bt = *b;
-  bt.cand_off = (const int64_t *)w_trial_off.p;
+  pp->hist_n = ip;
+  pp->hist_head = ip + M;
+  pp->accepted = ip + 2 * M;
+  pp->trial_status = (int8_t *)(ip + 3 * M);
+  pp->new_status = pp->trial_status + nT;
+  if (hipMemcpy(pp->trial_off, trials.data(), (M + 1) * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(DEBYE_EHIP, "polish: upload of the trial offsets failed"));
+  debye_batch bt = *shape;
+  bt.cand_off = pp->trial_off;
   bt.n_cand = nT;
   std::vector<int64_t> f_h(f_off_host, f_off_host + M + 1);
-  debye_plan *p1 = nullptr, *pT = nullptr;
-  if ((rc = debye_plan_create(b, f_h.data(), one.data(), n_poles_host, 0, &p1))) return rc;
-  if ((rc = debye_plan_create(&bt, f_h.data(), trials.data(), n_poles_host, 0, &pT))) {
-    debye_plan_destroy(p1);
+  if ((rc = debye_plan_create(shape, f_h.data(), one.data(), n_poles_host, 0, &pp->p1))) return bail(rc);
+  if ((rc = debye_plan_create(&bt, f_h.data(), trials.data(), n_poles_host, 0, &pp->pT))) return bail(rc);
+  *out = pp;
+  return DEBYE_OK;
+}
+
+int debye_polish_destroy(debye_polish *pp) {
+  if (!pp) return DEBYE_OK;
+  debye_plan_destroy(pp->p1);
+  debye_plan_destroy(pp->pT);
+  if (pp->ws) {
+    (void)hipDeviceSynchronize();   // no work of the context may still read the workspace
+    (void)hipFree(pp->ws);
+  }
+  delete pp;
+  return DEBYE_OK;
+}
+
+int debye_polish_begin(debye_polish *pp, const debye_batch *b, const double *theta, double damping, uint32_t flags,
+                       hipStream_t stream) {
+  int rc = polish_check(pp, b, damping, flags);
+  if (rc) return rc;
+  if (!theta) return fail(DEBYE_EINVAL, "theta is NULL");
+  // empty history (a fill kernel, not a memset, so that the call can be captured)
+  CHECK_HIP(dfit::launch_fill_i32(pp->hist_n, 2 * (int64_t)pp->M, 0, stream), "fill");
+  return debye_fit_eval_grad(pp->p1, b, theta, pp->ld, damping, flags, nullptr, pp->cost, pp->grad, nullptr, nullptr,
+                             pp->new_status, stream);
+}
+
+int debye_polish_step(debye_polish *pp, const debye_batch *b, double *theta, const double *lb, const double *ub,
+                      double damping, uint32_t flags, int32_t step, double *cost_hist, hipStream_t stream) {
+  int rc = polish_check(pp, b, damping, flags);
+  if (rc) return rc;
+  if (!theta || !lb || !ub) return fail(DEBYE_EINVAL, "NULL pointer");
+  if (step < 0 || (cost_hist && step >= pp->steps))
+    return fail(DEBYE_ERANGE, "step %d outside 0..%d", step, pp->steps - 1);
+  dfit::LbfgsArgs la = polish_args(pp, b, theta, lb, ub, cost_hist);
+  la.step = step;
+  debye_batch bt = *b;
+  bt.cand_off = pp->trial_off;
+  bt.n_cand = (int64_t)pp->M * pp->max_trials;
+  hipError_t e = dfit::launch_lbfgs_direction(la, stream);
+  if (e != hipSuccess) return hip_fail(e, "lbfgs direction");
+  if ((rc = debye_fit_eval(pp->pT, &bt, pp->trial_theta, pp->ld, damping, flags, pp->trial_cost, nullptr, nullptr,
+                           pp->trial_status, stream)))
     return rc;
-  }
-  auto done = [&](int r) {
-    (void)hipStreamSynchronize(stream);
-    debye_plan_destroy(p1);
-    debye_plan_destroy(pT);
-    return r;
-  };
-  dfit::LbfgsArgs la{};
-  la.M = M;
-  la.n_poles = b->n_poles;
-  la.ld = ld;
-  la.mem = lp.mem;
-  la.max_trials = T;
-  la.c1 = lp.c1;
-  la.lb = lb;
-  la.ub = ub;
-  la.theta = theta;
-  la.cost = cost;
-  la.acc_cost = acc_cost;
-  la.grad = grad;
-  la.S = S;
-  la.Y = Y;
-  la.rho = rho;
-  la.hist_n = hist_n;
-  la.hist_head = hist_head;
-  la.dir = dir;
-  la.gd = gd;
-  la.trial_theta = trial_theta;
-  la.trial_cost = trial_cost;
-  la.trial_status = trial_status;
-  la.new_theta = new_theta;
-  la.accepted = accepted;
-  la.new_cost = new_cost;
-  la.new_grad = new_grad;
-  la.new_status = new_status;
-  la.cost_hist = cost_hist;
-  la.steps = lp.steps;
-  if ((rc = debye_fit_eval_grad(p1, b, theta, ld, damping, flags, nullptr, cost, grad, nullptr, nullptr, new_status, stream)))
-    return done(rc);
-  for (int32_t s = 0; s < lp.steps; ++s) {
-    la.step = s;
-    hipError_t e = dfit::launch_lbfgs_direction(la, stream);
-    if (e != hipSuccess) return done(hip_fail(e, "lbfgs direction"));
-    if ((rc = debye_fit_eval(pT, &bt, trial_theta, ld, damping, flags, trial_cost, nullptr, nullptr, trial_status, stream)))
-      return done(rc);
-    if ((e = dfit::launch_lbfgs_select(la, stream)) != hipSuccess) return done(hip_fail(e, "lbfgs select"));
-    if ((rc = debye_fit_eval_grad(p1, b, new_theta, ld, damping, flags, nullptr, new_cost, new_grad, nullptr, nullptr,
-                                  new_status, stream)))
-      return done(rc);
-    if ((e = dfit::launch_lbfgs_update(la, stream)) != hipSuccess) return done(hip_fail(e, "lbfgs update"));
-  }
-  return done(DEBYE_OK);
+  if ((e = dfit::launch_lbfgs_select(la, stream)) != hipSuccess) return hip_fail(e, "lbfgs select");
+  if ((rc = debye_fit_eval_grad(pp->p1, b, pp->new_theta, pp->ld, damping, flags, nullptr, pp->new_cost, pp->new_grad,
+                                nullptr, nullptr, pp->new_status, stream)))
+    return rc;
+  if ((e = dfit::launch_lbfgs_update(la, stream)) != hipSuccess) return hip_fail(e, "lbfgs update");
+  return DEBYE_OK;
+}
+
+int debye_lbfgs_polish(debye_polish *pp, const debye_batch *b, double *theta, const double *lb, const double *ub,
+                       double damping, uint32_t flags, double *cost_hist, hipStream_t stream) {
+  int rc = polish_check(pp, b, damping, flags);
+  if (rc) return rc;
+  if (!theta || !lb || !ub) return fail(DEBYE_EINVAL, "NULL pointer");
+  if (pp->steps == 0) return DEBYE_OK;
+  if ((rc = debye_polish_begin(pp, b, theta, damping, flags, stream))) return rc;
+  for (int32_t s = 0; s < pp->steps; ++s)
+    if ((rc = debye_polish_step(pp, b, theta, lb, ub, damping, flags, s, cost_hist, stream))) return rc;
+  return DEBYE_OK;
 }
 
 }  // extern "C"

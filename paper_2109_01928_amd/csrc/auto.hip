@@ -169,9 +169,12 @@ extern "C" int debye_fit_auto(const debye_batch *mats, const int64_t *f_off_host
     // polish each best, then its weights and error
     if (p.polish_steps > 0) {
       debye_lbfgs_params lp{p.polish_steps, 10, 30, 1e-4};
-      if ((rc = debye_lbfgs_polish(&b1, f_e.data(), n_e.data(), gbx.as<double>(), ld, d_lb.as<double>(),
-                                   d_ub.as<double>(), damping, flags, lp, nullptr, stream)))
-        return rc;
+      debye_polish *pol = nullptr;
+      if ((rc = debye_polish_create(&b1, f_e.data(), n_e.data(), ld, lp, &pol))) return rc;
+      rc = debye_lbfgs_polish(pol, &b1, gbx.as<double>(), d_lb.as<double>(), d_ub.as<double>(), damping, flags,
+                              nullptr, stream);
+      debye_polish_destroy(pol);
+      if (rc) return rc;
     }
     DevBuf w1, e1, c1, afe;
     if ((rc = alloc_doubles(w1, E * ld)) || (rc = alloc_doubles(e1, E)) || (rc = alloc_doubles(c1, E)) ||

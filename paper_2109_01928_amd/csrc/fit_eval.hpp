@@ -2,7 +2,11 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+struct debye_plan;
+struct debye_batch;
 
 namespace dfit {
 
@@ -87,10 +91,18 @@ hipError_t launch_pso_step(const PsoArgs &a, hipStream_t s);
 hipError_t launch_set_counter(int32_t *c, int32_t value, hipStream_t s);
 // p[0..n) = v (a kernel, so that it can sit in a captured graph)
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_tick(int32_t *c, hipStream_t s);
 
 // error text for debye_last_error() (api.hip); returns code
 int set_error(int code, const char *msg);
+
+// debye_fit_eval_grad with the target-gradient records in a buffer that the
+// caller provides through record_buffer (api.hip; see there)
+int fit_eval_grad_external(const debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld,
+                           double damping, uint32_t flags, const double *grad_cost, double *cost,
+                           double *grad_log10_tau, double *grad_eps_re, double *grad_eps_im, int8_t *status,
+                           int (*record_buffer)(size_t bytes, double **out), hipStream_t stream);
 
 // average fractional error of fitted expansions (material.hip)
 struct AfeArgs {

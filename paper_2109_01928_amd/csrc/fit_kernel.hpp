@@ -1050,6 +1050,9 @@ void fit_kernel(const FitArgs a) {
       T4[cI] = LN10 * freq_sum(T4[cI], SP, SL);
     }
     if (writer) {
+      // padding entries of the row (poles beyond this material's count) are 0
+      if (q == 0 && a.grad_theta)
+        for (int64_t p = N; p < a.ld; ++p) a.grad_theta[c * a.ld + p] = 0.0;
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
         const int p = q * NB + cI;

@@ -2,7 +2,8 @@
 // 1989) with the two-loop recursion (Nocedal & Wright, Algorithm 7.4) and
 // Armijo backtracking alpha = 1, 1/2, 1/4, ... inside the search box: each
 // trial point is projected onto [lb, ub] and the sufficient-decrease test uses
-// the projected displacement p, C(trial) <= C + c1 g.p.  The trial points of
+// the projected displacement p, C(trial) <= C + c1 min(g.p, 0) (clamping can
+// make g.p positive; the cost is then not allowed to rise).  The trial points of
 // one step are all evaluated in one batched cost launch, and the accepted step
 // is the first trial (largest alpha) that passes, which is what a sequential
 // halving search returns.  One thread per material.
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(256) void lbfgs_select_kernel(const LbfgsArgs a) {
       const double *tt = a.trial_theta + r * a.ld;
       double gp = 0.0;
       for (int i = 0; i < N; ++i) gp += g[i] * (tt[i] - th[i]);
-      if (a.trial_status[r] == ST_OK && a.trial_cost[r] <= C + a.c1 * gp) {
+      if (a.trial_status[r] == ST_OK && a.trial_cost[r] <= C + a.c1 * fmin(gp, 0.0)) {
         pick = t;
         break;
       }
@@ -132,8 +133,10 @@ __global__ __launch_bounds__(256) void lbfgs_update_kernel(const LbfgsArgs a) {
   if (a.accepted[m]) {
     const int mem = a.mem;
     const int head = a.hist_head[m];
-    double *s = a.S + ((int64_t)m * mem + head) * ld;
-    double *y = a.Y + ((int64_t)m * mem + head) * ld;
+    // the pair is formed in registers and stored only if it is kept: with a
+    // full history, slot `head` still holds the oldest live pair, which a
+    // rejected pair (s.y <= 1e-300) must not overwrite
+    double s[DFIT_MAX_POLES], y[DFIT_MAX_POLES];
     double sy = 0.0;
     for (int i = 0; i < N; ++i) {
       s[i] = a.new_theta[m * ld + i] - a.theta[m * ld + i];
@@ -141,6 +144,12 @@ __global__ __launch_bounds__(256) void lbfgs_update_kernel(const LbfgsArgs a) {
       sy += s[i] * y[i];
     }
     if (sy > 1e-300) {
+      double *ss = a.S + ((int64_t)m * mem + head) * ld;
+      double *yy = a.Y + ((int64_t)m * mem + head) * ld;
+      for (int i = 0; i < N; ++i) {
+        ss[i] = s[i];
+        yy[i] = y[i];
+      }
       a.rho[(int64_t)m * mem + head] = 1.0 / sy;
       a.hist_head[m] = (head + 1) % mem;
       a.hist_n[m] = a.hist_n[m] < mem ? a.hist_n[m] + 1 : mem;

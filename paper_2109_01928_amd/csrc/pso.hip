@@ -176,6 +176,17 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_tick(int32_t *c, hipStream_t s) {
   hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, s, c);
   return hipGetLastError();

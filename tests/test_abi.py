@@ -63,10 +63,25 @@ def test_host_side_validation():
     b.max_poles = 4
     assert L.debye_plan_create(C.byref(b), f2.ctypes.data_as(C.c_void_p), c.ctypes.data_as(C.c_void_p),
                                n.ctypes.data_as(C.c_void_p), 0, C.byref(out)) == D.ERANGE
-    # L-BFGS parameter ranges
-    lp = D._CLbfgs(5, 0, 30, 1e-4)
+    # plan flags: only DEBYE_PLAN_TARGET_GRAD is defined
+    b = D._CBatch(2, 4, 10, 4, 8, 8, 8, 8, 8, 8)
+    f = np.array([0, 5, 10], np.int64)
+    assert L.debye_plan_create(C.byref(b), f.ctypes.data_as(C.c_void_p), c.ctypes.data_as(C.c_void_p),
+                               n.ctypes.data_as(C.c_void_p), 2, C.byref(out)) == D.EINVAL
+    assert b"flag" in L.debye_last_error()
+    # L-BFGS polish context: parameter ranges and shape, checked before any allocation
     b1 = D._CBatch(2, 4, 10, 2, 8, 8, 8, 8, 8, 8)
-    assert L.debye_lbfgs_polish(C.byref(b1), one, one, one, 4, one, one, 1e-8, 0, lp, None, z) == D.ERANGE
-    # negative damping, unknown flags
-    assert L.debye_lbfgs_polish(C.byref(b1), one, one, one, 4, one, one, -1.0, 0, D._CLbfgs(5, 5, 5, 1e-4), None, z) == D.ERANGE
-    assert L.debye_lbfgs_polish(C.byref(b1), one, one, one, 4, one, one, 1e-8, 8, D._CLbfgs(5, 5, 5, 1e-4), None, z) == D.EINVAL
+    n4 = np.array([4, 4], np.int32)
+    pp = C.c_void_p()
+    fp, np4 = f.ctypes.data_as(C.c_void_p), n4.ctypes.data_as(C.c_void_p)
+    assert L.debye_polish_create(C.byref(b1), fp, np4, 4, D._CLbfgs(5, 0, 30, 1e-4), C.byref(pp)) == D.ERANGE
+    assert L.debye_polish_create(C.byref(b1), fp, np4, 4, D._CLbfgs(5, 5, 65, 1e-4), C.byref(pp)) == D.ERANGE
+    assert L.debye_polish_create(C.byref(b1), fp, np4, 4, D._CLbfgs(5, 5, 5, 1.5), C.byref(pp)) == D.ERANGE
+    assert L.debye_polish_create(C.byref(b1), fp, np4, 3, D._CLbfgs(5, 5, 5, 1e-4), C.byref(pp)) == D.ERANGE
+    b2 = D._CBatch(2, 4, 10, 4, 8, 8, 8, 8, 8, 8)
+    assert L.debye_polish_create(C.byref(b2), fp, np4, 4, D._CLbfgs(5, 5, 5, 1e-4), C.byref(pp)) == D.EINVAL
+    assert b"one candidate per material" in L.debye_last_error()
+    # the enqueueing calls need a context
+    assert L.debye_lbfgs_polish(None, C.byref(b1), one, one, one, 1e-8, 0, None, z) == D.EINVAL
+    assert L.debye_polish_begin(None, C.byref(b1), one, 1e-8, 0, z) == D.EINVAL
+    assert L.debye_polish_step(None, C.byref(b1), one, one, one, 1e-8, 0, 0, None, z) == D.EINVAL

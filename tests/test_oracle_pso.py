@@ -149,3 +149,68 @@ def test_lbfgs_stays_in_box_from_a_corner(orc):
     th, hist = orc.lbfgs(b, th0, -12.0, -7.0, steps=40)
     assert np.all(th >= -12.0) and np.all(th <= -7.0)
     assert np.all(np.diff(hist[0]) <= 0) and hist[0, -1] < hist[0, 0]
+
+
+def _dense_bfgs_inverse(S, Y):
+    """Inverse-Hessian approximation by explicit BFGS updates from gamma I
+    (gamma = s.y / y.y of the newest pair), pairs applied oldest first:
+    H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T (Nocedal & Wright,
+    eq. 6.17 / 7.19, with the initial scaling of eq. 7.20)."""
+    n, N = S.shape
+    gamma = S[-1] @ Y[-1] / (Y[-1] @ Y[-1]) if n else 1.0
+    H = gamma * np.eye(N)
+    for s, y in zip(S, Y):
+        rho = 1.0 / (s @ y)
+        V = np.eye(N) - rho * np.outer(y, s)
+        H = V.T @ H @ V + rho * np.outer(s, s)
+    return H
+
+
+@pytest.mark.parametrize("N,n", [(1, 1), (4, 2), (6, 5), (12, 10), (20, 3)])
+def test_lbfgs_two_loop_equals_dense_bfgs(orc, N, n):
+    """The polish's search direction: the two-loop product H v equals the
+    dense BFGS inverse built from the same pairs, H is symmetric positive
+    definite, and it satisfies the newest secant condition H y = s."""
+    g = np.random.default_rng(N * 31 + n)
+    A = g.standard_normal((N, N))
+    A = A @ A.T + N * np.eye(N)                 # SPD curvature: s.y > 0
+    S = g.standard_normal((n, N))
+    Y = S @ A.T + 0.1 * g.standard_normal((n, N))
+    assert np.all(np.einsum("ij,ij->i", S, Y) > 0)
+    H = _dense_bfgs_inverse(S, Y)
+    v = g.standard_normal(N)
+    hv = orc.lbfgs_two_loop(S, Y, v)
+    np.testing.assert_allclose(hv, H @ v, rtol=1e-11, atol=1e-12 * np.abs(H @ v).max())
+    # the two-loop operator itself, column by column
+    Hop = np.stack([orc.lbfgs_two_loop(S, Y, e) for e in np.eye(N)], axis=1)
+    np.testing.assert_allclose(Hop, Hop.T, rtol=0, atol=1e-11 * np.abs(Hop).max())
+    assert np.linalg.eigvalsh(0.5 * (Hop + Hop.T)).min() > 0
+    np.testing.assert_allclose(orc.lbfgs_two_loop(S, Y, Y[-1]), S[-1], rtol=1e-11, atol=1e-12 * np.abs(S[-1]).max())
+
+
+def test_lbfgs_two_loop_without_pairs_is_identity(orc):
+    v = np.array([0.3, -2.0, 5.5])
+    np.testing.assert_array_equal(orc.lbfgs_two_loop(np.zeros((0, 3)), np.zeros((0, 3)), v), v)
+
+
+def test_lbfgs_two_loop_pins_order_and_scaling(orc):
+    """Plausible slips in the recursion (pairs taken newest-first in the dense
+    update, the scaling from the oldest pair, no scaling) give a different
+    product, so the comparison above would catch them."""
+    g = np.random.default_rng(7)
+    N, n = 5, 4
+    A = g.standard_normal((N, N))
+    A = A @ A.T + N * np.eye(N)
+    S = g.standard_normal((n, N))
+    Y = S @ A.T + 0.3 * g.standard_normal((n, N))
+    v = g.standard_normal(N)
+    hv = orc.lbfgs_two_loop(S, Y, v)
+    wrong_order = _dense_bfgs_inverse(S[::-1], Y[::-1]) @ v
+    gamma_old = (S[0] @ Y[0]) / (Y[0] @ Y[0])
+    H = gamma_old * np.eye(N)
+    for s, y in zip(S, Y):
+        rho = 1.0 / (s @ y)
+        V = np.eye(N) - rho * np.outer(y, s)
+        H = V.T @ H @ V + rho * np.outer(s, s)
+    for other in (wrong_order, H @ v):
+        assert np.max(np.abs(hv - other)) > 1e-6 * np.max(np.abs(hv))
