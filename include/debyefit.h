@@ -221,6 +221,23 @@ int debye_fit_eval_grad(const debye_plan *plan, const debye_batch *b, const doub
                         hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * debye_fit_eval_grad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, but the target
+ * gradients need no DEBYE_PLAN_TARGET_GRAD plan.  Their per-candidate records
+ * live in a static 64 MiB device array of the library (one per GPU, held
+ * until the process ends), so n_cand x (4 max_poles + 2) x 8 bytes must not
+ * exceed 64 MiB (DEBYE_ERANGE otherwise, checked on the host before any
+ * work is enqueued).  Every call on a GPU shares that array: calls that
+ * overlap on one GPU (other streams or threads) race.  The call itself
+ * allocates nothing; the plan is made beforehand.
+ * ------------------------------------------------------------------------ */
+int debye_fit_eval_grad_noalloc(const debye_plan *plan, const debye_batch *b, const double *log10_tau, int64_t ld,
+                                double damping, uint32_t flags, const double *grad_cost, double *cost,
+                                double *grad_log10_tau, double *grad_eps_re, double *grad_eps_im, int8_t *status,
+                                hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Target synthesis (Eqs. 3-6): eps_re/eps_im [n_freq] for every material
  * (kind [M] int8, params [M][DEBYE_PARAM_STRIDE]); jac (NULL or [n_freq][5][2])
  * receives d(eps', eps'')/d(eps_inf, d_eps, tau0, alpha, beta) for the

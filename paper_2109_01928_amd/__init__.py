@@ -35,6 +35,7 @@ EXPORTED = ["debye_plan_create", "debye_plan_destroy", "debye_plan_set_freq_spli
             "debye_schedule_preview",
             "debye_plan_info",
             "debye_last_error", "debye_version", "debye_basis", "debye_fit_eval", "debye_fit_eval_grad",
+            "debye_fit_eval_grad_noalloc",
             "debye_material_eval", "debye_material_vjp", "debye_pso_init", "debye_pso_step",
             "debye_pso_run", "debye_afe", "debye_fit_auto", "debye_de_init", "debye_de_trial", "debye_de_select", "debye_de_run",
             "debye_da_init", "debye_da_visit", "debye_da_accept", "debye_da_run", "debye_polish_create",
@@ -110,6 +111,7 @@ def lib():
     L.debye_basis.argtypes = [_vp, i64, _vp, i64, i64, i32, _vp, _vp, _vp]
     L.debye_fit_eval.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, _vp, _vp, _vp, _vp, _vp]
     L.debye_fit_eval_grad.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.debye_fit_eval_grad_noalloc.argtypes = L.debye_fit_eval_grad.argtypes
     L.debye_material_eval.argtypes = [i32, _vp, _vp, _vp, i64, _vp, C.c_uint64, _vp, _vp, _vp, _vp]
     L.debye_material_vjp.argtypes = [i32, _vp, i64, _vp, _vp, _vp, _vp, _vp]
     L.debye_pso_init.argtypes = [C.POINTER(_CBatch), i64, _vp, _vp, _CPso, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -270,19 +272,27 @@ def fit_eval(plan: Plan, b: Batch, theta, damping=DEFAULT_DAMPING, flags=0, want
     return cost, w, einf, st
 
 
-def fit_eval_grad(plan: Plan, b: Batch, theta, damping=DEFAULT_DAMPING, flags=0, grad_cost=None, targets=False):
-    """Cost and the variable-projection adjoint (debye_fit_eval_grad)."""
+def fit_eval_grad(plan: Plan, b: Batch, theta, damping=DEFAULT_DAMPING, flags=0, grad_cost=None, targets=False,
+                  noalloc=False, out=None):
+    """Cost and the variable-projection adjoint (debye_fit_eval_grad; with
+    noalloc, debye_fit_eval_grad_noalloc: target-gradient records in the
+    library's static workspace, no DEBYE_PLAN_TARGET_GRAD plan needed).
+    `out` (cost, grad_theta, grad_re, grad_im, status) reuses tensors."""
     ld = theta.shape[1]
     dev = theta.device
-    cost = torch.empty(b.P, dtype=torch.float64, device=dev)
-    g = torch.empty((b.P, ld), dtype=torch.float64, device=dev)
-    st = torch.empty(b.P, dtype=torch.int8, device=dev)
-    gr = torch.empty(b.F, dtype=torch.float64, device=dev) if targets else None
-    gi = torch.empty(b.F, dtype=torch.float64, device=dev) if targets else None
+    if out is None:
+        cost = torch.empty(b.P, dtype=torch.float64, device=dev)
+        g = torch.empty((b.P, ld), dtype=torch.float64, device=dev)
+        st = torch.empty(b.P, dtype=torch.int8, device=dev)
+        gr = torch.empty(b.F, dtype=torch.float64, device=dev) if targets else None
+        gi = torch.empty(b.F, dtype=torch.float64, device=dev) if targets else None
+    else:
+        cost, g, gr, gi, st = out
     gc = None if grad_cost is None else grad_cost.to(torch.float64).contiguous()
     cb = b.cstruct()
-    _check(lib().debye_fit_eval_grad(plan.handle, C.byref(cb), _ptr(theta), ld, float(damping), flags, _ptr(gc),
-                                     _ptr(cost), _ptr(g), _ptr(gr), _ptr(gi), _ptr(st), _stream()))
+    fn = lib().debye_fit_eval_grad_noalloc if noalloc else lib().debye_fit_eval_grad
+    _check(fn(plan.handle, C.byref(cb), _ptr(theta), ld, float(damping), flags, _ptr(gc), _ptr(cost), _ptr(g),
+              _ptr(gr), _ptr(gi), _ptr(st), _stream()))
     return cost, g, gr, gi, st
 
 
