@@ -110,6 +110,8 @@ def main():
                     help="materials of the batched whole fit that the per-material loop is compared with")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (no adjoint rate, polish leg or per-material comparison)")
+    ap.add_argument("--launch", default="auto", choices=["auto", "buckets", "persistent"],
+                    help="several pole counts: per-bucket launches, one persistent launch, or the autotuner's choice")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default frequency splits")
     ap.add_argument("--autotune-reps", type=int, default=1)
     ap.add_argument("--freq-split", type=int, default=0,
@@ -163,6 +165,8 @@ def main():
     ub = torch.tensor(wl.ub, device=dev)
     plan = D.Plan(b)
     theta0 = torch.tensor(W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=77), device=dev)
+    if args.launch != "auto":
+        plan.set_launch(D.LAUNCH_BUCKETS if args.launch == "buckets" else D.LAUNCH_PERSISTENT)
     if args.freq_split:
         plan.set_freq_split(args.freq_split)
     elif not args.no_autotune:
@@ -269,6 +273,8 @@ def main():
                    "materials": M, "freq_points": F if uniform else "ragged", "poles": N if uniform else "ragged",
                    "particles": P_per if uniform else "ragged", "evals_per_step": P},
         "schedule": {f"N{i['n_poles']}": f"{i['pole_split']}x{i['freq_split']} lanes" for i in sched},
+        "launch": "one launch" if len(sched) == 1 else
+                  ("persistent" if plan.launch() == D.LAUNCH_PERSISTENT else "per-bucket launches"),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
                      "traffic": measured_traffic(wl, kernel, sched), "kernel": kernel, "avg_launch_s": avg,

@@ -132,6 +132,24 @@ int debye_plan_destroy(debye_plan *plan);
  * re-capture its graph.  Not while work of the plan is in flight. */
 int debye_plan_set_freq_split(debye_plan *plan, int32_t n_poles, int32_t split);
 
+/* How an evaluation of a plan with several pole counts is launched:
+ *   DEBYE_LAUNCH_BUCKETS:    one launch per pole-count bucket, forked onto the
+ *                            plan's streams and joined (the default);
+ *   DEBYE_LAUNCH_PERSISTENT: one persistent launch over every bucket: a fixed
+ *                            grid of one-wave blocks, eight per CU, each taking
+ *                            work items (a bucket's tile) from its XCD's list,
+ *                            longest estimated duration first, through a
+ *                            counter in device memory, until the list is empty;
+ *   DEBYE_LAUNCH_AUTO:       back to the default, and let debye_plan_autotune
+ *                            time both and keep the faster.
+ * Plans with one pole count always launch it directly.  The forward
+ * evaluation (debye_fit_eval and the optimisers' runs) uses the mode; the
+ * adjoint keeps the per-bucket launches.  Not while work of the plan is in
+ * flight.  debye_plan_get_launch returns the mode in use (>= 0) or an error. */
+enum { DEBYE_LAUNCH_AUTO = 0, DEBYE_LAUNCH_BUCKETS = 1, DEBYE_LAUNCH_PERSISTENT = 2 };
+int debye_plan_set_launch(debye_plan *plan, int32_t mode);
+int debye_plan_get_launch(const debye_plan *plan);
+
 /* Autotune the schedule on real data: for every pole-count bucket without an
  * override, time `reps` launches (1..100) of the cost kernel at each frequency
  * split (1, 2, 4, ... up to 64 / pole split, while spectra keep at least 8
@@ -143,7 +161,10 @@ int debye_plan_set_freq_split(debye_plan *plan, int32_t n_poles, int32_t split);
  * candidates, e.g. the initial swarm).  Synchronises `stream`; allocates and
  * frees a temporary cost buffer, so it is a set-up call, not for capture.
  * The choice stays in the plan (debye_plan_info reports it); an override set
- * by debye_plan_set_freq_split takes precedence. */
+ * by debye_plan_set_freq_split takes precedence.  With several pole counts
+ * (and no mode fixed by debye_plan_set_launch) it then times whole
+ * evaluations with both launch modes, three rounds of `reps`, and keeps the
+ * persistent launch if it is at least 3 % faster. */
 int debye_plan_autotune(debye_plan *plan, const debye_batch *b, const double *log10_tau, int64_t ld,
                         double damping, uint32_t flags, int32_t reps, hipStream_t stream);
 

@@ -27,11 +27,13 @@ OK, EINVAL, ERANGE, EHIP, ENOMEM = 0, -1, -2, -3, -4
 ST_OK, ST_BADINPUT, ST_SINGULAR = 0, 1, 2
 FLAG_NO_SIGN_FLIP = 1
 PLAN_TARGET_GRAD = 1
+LAUNCH_AUTO, LAUNCH_BUCKETS, LAUNCH_PERSISTENT = 0, 1, 2
 MAX_POLES = 24
 PARAM_STRIDE = 16
 DEFAULT_DAMPING = 1e-8
 
 EXPORTED = ["debye_plan_create", "debye_plan_destroy", "debye_plan_set_freq_split", "debye_plan_autotune",
+            "debye_plan_set_launch", "debye_plan_get_launch",
             "debye_schedule_preview",
             "debye_plan_info",
             "debye_last_error", "debye_version", "debye_basis", "debye_fit_eval", "debye_fit_eval_grad",
@@ -105,6 +107,8 @@ def lib():
     L.debye_plan_create.argtypes = [C.POINTER(_CBatch), _vp, _vp, _vp, u32, C.POINTER(_vp)]
     L.debye_plan_destroy.argtypes = [_vp]
     L.debye_plan_set_freq_split.argtypes = [_vp, i32, i32]
+    L.debye_plan_set_launch.argtypes = [_vp, i32]
+    L.debye_plan_get_launch.argtypes = [_vp]
     L.debye_plan_info.argtypes = [_vp, i32, _vp, _vp, _vp, _vp, _vp]
     L.debye_plan_autotune.argtypes = [_vp, C.POINTER(_CBatch), _vp, i64, dbl, u32, i32, _vp]
     L.debye_schedule_preview.argtypes = [_vp, _vp, _vp, i32, i32, i32, i32, _vp, _vp, i64, _vp, _vp]
@@ -226,6 +230,17 @@ class Plan:
 
     def set_freq_split(self, split, n_poles=0):
         _check(lib().debye_plan_set_freq_split(self.handle, n_poles, split))
+
+    def set_launch(self, mode):
+        """LAUNCH_BUCKETS (per-bucket launches), LAUNCH_PERSISTENT (one
+        persistent launch over every bucket) or LAUNCH_AUTO (debye_plan_set_launch)."""
+        _check(lib().debye_plan_set_launch(self.handle, int(mode)))
+
+    def launch(self):
+        rc = lib().debye_plan_get_launch(self.handle)
+        if rc < 0:
+            _check(rc)
+        return rc
 
     def autotune(self, b: "Batch", theta, damping=1e-8, flags=0, reps=3):
         """Time each bucket's frequency splits on (b, theta) and keep the fastest

@@ -63,6 +63,7 @@ struct Bucket {
   bool uni = false;          // split 1 and every tile holds one material: wave-uniform spectra loads
   double flops = 0;          // algorithmic FP64 work of one evaluation of the bucket
   std::vector<int32_t> mats;
+  std::vector<float> tile_est;  // estimated duration of each tile (for the persistent launch's order)
   int32_t *d_lane_cand = nullptr, *d_lane_mat = nullptr, *d_mats = nullptr;
 };
 
@@ -93,6 +94,15 @@ struct debye_plan {
   std::vector<hipEvent_t> ev_join;
   hipEvent_t ev_fork = nullptr;
   std::vector<int> stream_of;
+  // several buckets: how an evaluation is launched (DEBYE_LAUNCH_*), whether
+  // the caller fixed it, and the persistent launch's tables
+  int32_t launch = DEBYE_LAUNCH_BUCKETS;
+  bool launch_fixed = false;
+  dfit::RaggedBucket *d_rbuckets = nullptr;
+  int64_t *d_items = nullptr;
+  int32_t *d_counters = nullptr;
+  int64_t item_off[9] = {};
+  size_t ragged_lds = 0;
 };
 
 namespace {
@@ -208,6 +218,22 @@ int build_tiles(debye_plan &p, Bucket &b) {
   const std::vector<int32_t> &lc = sc.lane_cand, &lm = sc.lane_mat;
   b.n_tiles = (int64_t)lc.size() / b.cpw;
   if (b.n_tiles == 0) return DEBYE_OK;
+  // estimated tile duration: the longest spectrum of its candidates, per
+  // frequency lane, times a per-point cost that follows the kernel's
+  // executed instructions (Gram accumulators, basis values, ring moves,
+  // the other passes), plus the dense solve
+  {
+    const int SP = b.SP, NB = (b.N + SP - 1) / SP, D = SP == 1 ? 0 : NB * SP / 2;
+    const int NG = SP == 1 ? b.N * (b.N + 1) / 2 : NB * (D + 1);
+    const double per_point = NG + 12.0 * NB + 60.0 + (SP > 1 ? 2.0 * D + 24.0 : 0.0);
+    b.tile_est.assign(b.n_tiles, 0.0f);
+    for (int64_t t = 0; t < b.n_tiles; ++t) {
+      int64_t fmax = 0;
+      for (int64_t l = t * b.cpw; l < (t + 1) * b.cpw; ++l)
+        if (lc[l] >= 0) fmax = std::max(fmax, p.f_off[lm[l] + 1] - p.f_off[lm[l]]);
+      b.tile_est[t] = (float)((double)((fmax + b.SF - 1) / b.SF) * per_point + 0.5 * (double)b.N * b.N * b.N);
+    }
+  }
   if (hipMalloc(&b.d_lane_cand, lc.size() * 4) != hipSuccess || hipMalloc(&b.d_lane_mat, lm.size() * 4) != hipSuccess ||
       hipMalloc(&b.d_mats, b.mats.size() * 4) != hipSuccess)
     return fail(DEBYE_ENOMEM, "plan: device allocation failed");
@@ -216,6 +242,54 @@ int build_tiles(debye_plan &p, Bucket &b) {
   CHECK_HIP(hipMemcpy(b.d_mats, b.mats.data(), b.mats.size() * 4, hipMemcpyHostToDevice), "plan upload");
   return DEBYE_OK;
 }
+
+// Tables of the persistent launch (plans with several pole-count buckets):
+// one descriptor per bucket, and per XCD the union of the buckets' tiles of
+// that XCD (each bucket's lists are already balanced over the XCDs by work),
+// longest estimated duration first.  Rebuilt after every re-tiling.
+int build_ragged(debye_plan &p) {
+  if (p.d_rbuckets) (void)hipFree(p.d_rbuckets);
+  if (p.d_items) (void)hipFree(p.d_items);
+  p.d_rbuckets = nullptr;
+  p.d_items = nullptr;
+  for (int x = 0; x < 9; ++x) p.item_off[x] = 0;
+  p.ragged_lds = 0;
+  if (p.buckets.size() < 2) return DEBYE_OK;
+  ++p.sched_gen;   // captured graphs hold the old tables
+  std::vector<dfit::RaggedBucket> rb(p.buckets.size());
+  std::vector<std::vector<std::pair<float, int64_t>>> per_xcd(8);
+  for (size_t i = 0; i < p.buckets.size(); ++i) {
+    const Bucket &bk = p.buckets[i];
+    rb[i] = dfit::RaggedBucket{bk.N, bk.SF, bk.cpw, bk.uni ? 1 : 0, bk.d_lane_cand, bk.d_lane_mat};
+    p.ragged_lds = std::max(p.ragged_lds, (size_t)dfit::lds_bytes_per_candidate(bk.N) * bk.cpw);
+    for (int x = 0; x < 8; ++x)
+      for (int64_t t = bk.xcd_off[x]; t < bk.xcd_off[x + 1]; ++t)
+        per_xcd[x].push_back({bk.tile_est[t], ((int64_t)i << 40) | t});
+  }
+  std::vector<int64_t> items;
+  for (int x = 0; x < 8; ++x) {
+    std::stable_sort(per_xcd[x].begin(), per_xcd[x].end(),
+                     [](const std::pair<float, int64_t> &u, const std::pair<float, int64_t> &v) { return u.first > v.first; });
+    for (const auto &it : per_xcd[x]) items.push_back(it.second);
+    p.item_off[x + 1] = (int64_t)items.size();
+  }
+  if (!p.d_counters && hipMalloc(&p.d_counters, 8 * sizeof(int32_t)) != hipSuccess) {
+    p.d_counters = nullptr;
+    return fail(DEBYE_ENOMEM, "plan: persistent-launch counters allocation failed");
+  }
+  if (hipMalloc(&p.d_rbuckets, rb.size() * sizeof(dfit::RaggedBucket)) != hipSuccess ||
+      hipMalloc(&p.d_items, std::max<size_t>(items.size(), 1) * 8) != hipSuccess)
+    return fail(DEBYE_ENOMEM, "plan: persistent-launch tables allocation failed");
+  CHECK_HIP(hipMemcpy(p.d_rbuckets, rb.data(), rb.size() * sizeof(dfit::RaggedBucket), hipMemcpyHostToDevice),
+            "plan upload");
+  if (!items.empty())
+    CHECK_HIP(hipMemcpy(p.d_items, items.data(), items.size() * 8, hipMemcpyHostToDevice), "plan upload");
+  return DEBYE_OK;
+}
+
+// blocks of the persistent launch: eight one-wave blocks per CU (two waves
+// per SIMD), each looping over its XCD's items
+constexpr int32_t RAGGED_BLOCKS = 256 * 8;
 
 int check_batch(const debye_batch *b) {
   if (!b) return fail(DEBYE_EINVAL, "batch is NULL");
@@ -440,6 +514,10 @@ int debye_plan_create(const debye_batch *shape, const int64_t *f_off_host, const
       return rc;
     }
   }
+  if ((rc = build_ragged(*p))) {
+    debye_plan_destroy(p);
+    return rc;
+  }
   // several pole counts: the buckets run concurrently on side streams, each
   // bucket (largest first) on the stream with the least work so far
   const int n_side = std::min<int>(MAX_SIDE_STREAMS, (int)p->buckets.size());
@@ -474,6 +552,9 @@ int debye_plan_destroy(debye_plan *p) {
     if (st) (void)hipStreamSynchronize(st);
   for (auto &b : p->buckets) free_bucket(b);
   if (p->d_record) (void)hipFree(p->d_record);
+  if (p->d_rbuckets) (void)hipFree(p->d_rbuckets);
+  if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_counters) (void)hipFree(p->d_counters);
   for (hipStream_t st : p->side)
     if (st) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : p->ev_join)
@@ -492,7 +573,23 @@ int debye_plan_set_freq_split(debye_plan *p, int32_t n_poles, int32_t split) {
     int rc = build_tiles(*p, b);
     if (rc) return rc;
   }
+  return build_ragged(*p);
+}
+
+int debye_plan_set_launch(debye_plan *p, int32_t mode) {
+  if (!p) return fail(DEBYE_EINVAL, "plan is NULL");
+  if (mode != DEBYE_LAUNCH_AUTO && mode != DEBYE_LAUNCH_BUCKETS && mode != DEBYE_LAUNCH_PERSISTENT)
+    return fail(DEBYE_EINVAL, "unknown launch mode %d", mode);
+  p->launch_fixed = mode != DEBYE_LAUNCH_AUTO;
+  const int32_t m = mode == DEBYE_LAUNCH_AUTO ? DEBYE_LAUNCH_BUCKETS : mode;
+  if (m != p->launch) ++p->sched_gen;
+  p->launch = m;
   return DEBYE_OK;
+}
+
+int debye_plan_get_launch(const debye_plan *p) {
+  if (!p) return fail(DEBYE_EINVAL, "plan is NULL");
+  return p->buckets.size() > 1 ? p->launch : DEBYE_LAUNCH_BUCKETS;
 }
 
 int debye_plan_autotune(debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld, double damping,
@@ -557,6 +654,35 @@ int debye_plan_autotune(debye_plan *p, const debye_batch *b, const double *log10
       if (best[i] < 0.97f * best[pick]) pick = i;
     p->sf_tuned[bk.N] = splits[pick];
     if ((rc = build_tiles(*p, bk))) return cleanup(rc);
+  }
+  if ((rc = build_ragged(*p))) return cleanup(rc);
+  // several buckets: the forked per-bucket launches against the one
+  // persistent launch, whole evaluations on the tuned tiles (three rounds,
+  // the best of each; the persistent launch must win by 3 %)
+  if (p->buckets.size() > 1 && !p->launch_fixed) {
+    auto time_eval = [&](int32_t mode, int n, float *ms) -> int {
+      p->launch = mode;
+      hipError_t e = hipEventRecord(e0, stream);
+      int r = DEBYE_OK;
+      for (int k = 0; k < n && r == DEBYE_OK && e == hipSuccess; ++k)
+        r = debye_fit_eval(p, b, log10_tau, ld, damping, flags, cost, nullptr, nullptr, nullptr, stream);
+      if (r) return r;
+      if (e == hipSuccess) e = hipEventRecord(e1, stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+      return e == hipSuccess ? DEBYE_OK : hip_fail(e, "autotune launch");
+    };
+    float best[2] = {INFINITY, INFINITY}, ms = 0;
+    const int32_t modes[2] = {DEBYE_LAUNCH_BUCKETS, DEBYE_LAUNCH_PERSISTENT};
+    for (int m = 0; m < 2; ++m)
+      if ((rc = time_eval(modes[m], 1, &ms))) return cleanup(rc);
+    for (int round = 0; round < 3; ++round)
+      for (int m = 0; m < 2; ++m) {
+        if ((rc = time_eval(modes[m], reps, &ms))) return cleanup(rc);
+        best[m] = std::min(best[m], ms);
+      }
+    p->launch = best[1] < 0.97f * best[0] ? DEBYE_LAUNCH_PERSISTENT : DEBYE_LAUNCH_BUCKETS;
+    ++p->sched_gen;
   }
   return cleanup(DEBYE_OK);
 }
@@ -626,6 +752,21 @@ int debye_fit_eval(const debye_plan *p, const debye_batch *b, const double *log1
   if (rc) return rc;
   if ((rc = check_damping(damping, flags))) return rc;
   if (!log10_tau || !cost) return fail(DEBYE_EINVAL, "log10_tau and cost must not be NULL");
+  if (p->launch == DEBYE_LAUNCH_PERSISTENT && p->buckets.size() > 1) {
+    // one launch over every bucket, on the caller's stream
+    dfit::RaggedArgs r{};
+    r.common = fit_args(p, p->buckets[0], b, log10_tau, ld, damping, flags);
+    r.common.cost = cost;
+    r.common.weights = weights;
+    r.common.eps_inf = eps_inf;
+    r.common.status = status;
+    r.buckets = p->d_rbuckets;
+    r.items = p->d_items;
+    for (int x = 0; x < 9; ++x) r.item_off[x] = p->item_off[x];
+    r.counters = p->d_counters;
+    CHECK_HIP(dfit::launch_fit_ragged(r, RAGGED_BLOCKS, p->ragged_lds, stream), "debye_fit_eval persistent launch");
+    return DEBYE_OK;
+  }
   return for_buckets(p, stream, [&](const Bucket &bk, hipStream_t s) -> int {
     dfit::FitArgs a = fit_args(p, bk, b, log10_tau, ld, damping, flags);
     a.cost = cost;

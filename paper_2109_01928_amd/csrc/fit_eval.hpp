@@ -34,6 +34,22 @@ struct FitArgs {
   int64_t rec_ld;
 };
 
+// One persistent launch over every pole-count bucket of a plan
+// (fit_ragged.hip): per-bucket schedule fields, and the per-XCD lists of work
+// items, each (bucket << 40) | tile, longest first.
+struct RaggedBucket {
+  int32_t n_poles, freq_split, cand_per_wave, uni;
+  const int32_t *lane_cand, *lane_mat;
+};
+struct RaggedArgs {
+  FitArgs common;                // batch, candidates, outputs (schedule fields per bucket)
+  const RaggedBucket *buckets;   // [n_buckets]
+  const int64_t *items;          // work items of XCD x: item_off[x] .. item_off[x+1]-1
+  int64_t item_off[9];
+  int32_t *counters;             // [8] next item of each XCD (reset by the launch)
+};
+hipError_t launch_fit_ragged(const RaggedArgs &r, int32_t blocks, size_t lds_bytes, hipStream_t s);
+
 struct TargetGradArgs {
   const int64_t *f_off, *cand_off;
   const double *omega, *eps_re, *eps_im, *theta;

@@ -390,6 +390,100 @@ __device__ __forceinline__ void unpark(const double *park, int cpw, int grp, dou
 }
 
 // --------------------------------------------------------------------------
+// Cost pass in rational form.  With w >= 0 (the sign flip) the model sums
+// over a set of NR poles are rational functions of y = w^2 with positive
+// coefficients,
+//   sum_i w_i R_i = P(y) / Q(y),  sum_i (w_i tau_i) R_i = P'(y) / Q(y),
+//   Q(y) = prod_i (1 + y tau_i^2),  P(y) = sum_i w_i prod_{j != i} (1 + y tau_j^2),
+// evaluated by Horner's rule with one reciprocal per point (no cancellation:
+// every term is positive).  The variable is scaled by the largest tau^2 of
+// the set, so every coefficient is at most binomial-sized.  GS lanes, each
+// with its own set, add their sums at every point (GS = 1: the set is the
+// whole candidate).  The lane takes points k0, k0 + stride, ... and returns
+// its partial sums of squared residuals (cost) and of eps' - shift - model
+// (sa).  Returns true when the wave must use the basis form instead: a
+// lane's smallest coefficient would be subnormal, Q exceeds 1e280 at some
+// point, or a cost is not finite (lanes that do not matter are ignored).
+// --------------------------------------------------------------------------
+template <int NR, int GS, class LOAD, class LOAD_FIRST>
+__device__ __forceinline__ bool rational_cost_pass(const double *tau2, const double *w, const double *wt,
+                                                   bool matters, int64_t k0, int64_t stride, int64_t F,
+                                                   const double *om, const double *epr, const double *epi,
+                                                   double shift, LOAD ld, LOAD_FIRST ld_first, double &cost,
+                                                   double &sa) {
+  double tmax = 0.0;
+#pragma unroll
+  for (int i = 0; i < NR; ++i) tmax = tau2[i] > tmax ? tau2[i] : tmax;
+  const double isc = tmax > 0.0 ? 1.0 / tmax : 1.0;
+  // coefficients built one pole at a time, every update a sum of positive
+  // terms: with t the pole's scaled tau^2,
+  //   P <- P (1 + y t) + w Q,  P' <- P' (1 + y t) + (w tau) Q,  Q <- Q (1 + y t)
+  // (O(NR^2) fused multiply-adds; only Q, P, P' stay live)
+  double qc[NR + 1], cr[NR], ci[NR];
+  double pnz = 1.0;   // product of the nonzero scaled tau^2: the smallest coefficient
+  qc[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= NR; ++k) qc[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) cr[k] = ci[k] = 0.0;
+#pragma unroll
+  for (int m = 0; m < NR; ++m) {
+    const double t = tau2[m] * isc, wm = w[m], wtm = wt[m];
+    pnz *= t > 0.0 ? t : 1.0;
+#pragma unroll
+    for (int k = m; k >= 1; --k) {
+      cr[k] = __builtin_fma(wm, qc[k], __builtin_fma(t, cr[k - 1], cr[k]));
+      ci[k] = __builtin_fma(wtm, qc[k], __builtin_fma(t, ci[k - 1], ci[k]));
+    }
+    cr[0] = __builtin_fma(wm, qc[0], cr[0]);
+    ci[0] = __builtin_fma(wtm, qc[0], ci[0]);
+#pragma unroll
+    for (int k = m + 1; k >= 1; --k) qc[k] = __builtin_fma(t, qc[k - 1], qc[k]);
+  }
+  double csum = qc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) csum += cr[k] + ci[k];
+  const bool coef_ok = !matters || (pnz >= 1e-280 && fabs(csum) < INFINITY);
+  if (__builtin_amdgcn_ballot_w64(!coef_ok) != 0) return true;
+  cost = 0.0;
+  sa = 0.0;
+  double qmax = 0.0;
+  int64_t k = k0;
+  double w_n = 0, er_n = 0, ei_n = 0;
+  if (k < F) {
+    w_n = ld_first(om, k);
+    er_n = ld_first(epr, k);
+    ei_n = ld_first(epi, k);
+  }
+  // two points per trip: their Horner and reciprocal chains interleave
+#pragma unroll 2
+  for (; k < F; k += stride) {
+    const double om_k = w_n, er = er_n, ei = ei_n;
+    const int64_t kn = (k + stride < F) ? k + stride : k;   // in-bounds prefetch, no branch
+    w_n = ld(om, kn);
+    er_n = ld(epr, kn);
+    ei_n = ld(epi, kn);
+    const double y = (om_k * om_k) * tmax;
+    double hq = qc[NR], hr = cr[NR - 1], hi = ci[NR - 1];
+#pragma unroll
+    for (int d = NR - 1; d >= 0; --d) hq = __builtin_fma(hq, y, qc[d]);
+#pragma unroll
+    for (int d = NR - 2; d >= 0; --d) {
+      hr = __builtin_fma(hr, y, cr[d]);
+      hi = __builtin_fma(hi, y, ci[d]);
+    }
+    qmax = hq > qmax ? hq : qmax;
+    const double r = rcp_nr(hq);
+    const double rr = (er - shift) - group_sum<GS>(hr * r);
+    const double ri = __builtin_fma(-om_k, group_sum<GS>(hi * r), ei);
+    sa += rr;
+    cost = __builtin_fma(rr, rr, cost);
+    cost = __builtin_fma(ri, ri, cost);
+  }
+  return __builtin_amdgcn_ballot_w64(matters && (!(qmax <= 1e280) || !(fabs(cost) + fabs(sa) < INFINITY))) != 0;
+}
+
+// --------------------------------------------------------------------------
 // The kernel.  GRAD adds the adjoint (grad w.r.t. log10 tau, and per-candidate
 // records for the target gradient).
 // --------------------------------------------------------------------------
@@ -406,9 +500,10 @@ template <int N, int SP, bool GRAD, int UNI> constexpr int waves_per_simd() {
 //      the spectra are read with wave-uniform (scalar) loads;
 //   2: frequency split > 1: wave-uniform spectrum base, per-lane 32-bit
 //      byte offsets (one offset per point for the three arrays).
+// One work tile (one wavefront: the candidates the plan lists for it) of the
+// cost kernel for N poles; the kernels below call it for their tiles.
 template <int N, int SP, bool GRAD, int UNI>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_simd<N, SP, GRAD, UNI>())))
-void fit_kernel(const FitArgs a) {
+__device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
   using S = Shape<N, SP>;
   constexpr int NB = S::NB, NV = S::NV, NG = S::NG, D = S::D;
   extern __shared__ double lds_all[];
@@ -420,15 +515,6 @@ void fit_kernel(const FitArgs a) {
   const int sub = lane - grp * SL;
   const int q = sub % SP;            // pole block
   const int fl = UNI == 1 ? 0 : sub / SP; // frequency lane
-  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
-  // block b runs on XCD b % 8 as its (b / 8)-th block.  The plan gives every
-  // XCD its own list of tiles (whole materials where possible, so that a
-  // material's spectra stay in one L2; the lists balanced by work, each
-  // longest first).  The grid covers the longest list; surplus blocks exit.
-  const int xcd = blockIdx.x & 7;
-  const int64_t j = blockIdx.x >> 3;
-  if (j >= a.xcd_off[xcd + 1] - a.xcd_off[xcd]) return;
-  const int64_t tile = a.xcd_off[xcd] + j;
   const int64_t slot = tile * a.cand_per_wave + grp;
   const int32_t cand = a.lane_cand[slot];
   const bool active = cand >= 0;
@@ -828,108 +914,55 @@ void fit_kernel(const FitArgs a) {
     return acc;
   };
   double cost, sa = 0.0;
+  // lanes whose partial sums are added at the end: the frequency lanes of the
+  // pole group (basis form: the pole group's sums are combined per point), or
+  // all lanes of the candidate (rational form over the whole candidate)
+  int red_from = SP;
   if constexpr (GRAD) {
     cost = pass3_basis(sa);
   } else {
-    // With w >= 0 (the sign flip) the lane's model sums are rational
-    // functions of y = w^2 with positive coefficients,
-    //   sum_i w_i R_i = P(y) / Q(y),  sum_i (w_i tau_i) R_i = P'(y) / Q(y),
-    //   Q(y) = prod_i (1 + y tau_i^2),  P(y) = sum_i w_i prod_{j != i} (1 + y tau_j^2),
-    // evaluated by Horner's rule with one reciprocal per point (no
-    // cancellation: every term is positive).  The variable is scaled by the
-    // lane's largest tau^2, so every coefficient is at most binomial-sized.
-    // A wave falls back to the basis form if a lane's smallest coefficient
-    // would be subnormal, Q exceeds 1e280 at some point, or a cost is not
-    // finite.
-    double tmax = 0.0;
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) tmax = tau2_of(cI) > tmax ? tau2_of(cI) : tmax;
-    const double isc = tmax > 0.0 ? 1.0 / tmax : 1.0;
-    double tp[NB], qc[NB + 1], cr[NB], ci[NB];
-    double pnz = 1.0;   // product of the nonzero scaled tau^2: the smallest coefficient
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      tp[cI] = tau2_of(cI) * isc;
-      pnz *= tp[cI] > 0.0 ? tp[cI] : 1.0;
-    }
-    qc[0] = 1.0;
-#pragma unroll
-    for (int k = 1; k <= NB; ++k) qc[k] = 0.0;
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int k = i + 1; k >= 1; --k) qc[k] = __builtin_fma(tp[i], qc[k - 1], qc[k]);
-#pragma unroll
-    for (int k = 0; k < NB; ++k) cr[k] = ci[k] = 0.0;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      double e[NB];
-      e[0] = 1.0;
-#pragma unroll
-      for (int k = 1; k < NB; ++k) e[k] = 0.0;
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        if (i == j) continue;
-        const int deg = i < j ? i + 1 : i;   // factors taken so far, this one included
-#pragma unroll
-        for (int k = deg; k >= 1; --k) e[k] = __builtin_fma(tp[i], e[k - 1], e[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        cr[k] = __builtin_fma(wv_[j], e[k], cr[k]);
-        ci[k] = __builtin_fma(wt[j], e[k], ci[k]);
-      }
-    }
-    double csum = qc[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) csum += cr[k] + ci[k];
     // (lanes whose cost is replaced by their status do not count)
     const bool matters = active && !bad && ok;
-    const bool coef_ok = !matters || (pnz >= 1e-280 && fabs(csum) < INFINITY);
-    bool use_basis = !flip || __builtin_amdgcn_ballot_w64(!coef_ok) != 0;
-    cost = 0.0;
+    bool use_basis = !flip;
     if (!use_basis) {
-      double qmax = 0.0;
-      int64_t k = fl;
-      double w_n = 0, er_n = 0, ei_n = 0;
-      if (k < F) {
-        w_n = ld_first(om, k);
-        er_n = ld_first(epr, k);
-        ei_n = ld_first(epi, k);
-      }
-      // two points per trip: their Horner and reciprocal chains interleave
-#pragma unroll 2
-      for (; k < F; k += SF) {
-        const double w = w_n, er = er_n, ei = ei_n;
-        const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
-        w_n = ld(om, kn);
-        er_n = ld(epr, kn);
-        ei_n = ld(epi, kn);
-        const double y = (w * w) * tmax;
-        double hq = qc[NB], hr = cr[NB - 1], hi = ci[NB - 1];
+      if constexpr (SP == 1) {
+        double tau2v[NB];
 #pragma unroll
-        for (int d = NB - 1; d >= 0; --d) hq = __builtin_fma(hq, y, qc[d]);
+        for (int cI = 0; cI < NB; ++cI) tau2v[cI] = tau2_of(cI);
+        use_basis = rational_cost_pass<NB, 1>(tau2v, wv_, wt, matters, fl, SF, F, om, epr, epi, shift, ld, ld_first,
+                                             cost, sa);
+      } else {
+        // every lane of the candidate takes all N poles (gathered through the
+        // candidate's LDS region, whose right-hand-side, first-solution and
+        // scaling vectors are free after the solves) and every SL-th point:
+        // one rational function of degree N per point instead of SP of degree
+        // NB combined across lanes
+        const LdsLayout<N> lay(L);
+        double *t2s = lay.vb, *wsh = lay.vz, *wts = lay.invd;
+        __syncthreads();
 #pragma unroll
-        for (int d = NB - 2; d >= 0; --d) {
-          hr = __builtin_fma(hr, y, cr[d]);
-          hi = __builtin_fma(hi, y, ci[d]);
+        for (int cI = 0; cI < NB; ++cI) {
+          const int p = q * NB + cI;
+          if (p < N) {
+            t2s[p] = tau2_of(cI);
+            wsh[p] = wv_[cI];
+            wts[p] = wt[cI];
+          }
         }
-        qmax = hq > qmax ? hq : qmax;
-        const double r = rcp_nr(hq);
-        const double rr = (er - shift) - group_sum<SP>(hr * r);
-        const double ri = __builtin_fma(-w, group_sum<SP>(hi * r), ei);
-        sa += rr;
-        cost = __builtin_fma(rr, rr, cost);
-        cost = __builtin_fma(ri, ri, cost);
+        __syncthreads();
+        use_basis = rational_cost_pass<N, 1>(t2s, wsh, wts, matters, sub, SL, F, om, epr, epi, shift, ld, ld_first,
+                                            cost, sa);
+        red_from = 1;
       }
-      use_basis =
-          __builtin_amdgcn_ballot_w64(matters && (!(qmax <= 1e280) || !(fabs(cost) + fabs(sa) < INFINITY))) != 0;
     }
-    if (use_basis) cost = pass3_basis(sa);
+    if (use_basis) {
+      cost = pass3_basis(sa);
+      red_from = SP;
+    }
   }
-  cost = freq_sum(cost, SP, SL);
+  cost = freq_sum(cost, red_from, SL);
   if constexpr (!GRAD) {
-    sa = freq_sum(sa, SP, SL);
+    sa = freq_sum(sa, red_from, SL);
     if (F > 0) {
       cost -= sa * (sa / (double)F);
       einf = shift + sa / (double)F;
@@ -1075,6 +1108,21 @@ void fit_kernel(const FitArgs a) {
       }
     }
   }
+}
+
+// The cost kernel: one tile per 64-lane block.  XCD-aware tile order:
+// workgroups are dealt round-robin to the 8 XCDs, so block b runs on XCD
+// b % 8 as its (b / 8)-th block.  The plan gives every XCD its own list of
+// tiles (whole materials where possible, so that a material's spectra stay in
+// one L2; the lists balanced by work, each longest first).  The grid covers
+// the longest list; surplus blocks exit.
+template <int N, int SP, bool GRAD, int UNI>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_simd<N, SP, GRAD, UNI>())))
+void fit_kernel(const FitArgs a) {
+  const int xcd = blockIdx.x & 7;
+  const int64_t j = blockIdx.x >> 3;
+  if (j >= a.xcd_off[xcd + 1] - a.xcd_off[xcd]) return;
+  fit_tile<N, SP, GRAD, UNI>(a, a.xcd_off[xcd] + j);
 }
 
 // Pole split by pole count, measured per bucket on the ragged workload (each
