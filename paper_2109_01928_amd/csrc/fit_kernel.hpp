@@ -599,7 +599,35 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
     Sv[cI] = 0.0;
   }
   double sum_er = 0.0;
-  {
+  // one point of the Gram pass
+  auto gram_point = [&](double w, double er, double ei) {
+    double Iv[NV];
+    basis_Us<NB>(w, w * w, tau2s, sq, Iv);
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) bv[cI] = __builtin_fma(Iv[cI], ei, bv[cI]);
+    if constexpr (SP > 1) {
+#pragma unroll
+      for (int v = NB; v < NV; ++v) Iv[v] = ring_fetch<SP>(Iv[v % NB], v / NB);
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI)
+#pragma unroll
+        for (int d = 0; d <= D; ++d) G[cI * (D + 1) + d] = __builtin_fma(Iv[cI], Iv[cI + d], G[cI * (D + 1) + d]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = i; j < N; ++j) G[tri(N, i, j)] = __builtin_fma(Iv[i], Iv[j], G[tri(N, i, j)]);
+    }
+    sum_er += er;
+  };
+  // Two points per trip let the reciprocal chains of their bases interleave.
+  // With no DPP in the body (SP == 1) the compiler pairs the points itself.
+  // The ring's DPP moves are convergent operations, which the compiler does
+  // not unroll into a loop with a remainder, so on the pole-split path the
+  // pair is written out, where it fits the register budget: four pole lanes
+  // up to N = 20 (228 VGPRs at N = 20; the two-lane forms and N > 20 spill).
+  constexpr bool PAIR_RING = SP == 4 && N <= 20;
+  if constexpr (!PAIR_RING) {
     int64_t k = fl;
     double w_n = 0, er_n = 0, ei_n = 0;
     if (k < F) {
@@ -607,8 +635,7 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
       er_n = ld_first(epr, k);
       ei_n = ld_first(epi, k);
     }
-    // two points per trip: the reciprocal chains of their bases interleave
-#pragma unroll 2
+#pragma unroll SP == 1 ? 2 : 1
     for (; k < F; k += SF) {
       const double w = w_n, er = er_n, ei = ei_n;
       const int64_t kn = (k + SF < F) ? k + SF : k;   // in-bounds prefetch, no branch
@@ -634,6 +661,35 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
       }
       sum_er += er;
     }
+  } else {
+    // the odd point last; the pole lanes of a candidate share their
+    // frequency lane, hence their trip counts
+    int64_t k = fl;
+    double wa_n = 0, era_n = 0, eia_n = 0, wb_n = 0, erb_n = 0, eib_n = 0;
+    if (k < F) {
+      wa_n = ld_first(om, k);
+      era_n = ld_first(epr, k);
+      eia_n = ld_first(epi, k);
+    }
+    if (k + SF < F) {
+      wb_n = ld_first(om, k + SF);
+      erb_n = ld_first(epr, k + SF);
+      eib_n = ld_first(epi, k + SF);
+    }
+    for (; k + SF < F; k += 2 * SF) {
+      const double wa = wa_n, era = era_n, eia = eia_n, wb = wb_n, erb = erb_n, eib = eib_n;
+      // in-bounds prefetch of the next two points, no branch
+      const int64_t ka = (k + 2 * SF < F) ? k + 2 * SF : k, kb = (k + 3 * SF < F) ? k + 3 * SF : k;
+      wa_n = ld(om, ka);
+      era_n = ld(epr, ka);
+      eia_n = ld(epi, ka);
+      wb_n = ld(om, kb);
+      erb_n = ld(epr, kb);
+      eib_n = ld(epi, kb);
+      gram_point(wa, era, eia);
+      gram_point(wb, erb, eib);
+    }
+    if (k < F) gram_point(wa_n, era_n, eia_n);
   }
 #pragma unroll
   for (int e = 0; e < NG; ++e) G[e] = freq_sum(G[e], SP, SL);
