@@ -19,6 +19,8 @@ The JSON line also carries:
     vector peak;
   - fwd_adjoint_kernel_evals_per_s: the forward + variable-projection adjoint
     kernel over the same 8.4M candidates;
+  - fwd_no_refine_kernel_evals_per_s: the forward kernel without the
+    refinement step (DEBYE_FLAG_NO_REFINE; not the tolerance of `value`);
   - polish: 50 L-BFGS steps (adjoint gradients, 30 batched Armijo trials) on
     every material's swarm best, timed once;
   - batched_vs_per_material: a shard of the materials fitted whole (all swarm
@@ -285,6 +287,7 @@ def main():
     if not args.no_extras:
         theta = (pop.x if pop is not None else sw.x)
         line["fwd_adjoint_kernel_evals_per_s"] = adjoint_rate(D, plan, bb, theta, stream)
+        line["fwd_no_refine_kernel_evals_per_s"] = no_refine_rate(D, plan, bb, theta, stream)
         best = (pop.best_x if pop is not None else sw.gbest_x).clone()
         if args.polish_steps > 0:
             line["polish"] = polish_leg(D, wl, er, ei, best, lb, ub, args.polish_steps, stream)
@@ -323,6 +326,22 @@ def adjoint_rate(D, plan, bb, theta, stream, reps=2):
     g0.record(stream)
     for _ in range(reps):
         D.fit_eval_grad(plan, bb, theta)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    return bb.P * reps / (g0.elapsed_time(g1) * 1e-3)
+
+
+def no_refine_rate(D, plan, bb, theta, stream, reps=2):
+    """Forward kernel rate with DEBYE_FLAG_NO_REFINE (no refinement pass;
+    accuracy limited by the conditioning of the normal equations)."""
+    import torch
+    log("forward kernel rate without the refinement step")
+    D.fit_eval(plan, bb, theta, flags=D.FLAG_NO_REFINE, want_weights=False)
+    torch.cuda.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record(stream)
+    for _ in range(reps):
+        D.fit_eval(plan, bb, theta, flags=D.FLAG_NO_REFINE, want_weights=False)
     g1.record(stream)
     torch.cuda.synchronize()
     return bb.P * reps / (g0.elapsed_time(g1) * 1e-3)

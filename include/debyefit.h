@@ -62,7 +62,20 @@ enum {
 
 /* flags */
 enum {
-  DEBYE_FLAG_NO_SIGN_FLIP = 1u /* keep signed LS weights (w = z instead of |z|) */
+  DEBYE_FLAG_NO_SIGN_FLIP = 1u, /* keep signed LS weights (w = z instead of |z|) */
+  DEBYE_FLAG_NO_REFINE = 2u     /* skip the refinement step (one corrected
+                                   semi-normal-equations pass, Sec. III-B's damped
+                                   least squares solved to full accuracy): z is the
+                                   damped Cholesky solution of the normal equations
+                                   alone.  Faster (one basis pass fewer in the
+                                   forward evaluation), but its relative error in z
+                                   grows with the condition number of the scaled
+                                   damped Gram matrix (at most about
+                                   n_poles / damping) times the unit roundoff, so
+                                   costs are no longer within 1e-10 of the
+                                   least-squares result for ill-conditioned
+                                   candidates.  In debye_fit_eval_grad the
+                                   gradient formula then holds only to that error. */
 };
 
 /* material kinds for debye_material_eval (parameter rows of DEBYE_PARAM_STRIDE) */

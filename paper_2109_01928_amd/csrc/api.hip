@@ -314,9 +314,14 @@ int check_plan_batch(const debye_plan *p, const debye_batch *b, int64_t ld) {
   return DEBYE_OK;
 }
 
+static_assert((unsigned)DEBYE_FLAG_NO_SIGN_FLIP == (unsigned)dfit::FLAG_NO_SIGN_FLIP &&
+                  (unsigned)DEBYE_FLAG_NO_REFINE == (unsigned)dfit::FLAG_NO_REFINE,
+              "the kernels read the ABI's flag bits");
+
 int check_damping(double damping, uint32_t flags) {
   if (!(damping >= 0.0) || !std::isfinite(damping)) return fail(DEBYE_ERANGE, "damping must be finite and >= 0");
-  if (flags & ~(uint32_t)DEBYE_FLAG_NO_SIGN_FLIP) return fail(DEBYE_EINVAL, "unknown flag bits 0x%x", flags);
+  if (flags & ~(uint32_t)(DEBYE_FLAG_NO_SIGN_FLIP | DEBYE_FLAG_NO_REFINE))
+    return fail(DEBYE_EINVAL, "unknown flag bits 0x%x", flags);
   return DEBYE_OK;
 }
 

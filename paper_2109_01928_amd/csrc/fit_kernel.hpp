@@ -783,13 +783,16 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
   // The residual is nearly orthogonal to the columns of I, so g is a sum with
   // heavy cancellation; it is accumulated with compensation (residual
   // refinement with the residual products summed in extra precision).
+  // FLAG_NO_REFINE skips it (the forward kernels skip the whole pass; the
+  // adjoint still runs it for the column sums of R that its eps_inf needs).
+  const bool refine = !(a.flags & FLAG_NO_REFINE);
   double gv[NB], gl[NB];
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) {
     gv[cI] = 0.0;
     gl[cI] = 0.0;
   }
-  {
+  if (GRAD || refine) {
     // I z = w sum_i (tau_i s_i z_i) (R_i / s_i), and I^T r = tau s ((R / s)^T (w r))
     double zs[NB];
 #pragma unroll
@@ -850,38 +853,40 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], 1.0, pb[cI]);
     }
-  }
 #pragma unroll
-  for (int cI = 0; cI < NB; ++cI) {
-    gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL) * ts[cI];
-    if constexpr (GRAD) Sv[cI] = freq_sum(Sv[cI], SP, SL) * pole_scale<NB>(sq, cI);
+    for (int cI = 0; cI < NB; ++cI) {
+      gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL) * ts[cI];
+      if constexpr (GRAD) Sv[cI] = freq_sum(Sv[cI], SP, SL) * pole_scale<NB>(sq, cI);
+    }
   }
 
   // correction: zt += A^-1 (D^-1 g - damping zt)
-  if constexpr (SP == 1) {
-    double dz[N];
+  if (refine) {
+    if constexpr (SP == 1) {
+      double dz[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) dz[i] = __builtin_fma(gv[i], invd_r[i], -damping * zt[i]);
-    double Af[S::NT], uf[N];
-    unpark<N>(lds_all, WAVE / SL, grp, Af, uf);
-    chol_solve<N>(Af, uf, dz);
+      for (int i = 0; i < N; ++i) dz[i] = __builtin_fma(gv[i], invd_r[i], -damping * zt[i]);
+      double Af[S::NT], uf[N];
+      unpark<N>(lds_all, WAVE / SL, grp, Af, uf);
+      chol_solve<N>(Af, uf, dz);
 #pragma unroll
-    for (int i = 0; i < N; ++i) zt[i] += dz[i];
-  } else {
-    const LdsLayout<N> lay(L);
-    double *A = lay.A, *uinv = lay.uinv, *vw = lay.vw;
+      for (int i = 0; i < N; ++i) zt[i] += dz[i];
+    } else {
+      const LdsLayout<N> lay(L);
+      double *A = lay.A, *uinv = lay.uinv, *vw = lay.vw;
 #pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      const int p = q * NB + cI;
-      if (p < N) vw[p] = __builtin_fma(gv[cI], invd_own[cI], -damping * zt[cI]);
-    }
-    __syncthreads();
-    lds_chol_solve(N, A, uinv, vw);
-    __syncthreads();
+      for (int cI = 0; cI < NB; ++cI) {
+        const int p = q * NB + cI;
+        if (p < N) vw[p] = __builtin_fma(gv[cI], invd_own[cI], -damping * zt[cI]);
+      }
+      __syncthreads();
+      lds_chol_solve(N, A, uinv, vw);
+      __syncthreads();
 #pragma unroll
-    for (int cI = 0; cI < NB; ++cI) {
-      const int p = q * NB + cI;
-      zt[cI] += p < N ? vw[p] : 0.0;
+      for (int cI = 0; cI < NB; ++cI) {
+        const int p = q * NB + cI;
+        zt[cI] += p < N ? vw[p] : 0.0;
+      }
     }
   }
   double wv_[NB];
