@@ -488,10 +488,11 @@ __device__ __forceinline__ bool rational_cost_pass(const double *tau2, const dou
 // records for the target gradient).
 // --------------------------------------------------------------------------
 // target waves per SIMD: bounds the register budget of each instantiation
-// (three for the small one-lane kernels and for the uniform-tile forward
-// N = 12 two-lane kernels, which fit 168 registers; two elsewhere)
+// (three for the small one-lane kernels, which fit 168 registers; two
+// elsewhere: the N = 12 two-lane kernels fit three waves with one point per
+// trip of the Gram pass, but two waves with two points per trip are faster)
 template <int N, int SP, bool GRAD, int UNI> constexpr int waves_per_simd() {
-  return ((SP == 1 && N <= 6) || (SP == 2 && N == 12 && !GRAD && UNI != 0)) ? 3 : 2;
+  return (SP == 1 && N <= 6) ? 3 : 2;
 }
 
 // UNI (uniform tiles; the plan checks that every active lane of every tile
@@ -624,9 +625,11 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
   // With no DPP in the body (SP == 1) the compiler pairs the points itself.
   // The ring's DPP moves are convergent operations, which the compiler does
   // not unroll into a loop with a remainder, so on the pole-split path the
-  // pair is written out, where it fits the register budget: four pole lanes
-  // up to N = 20 (228 VGPRs at N = 20; the two-lane forms and N > 20 spill).
-  constexpr bool PAIR_RING = SP == 4 && N <= 20;
+  // pair is written out where it fits the register budget at two waves per
+  // SIMD: four pole lanes up to N = 20 (228 VGPRs at N = 20), two up to
+  // N = 14 (the general-tile form from N = 13 on, N = 15, 16 and N > 20
+  // spill with it).
+  constexpr bool PAIR_RING = (SP == 4 && N <= 20) || (SP == 2 && (N == 12 || (N <= 14 && UNI != 0)));
   if constexpr (!PAIR_RING) {
     int64_t k = fl;
     double w_n = 0, er_n = 0, ei_n = 0;
