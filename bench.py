@@ -107,7 +107,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-material", type=int, default=8,
-                    help="materials timed in the plain per-material loop (0: skip the comparison)")
+                    help="materials timed in the plain per-material loop (0: only the batched whole fit of the "
+                         "shard; -1: skip both)")
     ap.add_argument("--shard", type=int, default=512,
                     help="materials of the batched whole fit that the per-material loop is compared with")
     ap.add_argument("--no-extras", action="store_true",
@@ -291,7 +292,7 @@ def main():
         best = (pop.best_x if pop is not None else sw.gbest_x).clone()
         if args.polish_steps > 0:
             line["polish"] = polish_leg(D, wl, er, ei, best, lb, ub, args.polish_steps, stream)
-        if args.per_material > 0:
+        if args.per_material >= 0:
             line["batched_vs_per_material"] = shard_comparison(D, W, wl, er, ei, args)
         del theta, best
     if not args.no_cpu_baseline:
@@ -373,9 +374,10 @@ def polish_leg(D, wl, er, ei, best, lb, ub, steps, stream):
 
 def shard_comparison(D, W, wl, er, ei, args):
     """Batched fit vs the plain per-material loop at equal final residual: the
-    first `shard` materials fitted together (swarm of the workload's size and
-    iteration count, graph-replayed, then the L-BFGS polish); then, for the
-    first `per_material` of them, each material alone (its own plan and swarm,
+    first `shard` materials fitted together (the chosen optimiser with the
+    workload's population and iteration count, graph-replayed, then the L-BFGS
+    polish); then, for the swarm only, the first `per_material` of them, each
+    material alone (its own plan and swarm,
     forward evaluations only, the host reading the best cost after every
     iteration) until its best cost is within 1e-3 of the batched final cost, or
     10x the iterations.  Times per material are compared; the per-material
@@ -397,9 +399,16 @@ def shard_comparison(D, W, wl, er, ei, args):
     pol = D.Polish(b1, wl.ld, steps=max(steps, 1), mem=MEM, max_trials=T_TRIALS)
     plan1 = D.Plan(b1)
 
+    pop = D.Population.empty(bs.P, S, wl.ld, wl.iters + 1) if args.optimizer != "pso" else None
+
     def batched(mode):
-        D.pso_run(plan, bs, lbs, ubs, sw, wl.iters, wl.inertia, wl.c1, wl.c2, wl.seed, use_graph=mode)
-        best = sw.gbest_x.clone()
+        if args.optimizer == "de":
+            D.de_run(plan, bs, lbs, ubs, pop, wl.iters, seed=wl.seed, use_graph=mode)
+        elif args.optimizer == "da":
+            D.da_run(plan, bs, lbs, ubs, pop, wl.iters, seed=wl.seed, use_graph=mode)
+        else:
+            D.pso_run(plan, bs, lbs, ubs, sw, wl.iters, wl.inertia, wl.c1, wl.c2, wl.seed, use_graph=mode)
+        best = (pop.best_x if pop is not None else sw.gbest_x).clone()
         if steps > 0:
             pol.run(b1, best, lbs, ubs)
         return best
@@ -416,8 +425,8 @@ def shard_comparison(D, W, wl, er, ei, args):
     final = c1.cpu().numpy()
     afe = D.afe(b1, best, w1, e1).cpu().numpy()
     batched_s = times["graph"]
-    # the plain per-material loop
-    K = min(args.per_material, S)
+    # the plain per-material loop (the swarm's; for DE and DA only the batched fit is timed)
+    K = min(args.per_material, S) if args.optimizer == "pso" else 0
     cap = 10 * wl.iters
     t_mat, reached, used = [], 0, []
     for m in range(K):
@@ -442,13 +451,15 @@ def shard_comparison(D, W, wl, er, ei, args):
         t_mat.append(time.perf_counter() - t)
         reached += best_c <= goal
         used.append(it)
-    per_mat = float(np.mean(t_mat))
-    return {"shard_materials": S, "iterations": wl.iters, "polish_steps": steps,
-            "batched_s": batched_s, "batched_eager_s": times["eager"], "batched_s_per_material": batched_s / S,
-            "per_material_timed": K, "per_material_s_mean": per_mat, "per_material_extrapolated_s": per_mat * S,
-            "speedup": per_mat * S / batched_s, "reached_batched_cost": f"{reached}/{K}",
-            "median_iterations": float(np.median(used)), "iteration_cap": cap,
-            "afe_percent_median": float(np.median(afe)), "afe_below_5_percent": float(np.mean(afe < 5.0))}
+    out = {"optimizer": args.optimizer, "shard_materials": S, "iterations": wl.iters, "polish_steps": steps,
+           "batched_s": batched_s, "batched_eager_s": times["eager"], "batched_s_per_material": batched_s / S,
+           "afe_percent_median": float(np.median(afe)), "afe_below_5_percent": float(np.mean(afe < 5.0))}
+    if K > 0:
+        per_mat = float(np.mean(t_mat))
+        out.update({"per_material_timed": K, "per_material_s_mean": per_mat, "per_material_extrapolated_s": per_mat * S,
+                    "speedup": per_mat * S / batched_s, "reached_batched_cost": f"{reached}/{K}",
+                    "median_iterations": float(np.median(used)), "iteration_cap": cap})
+    return out
 
 
 def cpu_leg(D, W, wl, er, ei, plan, seconds):
