@@ -21,7 +21,7 @@ The JSON line also carries:
     kernel over the same 8.4M candidates;
   - fwd_no_refine_kernel_evals_per_s: the forward kernel without the
     refinement step (DEBYE_FLAG_NO_REFINE; not the tolerance of `value`);
-  - polish: 50 L-BFGS steps (adjoint gradients, 30 batched Armijo trials) on
+  - polish: 50 L-BFGS steps (adjoint gradients, up to 30 Armijo trials) on
     every material's swarm best, timed once;
   - batched_vs_per_material: a shard of the materials fitted whole (all swarm
     iterations + polish) in one batch, against the plain per-material loop
@@ -350,8 +350,10 @@ def no_refine_rate(D, plan, bb, theta, stream, reps=2):
 
 def polish_leg(D, wl, er, ei, best, lb, ub, steps, stream):
     """50 L-BFGS steps on every material's swarm best: per step one batched
-    forward launch of the 30 Armijo trials of every material and one
-    forward + adjoint launch at the accepted points."""
+    forward launch of every material's full step, one of the remaining Armijo
+    trials (of the materials whose full step failed), and one forward +
+    adjoint launch at the accepted points; materials that accept no trial
+    stall and drop out of the launches."""
     import torch
     log(f"polish leg: {steps} steps x {T_TRIALS} trials on {wl.M} materials")
     b1 = D.Batch(wl.f_off, np.arange(wl.M + 1), wl.n_poles, wl.omega, er, ei)
@@ -366,9 +368,10 @@ def polish_leg(D, wl, er, ei, best, lb, ub, steps, stream):
     s = e0.elapsed_time(e1) * 1e-3
     h = hist.cpu().numpy()
     drop = 1 - h[:, -1] / h[:, 0]
-    evals = wl.M * steps * T_TRIALS + wl.M * (steps + 1)
-    return {"materials": wl.M, "steps": steps, "trials": T_TRIALS, "seconds": s,
-            "evals": evals, "evals_per_s": evals / s, "median_rel_cost_drop": float(np.median(drop)),
+    # materials whose last step still moved (the others stalled: no acceptable trial)
+    moving = float(np.mean(h[:, -1] < h[:, -2])) if steps > 0 else 0.0
+    return {"materials": wl.M, "steps": steps, "trials": T_TRIALS, "seconds": s, "ms_per_step": 1e3 * s / max(steps, 1),
+            "median_rel_cost_drop": float(np.median(drop)), "moving_at_last_step": moving,
             "monotone": bool(np.all(np.diff(h, axis=1) <= 0))}
 
 

@@ -447,6 +447,12 @@ template <class LAUNCH> int for_buckets(const debye_plan *p, hipStream_t stream,
 
 }  // namespace
 
+namespace {
+int fit_eval_impl(const debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld, double damping,
+                  uint32_t flags, double *cost, double *weights, double *eps_inf, int8_t *status,
+                  const int32_t *skip_mat, hipStream_t stream);
+}  // namespace
+
 extern "C" {
 
 const char *debye_last_error(void) { return g_error.c_str(); }
@@ -753,6 +759,18 @@ int debye_basis(const double *omega, int64_t F, const double *log10_tau, int64_t
 
 int debye_fit_eval(const debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld, double damping,
                    uint32_t flags, double *cost, double *weights, double *eps_inf, int8_t *status, hipStream_t stream) {
+  return fit_eval_impl(p, b, log10_tau, ld, damping, flags, cost, weights, eps_inf, status, nullptr, stream);
+}
+
+}  // extern "C"
+
+namespace {
+// debye_fit_eval with an optional mask of materials to leave out ([M],
+// nonzero = skip: waves holding only such candidates exit at once and their
+// outputs are left as they were)
+int fit_eval_impl(const debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld, double damping,
+                  uint32_t flags, double *cost, double *weights, double *eps_inf, int8_t *status,
+                  const int32_t *skip_mat, hipStream_t stream) {
   int rc = check_plan_batch(p, b, ld);
   if (rc) return rc;
   if ((rc = check_damping(damping, flags))) return rc;
@@ -765,6 +783,7 @@ int debye_fit_eval(const debye_plan *p, const debye_batch *b, const double *log1
     r.common.weights = weights;
     r.common.eps_inf = eps_inf;
     r.common.status = status;
+    r.common.skip_mat = skip_mat;
     r.buckets = p->d_rbuckets;
     r.items = p->d_items;
     for (int x = 0; x < 9; ++x) r.item_off[x] = p->item_off[x];
@@ -778,12 +797,12 @@ int debye_fit_eval(const debye_plan *p, const debye_batch *b, const double *log1
     a.weights = weights;
     a.eps_inf = eps_inf;
     a.status = status;
+    a.skip_mat = skip_mat;
     CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, false, bk.uni, s), "debye_fit_eval launch");
     return DEBYE_OK;
   });
 }
-
-}  // extern "C"
+}  // namespace
 
 namespace {
 // cost + adjoint launches of every bucket; `record` ([n_cand][rec_ld]
@@ -792,7 +811,7 @@ namespace {
 int fit_eval_grad_launch(const debye_plan *p, const debye_batch *b, const double *log10_tau, int64_t ld,
                          double damping, uint32_t flags, const double *grad_cost, double *cost,
                          double *grad_log10_tau, double *grad_eps_re, double *grad_eps_im, int8_t *status,
-                         double *record, int64_t rec_ld, hipStream_t stream) {
+                         double *record, int64_t rec_ld, hipStream_t stream, const int32_t *skip_mat = nullptr) {
   const bool targets = grad_eps_re != nullptr;
   if (targets) {
     // materials without candidates get zero target gradients (a fill kernel,
@@ -808,6 +827,7 @@ int fit_eval_grad_launch(const debye_plan *p, const debye_batch *b, const double
     a.grad_theta = grad_log10_tau;
     a.record = targets ? record : nullptr;
     a.rec_ld = rec_ld;
+    a.skip_mat = targets ? nullptr : skip_mat;
     CHECK_HIP(dfit::launch_fit(bk.N, a, bk.n_tiles, true, bk.uni, s), "debye_fit_eval_grad launch");
     if (!targets) return DEBYE_OK;
     dfit::TargetGradArgs t{};
@@ -1348,9 +1368,10 @@ struct debye_polish {
   debye_plan *p1 = nullptr, *pT = nullptr;
   void *ws = nullptr;         // one allocation for every buffer below
   int64_t *trial_off = nullptr;
-  double *grad, *S, *Y, *rho, *dir, *gd, *trial_theta, *trial_cost, *new_theta, *new_cost, *new_grad, *cost, *acc_cost;
-  int32_t *hist_n, *hist_head, *accepted;
-  int8_t *trial_status, *new_status;
+  double *grad, *S, *Y, *rho, *dir, *gd, *trial_theta, *trial_cost, *new_theta, *new_cost, *new_grad, *cost, *acc_cost,
+      *first_cost;
+  int32_t *hist_n, *hist_head, *accepted, *done, *stalled;
+  int8_t *trial_status, *new_status, *first_status;
 };
 
 namespace {
@@ -1388,6 +1409,10 @@ dfit::LbfgsArgs polish_args(const debye_polish *pp, const debye_batch *b, double
   la.trial_theta = pp->trial_theta;
   la.trial_cost = pp->trial_cost;
   la.trial_status = pp->trial_status;
+  la.first_cost = pp->first_cost;
+  la.first_status = pp->first_status;
+  la.done = pp->done;
+  la.stalled = pp->stalled;
   la.new_theta = pp->new_theta;
   la.accepted = pp->accepted;
   la.new_cost = pp->new_cost;
@@ -1435,8 +1460,9 @@ int debye_polish_create(const debye_batch *shape, const int64_t *f_off_host, con
   const int64_t n1 = (int64_t)M * ld, nT = (int64_t)M * T;
   const size_t doubles = (size_t)(n1 /*grad*/ + 2 * (int64_t)M * lp.mem * ld /*S,Y*/ + (int64_t)M * lp.mem /*rho*/ +
                                   n1 /*dir*/ + M /*gd*/ + nT * ld /*trial theta*/ + nT /*trial cost*/ + n1 /*new theta*/ +
-                                  M /*new cost*/ + n1 /*new grad*/ + M /*cost*/ + M /*accepted cost*/);
-  const size_t bytes = (size_t)(M + 1) * 8 + doubles * 8 + (size_t)3 * M * 4 + (size_t)nT + (size_t)M + 64;
+                                  M /*new cost*/ + n1 /*new grad*/ + M /*cost*/ + M /*accepted cost*/ +
+                                  M /*first trials' cost*/);
+  const size_t bytes = (size_t)(M + 1) * 8 + doubles * 8 + (size_t)5 * M * 4 + (size_t)nT + (size_t)2 * M + 64;
   if (hipMalloc(&pp->ws, bytes) != hipSuccess) {
     pp->ws = nullptr;
     return bail(fail(DEBYE_ENOMEM, "polish workspace allocation failed"));
@@ -1461,12 +1487,16 @@ int debye_polish_create(const debye_batch *shape, const int64_t *f_off_host, con
   pp->new_grad = take(n1);
   pp->cost = take(M);
   pp->acc_cost = take(M);
+  pp->first_cost = take(M);
   int32_t *ip = (int32_t *)dp;
   pp->hist_n = ip;
   pp->hist_head = ip + M;
   pp->accepted = ip + 2 * M;
-  pp->trial_status = (int8_t *)(ip + 3 * M);
+  pp->done = ip + 3 * M;
+  pp->stalled = ip + 4 * M;
+  pp->trial_status = (int8_t *)(ip + 5 * M);
   pp->new_status = pp->trial_status + nT;
+  pp->first_status = pp->new_status + M;
   if (hipMemcpy(pp->trial_off, trials.data(), (M + 1) * 8, hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(DEBYE_EHIP, "polish: upload of the trial offsets failed"));
   debye_batch bt = *shape;
@@ -1498,6 +1528,7 @@ int debye_polish_begin(debye_polish *pp, const debye_batch *b, const double *the
   if (!theta) return fail(DEBYE_EINVAL, "theta is NULL");
   // empty history (a fill kernel, not a memset, so that the call can be captured)
   CHECK_HIP(dfit::launch_fill_i32(pp->hist_n, 2 * (int64_t)pp->M, 0, stream), "fill");
+  CHECK_HIP(dfit::launch_fill_i32(pp->stalled, (int64_t)pp->M, 0, stream), "fill");
   return debye_fit_eval_grad(pp->p1, b, theta, pp->ld, damping, flags, nullptr, pp->cost, pp->grad, nullptr, nullptr,
                              pp->new_status, stream);
 }
@@ -1516,12 +1547,25 @@ int debye_polish_step(debye_polish *pp, const debye_batch *b, double *theta, con
   bt.n_cand = (int64_t)pp->M * pp->max_trials;
   hipError_t e = dfit::launch_lbfgs_direction(la, stream);
   if (e != hipSuccess) return hip_fail(e, "lbfgs direction");
-  if ((rc = debye_fit_eval(pp->pT, &bt, pp->trial_theta, pp->ld, damping, flags, pp->trial_cost, nullptr, nullptr,
-                           pp->trial_status, stream)))
+  // the full step of every material still moving (trial 0: rows m * max_trials
+  // of the trial array).  A material whose step found no acceptable trial is
+  // stalled for good: its point, gradient and history stay as they were, so
+  // every later step would rebuild the same trials and reject them again.
+  if ((rc = fit_eval_impl(pp->p1, b, pp->trial_theta, pp->ld * pp->max_trials, damping, flags, pp->first_cost,
+                          nullptr, nullptr, pp->first_status, pp->stalled, stream)))
     return rc;
-  if ((e = dfit::launch_lbfgs_select(la, stream)) != hipSuccess) return hip_fail(e, "lbfgs select");
-  if ((rc = debye_fit_eval_grad(pp->p1, b, pp->new_theta, pp->ld, damping, flags, nullptr, pp->new_cost, pp->new_grad,
-                                nullptr, nullptr, pp->new_status, stream)))
+  if ((e = dfit::launch_lbfgs_first(la, stream)) != hipSuccess) return hip_fail(e, "lbfgs first trial");
+  if (pp->max_trials > 1) {
+    // the remaining trials, only for the materials the full step left undecided
+    if ((rc = fit_eval_impl(pp->pT, &bt, pp->trial_theta, pp->ld, damping, flags, pp->trial_cost, nullptr, nullptr,
+                            pp->trial_status, pp->done, stream)))
+      return rc;
+    if ((e = dfit::launch_lbfgs_select(la, stream)) != hipSuccess) return hip_fail(e, "lbfgs select");
+  }
+  // cost and gradient at the accepted points (the stalled materials, which
+  // accepted none, are left out)
+  if ((rc = fit_eval_grad_launch(pp->p1, b, pp->new_theta, pp->ld, damping, flags, nullptr, pp->new_cost, pp->new_grad,
+                                 nullptr, nullptr, pp->new_status, nullptr, 0, stream, pp->stalled)))
     return rc;
   if ((e = dfit::launch_lbfgs_update(la, stream)) != hipSuccess) return hip_fail(e, "lbfgs update");
   return DEBYE_OK;

@@ -32,6 +32,9 @@ struct FitArgs {
   double *grad_theta;
   double *record;  // [n_cand][rec_ld] per-candidate w | z | mu | eps_inf, gc (or NULL)
   int64_t rec_ld;
+  // [M] or NULL: materials whose candidates need no evaluation (nonzero);
+  // a wave holding only such candidates exits at once, writing nothing
+  const int32_t *skip_mat;
 };
 
 // One persistent launch over every pole-count bucket of a plan
@@ -201,6 +204,10 @@ struct LbfgsArgs {
   double *trial_theta; // [M*max_trials][ld]
   const double *trial_cost;  // [M*max_trials]
   const int8_t *trial_status;
+  const double *first_cost;    // [M] cost of each material's first trial (full step)
+  const int8_t *first_status;  // [M]
+  int32_t *done;       // [M] step decided by the first trial (or skipped)
+  int32_t *stalled;    // [M] no acceptable trial at some step: the point never moves again
   double *new_theta;   // [M][ld] accepted point
   double *acc_cost;    // [M] cost of the accepted trial
   int32_t *accepted;   // [M]
@@ -210,6 +217,7 @@ struct LbfgsArgs {
   int32_t step, steps;
 };
 hipError_t launch_lbfgs_direction(const LbfgsArgs &a, hipStream_t s);
+hipError_t launch_lbfgs_first(const LbfgsArgs &a, hipStream_t s);
 hipError_t launch_lbfgs_select(const LbfgsArgs &a, hipStream_t s);
 hipError_t launch_lbfgs_update(const LbfgsArgs &a, hipStream_t s);
 

@@ -521,6 +521,9 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
   const bool active = cand >= 0;
   const int32_t mat = active ? a.lane_mat[slot] : 0;
   const int64_t c = active ? cand : 0;
+  // a wave whose candidates all belong to materials marked done exits
+  // before any work (wave-uniform: a block is one wave)
+  if (a.skip_mat && __builtin_amdgcn_ballot_w64(active && a.skip_mat[mat] == 0) == 0) return;
 
   int64_t f0 = 0, F = 0;
   if constexpr (UNI != 0) {

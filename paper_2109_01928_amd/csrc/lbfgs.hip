@@ -3,10 +3,15 @@
 // Armijo backtracking alpha = 1, 1/2, 1/4, ... inside the search box: each
 // trial point is projected onto [lb, ub] and the sufficient-decrease test uses
 // the projected displacement p, C(trial) <= C + c1 min(g.p, 0) (clamping can
-// make g.p positive; the cost is then not allowed to rise).  The trial points of
-// one step are all evaluated in one batched cost launch, and the accepted step
+// make g.p positive; the cost is then not allowed to rise).  The accepted step
 // is the first trial (largest alpha) that passes, which is what a sequential
-// halving search returns.  One thread per material.
+// halving search returns.  The trials are evaluated in two batched cost
+// launches: the full step of every material first; then all further trials,
+// only for the materials whose full step failed (the others' waves exit at
+// once).  A step that accepts no trial leaves the point, gradient and history
+// as they were, so every later step would rebuild and reject the same trials:
+// such a material is marked stalled and left out of all later evaluations.
+// One thread per material.
 
 #include "common.hpp"
 #include "fit_eval.hpp"
@@ -98,31 +103,70 @@ __global__ __launch_bounds__(256) void lbfgs_direction_kernel(const LbfgsArgs a)
   }
 }
 
-__global__ __launch_bounds__(256) void lbfgs_select_kernel(const LbfgsArgs a) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= a.M) return;
+namespace {
+// the sufficient-decrease test of trial t of material m
+__device__ bool armijo_ok(const LbfgsArgs &a, int m, int t, double cost_t, int8_t status_t) {
   const int N = a.n_poles[m];
-  const double gd = a.gd[m];
-  const double C = a.cost[m];
-  int pick = -1;
   const double *g = a.grad + (int64_t)m * a.ld;
   const double *th = a.theta + (int64_t)m * a.ld;
-  if (gd == gd) {  // not skipped
-    for (int t = 0; t < a.max_trials; ++t) {
-      const int64_t r = (int64_t)m * a.max_trials + t;
-      const double *tt = a.trial_theta + r * a.ld;
-      double gp = 0.0;
-      for (int i = 0; i < N; ++i) gp += g[i] * (tt[i] - th[i]);
-      if (a.trial_status[r] == ST_OK && a.trial_cost[r] <= C + a.c1 * fmin(gp, 0.0)) {
-        pick = t;
-        break;
-      }
-    }
-  }
+  const double *tt = a.trial_theta + ((int64_t)m * a.max_trials + t) * a.ld;
+  double gp = 0.0;
+  for (int i = 0; i < N; ++i) gp += g[i] * (tt[i] - th[i]);
+  return status_t == ST_OK && cost_t <= a.cost[m] + a.c1 * fmin(gp, 0.0);
+}
+
+// the step's outcome: trial `pick` accepted with cost `c`, or none (pick < 0)
+__device__ void decide(const LbfgsArgs &a, int m, int pick, double c) {
+  const int N = a.n_poles[m];
   a.accepted[m] = pick >= 0 ? 1 : 0;
-  a.acc_cost[m] = pick >= 0 ? a.trial_cost[(int64_t)m * a.max_trials + pick] : C;
+  a.acc_cost[m] = pick >= 0 ? c : a.cost[m];
   const double *src = pick >= 0 ? a.trial_theta + ((int64_t)m * a.max_trials + pick) * a.ld : a.theta + (int64_t)m * a.ld;
   for (int i = 0; i < N; ++i) a.new_theta[(int64_t)m * a.ld + i] = src[i];
+}
+}  // namespace
+
+// after the first launch: materials whose full step passes (or that are
+// skipped) are decided; the rest wait for the remaining trials
+__global__ __launch_bounds__(256) void lbfgs_first_kernel(const LbfgsArgs a) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.M) return;
+  const double gd = a.gd[m];
+  // stalled earlier (its full step was not evaluated), or nothing to step
+  // along (non-finite cost or gradient, zero gradient): no step
+  if (a.stalled[m] || !(gd == gd)) {
+    decide(a, m, -1, 0.0);
+    a.done[m] = 1;
+    a.stalled[m] = 1;
+    return;
+  }
+  if (armijo_ok(a, m, 0, a.first_cost[m], a.first_status[m])) {
+    decide(a, m, 0, a.first_cost[m]);
+    a.done[m] = 1;
+    return;
+  }
+  a.done[m] = 0;
+  if (a.max_trials == 1) {
+    decide(a, m, -1, 0.0);
+    a.stalled[m] = 1;
+  }
+}
+
+// after the second launch: the first of the remaining trials that passes
+__global__ __launch_bounds__(256) void lbfgs_select_kernel(const LbfgsArgs a) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.M || a.done[m]) return;
+  int pick = -1;
+  double c = 0.0;
+  for (int t = 1; t < a.max_trials; ++t) {
+    const int64_t r = (int64_t)m * a.max_trials + t;
+    if (armijo_ok(a, m, t, a.trial_cost[r], a.trial_status[r])) {
+      pick = t;
+      c = a.trial_cost[r];
+      break;
+    }
+  }
+  decide(a, m, pick, c);
+  if (pick < 0) a.stalled[m] = 1;
 }
 
 __global__ __launch_bounds__(256) void lbfgs_update_kernel(const LbfgsArgs a) {
@@ -167,6 +211,10 @@ static dim3 grid_for(int32_t M) { return dim3((unsigned)((M + 255) / 256)); }
 
 hipError_t launch_lbfgs_direction(const LbfgsArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(lbfgs_direction_kernel, grid_for(a.M), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_lbfgs_first(const LbfgsArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(lbfgs_first_kernel, grid_for(a.M), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_lbfgs_select(const LbfgsArgs &a, hipStream_t s) {
