@@ -75,13 +75,13 @@ def log(msg):
 def make_workload(W, args):
     it = args.iters
     if args.workload == "mixed":
-        wl = W.mixed_uniform(M=args.materials or 1024, iters=it if it >= 0 else 200)
+        wl = W.mixed_uniform(M=args.materials or 1024, N=args.poles or 8, iters=it if it >= 0 else 200)
     elif args.workload == "single":
         wl = W.single_hn()
     elif args.workload == "ragged":
         wl = W.mixed_ragged(M=args.materials or 4096, iters=it if it >= 0 else 300)
     elif args.workload == "hncc":
-        wl = W.hn_cc(M=args.materials or 1024, iters=it if it >= 0 else 200)
+        wl = W.hn_cc(M=args.materials or 1024, N=args.poles or 12, iters=it if it >= 0 else 200)
     else:
         wl = W.tables(M=args.materials or 65536, iters=it if it >= 0 else 400)
     if it >= 0:
@@ -102,6 +102,7 @@ def main():
                     help="global search: particle swarm (default), differential evolution (rand/1/bin) or "
                          "annealing (batched generalized simulated annealing chains)")
     ap.add_argument("--materials", type=int, default=0, help="override the workload's material count")
+    ap.add_argument("--poles", type=int, default=0, help="override the pole count (mixed and hncc workloads)")
     ap.add_argument("--iters", type=int, default=-1, help="override the workload's swarm iterations (shard fit)")
     ap.add_argument("--polish-steps", type=int, default=-1)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
