@@ -351,10 +351,11 @@ def no_refine_rate(D, plan, bb, theta, stream, reps=2):
 
 def polish_leg(D, wl, er, ei, best, lb, ub, steps, stream):
     """50 L-BFGS steps on every material's swarm best: per step one batched
-    forward launch of every material's full step, one of the remaining Armijo
-    trials (of the materials whose full step failed), and one forward +
-    adjoint launch at the accepted points; materials that accept no trial
-    stall and drop out of the launches."""
+    forward launch of every material's full step, then launches of further
+    Armijo trials only for the materials still undecided (the next four
+    halvings, then the rest), and one forward + adjoint launch at the accepted
+    points; materials that accept no trial stall and drop out of the
+    launches."""
     import torch
     log(f"polish leg: {steps} steps x {T_TRIALS} trials on {wl.M} materials")
     b1 = D.Batch(wl.f_off, np.arange(wl.M + 1), wl.n_poles, wl.omega, er, ei)

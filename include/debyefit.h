@@ -513,10 +513,13 @@ int debye_da_run(const debye_plan *plan, const debye_batch *b, int64_t ld, const
  * direction is not a descent direction) is steepest descent scaled so that its
  * largest component is at most 1; a step with no acceptable trial leaves theta
  * unchanged; pairs with s.y <= 1e-300 are not stored (the history keeps its
- * older pairs).  The trials of a step are evaluated in two batched launches:
- * the full step (alpha = 1) of every material, then the remaining trials of
- * the materials whose full step failed (the result is the one a sequential
- * halving search returns).
+ * older pairs).  The trials of a step are evaluated in three batched
+ * launches: the full step (alpha = 1) of every material, the next four
+ * halvings of the materials whose full step failed, and the remaining trials
+ * of those still undecided (the result is the one a sequential halving search
+ * returns).  A step with no acceptable trial leaves point, gradient and
+ * history unchanged, so the material is left out of the later steps' launches
+ * (its next steps would reject the same trials).
  *
  * The polish context owns every buffer (history, trials, gradients and the two
  * evaluation plans); debye_polish_create is the set-up call that allocates.
@@ -525,7 +528,7 @@ int debye_da_run(const debye_plan *plan, const debye_batch *b, int64_t ld, const
  * work on `stream`: no allocation, no synchronisation, so a step can be
  * captured into a HIP graph.  Calls with one context must not overlap.
  *   debye_polish_begin:  cost and gradient at theta, history emptied.
- *   debye_polish_step:   one step (direction -> full steps -> remaining
+ *   debye_polish_step:   one step (direction -> full steps -> further
  *                        trials where needed -> selection -> gradient at the
  *                        accepted point -> history update);
  *                        cost_hist [M][steps+1] (may be NULL) receives the cost

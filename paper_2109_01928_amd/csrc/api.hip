@@ -1358,20 +1358,22 @@ int debye_da_run(const debye_plan *pc, const debye_batch *b, int64_t ld, const d
   return graph_leave(g, stream);
 }
 
-// ---- L-BFGS polish: a context that owns the workspace and the two plans
-// (one candidate per material for the gradient, max_trials per material for
-// the batched line search), so that the calls below only enqueue work
+// ---- L-BFGS polish: a context that owns the workspace and the plans (one
+// candidate per material, for the gradient and the full steps; ta and tb
+// trials per material, for the two later stages of the line search), so that
+// the calls below only enqueue work
+constexpr int32_t POLISH_STAGE_A = 4;   // halvings tried right after a failed full step
+
 struct debye_polish {
-  int32_t M = 0, max_poles = 0, mem = 0, max_trials = 0, steps = 0;
+  int32_t M = 0, max_poles = 0, mem = 0, max_trials = 0, steps = 0, ta = 0, tb = 0;
   int64_t ld = 0, n_freq = 0;
   double c1 = 0;
-  debye_plan *p1 = nullptr, *pT = nullptr;
+  debye_plan *p1 = nullptr, *pA = nullptr, *pB = nullptr;
   void *ws = nullptr;         // one allocation for every buffer below
-  int64_t *trial_off = nullptr;
-  double *grad, *S, *Y, *rho, *dir, *gd, *trial_theta, *trial_cost, *new_theta, *new_cost, *new_grad, *cost, *acc_cost,
-      *first_cost;
+  int64_t *off_a = nullptr, *off_b = nullptr;   // [M+1] candidate offsets of the two later stages
+  double *grad, *S, *Y, *rho, *dir, *gd, *trial_theta, *trial_cost, *new_theta, *new_cost, *new_grad, *cost, *acc_cost;
   int32_t *hist_n, *hist_head, *accepted, *done, *stalled;
-  int8_t *trial_status, *new_status, *first_status;
+  int8_t *trial_status, *new_status;
 };
 
 namespace {
@@ -1392,6 +1394,8 @@ dfit::LbfgsArgs polish_args(const debye_polish *pp, const debye_batch *b, double
   la.ld = pp->ld;
   la.mem = pp->mem;
   la.max_trials = pp->max_trials;
+  la.ta = pp->ta;
+  la.tb = pp->tb;
   la.c1 = pp->c1;
   la.lb = lb;
   la.ub = ub;
@@ -1409,8 +1413,6 @@ dfit::LbfgsArgs polish_args(const debye_polish *pp, const debye_batch *b, double
   la.trial_theta = pp->trial_theta;
   la.trial_cost = pp->trial_cost;
   la.trial_status = pp->trial_status;
-  la.first_cost = pp->first_cost;
-  la.first_status = pp->first_status;
   la.done = pp->done;
   la.stalled = pp->stalled;
   la.new_theta = pp->new_theta;
@@ -1439,16 +1441,20 @@ int debye_polish_create(const debye_batch *shape, const int64_t *f_off_host, con
                 DFIT_MAX_MEM);
   const int32_t M = shape->n_mat;
   const int T = lp.max_trials;
-  std::vector<int64_t> one(M + 1), trials(M + 1);
+  const int32_t ta = std::min(POLISH_STAGE_A, T - 1), tb = T - 1 - ta;
+  std::vector<int64_t> one(M + 1), offs_a(M + 1), offs_b(M + 1);
   for (int32_t m = 0; m <= M; ++m) {
     one[m] = m;
-    trials[m] = (int64_t)m * T;
+    offs_a[m] = (int64_t)m * ta;
+    offs_b[m] = (int64_t)m * tb;
   }
   debye_polish *pp = new debye_polish();
   pp->M = M;
   pp->max_poles = shape->max_poles;
   pp->mem = lp.mem;
   pp->max_trials = T;
+  pp->ta = ta;
+  pp->tb = tb;
   pp->steps = lp.steps;
   pp->c1 = lp.c1;
   pp->ld = ld;
@@ -1460,15 +1466,15 @@ int debye_polish_create(const debye_batch *shape, const int64_t *f_off_host, con
   const int64_t n1 = (int64_t)M * ld, nT = (int64_t)M * T;
   const size_t doubles = (size_t)(n1 /*grad*/ + 2 * (int64_t)M * lp.mem * ld /*S,Y*/ + (int64_t)M * lp.mem /*rho*/ +
                                   n1 /*dir*/ + M /*gd*/ + nT * ld /*trial theta*/ + nT /*trial cost*/ + n1 /*new theta*/ +
-                                  M /*new cost*/ + n1 /*new grad*/ + M /*cost*/ + M /*accepted cost*/ +
-                                  M /*first trials' cost*/);
-  const size_t bytes = (size_t)(M + 1) * 8 + doubles * 8 + (size_t)5 * M * 4 + (size_t)nT + (size_t)2 * M + 64;
+                                  M /*new cost*/ + n1 /*new grad*/ + M /*cost*/ + M /*accepted cost*/);
+  const size_t bytes = (size_t)2 * (M + 1) * 8 + doubles * 8 + (size_t)5 * M * 4 + (size_t)nT + (size_t)M + 64;
   if (hipMalloc(&pp->ws, bytes) != hipSuccess) {
     pp->ws = nullptr;
     return bail(fail(DEBYE_ENOMEM, "polish workspace allocation failed"));
   }
-  pp->trial_off = (int64_t *)pp->ws;
-  double *dp = (double *)(pp->trial_off + M + 1);
+  pp->off_a = (int64_t *)pp->ws;
+  pp->off_b = pp->off_a + M + 1;
+  double *dp = (double *)(pp->off_b + M + 1);
   auto take = [&](int64_t n) {
     double *r = dp;
     dp += n;
@@ -1487,7 +1493,6 @@ int debye_polish_create(const debye_batch *shape, const int64_t *f_off_host, con
   pp->new_grad = take(n1);
   pp->cost = take(M);
   pp->acc_cost = take(M);
-  pp->first_cost = take(M);
   int32_t *ip = (int32_t *)dp;
   pp->hist_n = ip;
   pp->hist_head = ip + M;
@@ -1496,15 +1501,22 @@ int debye_polish_create(const debye_batch *shape, const int64_t *f_off_host, con
   pp->stalled = ip + 4 * M;
   pp->trial_status = (int8_t *)(ip + 5 * M);
   pp->new_status = pp->trial_status + nT;
-  pp->first_status = pp->new_status + M;
-  if (hipMemcpy(pp->trial_off, trials.data(), (M + 1) * 8, hipMemcpyHostToDevice) != hipSuccess)
+  if (hipMemcpy(pp->off_a, offs_a.data(), (M + 1) * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pp->off_b, offs_b.data(), (M + 1) * 8, hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(DEBYE_EHIP, "polish: upload of the trial offsets failed"));
-  debye_batch bt = *shape;
-  bt.cand_off = pp->trial_off;
-  bt.n_cand = nT;
   std::vector<int64_t> f_h(f_off_host, f_off_host + M + 1);
   if ((rc = debye_plan_create(shape, f_h.data(), one.data(), n_poles_host, 0, &pp->p1))) return bail(rc);
-  if ((rc = debye_plan_create(&bt, f_h.data(), trials.data(), n_poles_host, 0, &pp->pT))) return bail(rc);
+  debye_batch bt = *shape;
+  if (ta > 0) {
+    bt.cand_off = pp->off_a;
+    bt.n_cand = (int64_t)M * ta;
+    if ((rc = debye_plan_create(&bt, f_h.data(), offs_a.data(), n_poles_host, 0, &pp->pA))) return bail(rc);
+  }
+  if (tb > 0) {
+    bt.cand_off = pp->off_b;
+    bt.n_cand = (int64_t)M * tb;
+    if ((rc = debye_plan_create(&bt, f_h.data(), offs_b.data(), n_poles_host, 0, &pp->pB))) return bail(rc);
+  }
   *out = pp;
   return DEBYE_OK;
 }
@@ -1512,7 +1524,8 @@ int debye_polish_create(const debye_batch *shape, const int64_t *f_off_host, con
 int debye_polish_destroy(debye_polish *pp) {
   if (!pp) return DEBYE_OK;
   debye_plan_destroy(pp->p1);
-  debye_plan_destroy(pp->pT);
+  debye_plan_destroy(pp->pA);
+  debye_plan_destroy(pp->pB);
   if (pp->ws) {
     (void)hipDeviceSynchronize();   // no work of the context may still read the workspace
     (void)hipFree(pp->ws);
@@ -1542,25 +1555,35 @@ int debye_polish_step(debye_polish *pp, const debye_batch *b, double *theta, con
     return fail(DEBYE_ERANGE, "step %d outside 0..%d", step, pp->steps - 1);
   dfit::LbfgsArgs la = polish_args(pp, b, theta, lb, ub, cost_hist);
   la.step = step;
-  debye_batch bt = *b;
-  bt.cand_off = pp->trial_off;
-  bt.n_cand = (int64_t)pp->M * pp->max_trials;
+  const int32_t M = pp->M;
+  const int64_t ld = pp->ld;
   hipError_t e = dfit::launch_lbfgs_direction(la, stream);
   if (e != hipSuccess) return hip_fail(e, "lbfgs direction");
-  // the full step of every material still moving (trial 0: rows m * max_trials
-  // of the trial array).  A material whose step found no acceptable trial is
+  // stage 0: the full step of every material still moving (rows 0 .. M-1 of
+  // the trial arrays).  A material whose step found no acceptable trial is
   // stalled for good: its point, gradient and history stay as they were, so
   // every later step would rebuild the same trials and reject them again.
-  if ((rc = fit_eval_impl(pp->p1, b, pp->trial_theta, pp->ld * pp->max_trials, damping, flags, pp->first_cost,
-                          nullptr, nullptr, pp->first_status, pp->stalled, stream)))
+  if ((rc = fit_eval_impl(pp->p1, b, pp->trial_theta, ld, damping, flags, pp->trial_cost, nullptr, nullptr,
+                          pp->trial_status, pp->stalled, stream)))
     return rc;
   if ((e = dfit::launch_lbfgs_first(la, stream)) != hipSuccess) return hip_fail(e, "lbfgs first trial");
-  if (pp->max_trials > 1) {
-    // the remaining trials, only for the materials the full step left undecided
-    if ((rc = fit_eval_impl(pp->pT, &bt, pp->trial_theta, pp->ld, damping, flags, pp->trial_cost, nullptr, nullptr,
-                            pp->trial_status, pp->done, stream)))
+  // stages A and B: the next ta halvings, then the rest, each only for the
+  // materials the earlier stages left undecided
+  debye_batch bt = *b;
+  int64_t row = M;
+  int32_t t_lo = 1;
+  for (int stage = 0; stage < 2; ++stage) {
+    const int32_t n = stage == 0 ? pp->ta : pp->tb;
+    if (n == 0) continue;
+    bt.cand_off = stage == 0 ? pp->off_a : pp->off_b;
+    bt.n_cand = (int64_t)M * n;
+    if ((rc = fit_eval_impl(stage == 0 ? pp->pA : pp->pB, &bt, pp->trial_theta + row * ld, ld, damping, flags,
+                            pp->trial_cost + row, nullptr, nullptr, pp->trial_status + row, pp->done, stream)))
       return rc;
-    if ((e = dfit::launch_lbfgs_select(la, stream)) != hipSuccess) return hip_fail(e, "lbfgs select");
+    if ((e = dfit::launch_lbfgs_select(la, t_lo, t_lo + n - 1, stream)) != hipSuccess)
+      return hip_fail(e, "lbfgs select");
+    row += (int64_t)M * n;
+    t_lo += n;
   }
   // cost and gradient at the accepted points (the stalled materials, which
   // accepted none, are left out)

@@ -201,12 +201,14 @@ struct LbfgsArgs {
   int32_t *hist_n, *hist_head;  // [M]
   double *dir;         // [M][ld]
   double *gd;          // [M] g.d of the chosen direction
+  // the trials of a step in three stages, rows of the trial arrays: the full
+  // step of material m at row m; trials 1 .. ta at M + m*ta + (t-1); trials
+  // ta+1 .. max_trials-1 at M + M*ta + m*tb + (t-1-ta), tb = max_trials-1-ta
+  int32_t ta, tb;
   double *trial_theta; // [M*max_trials][ld]
   const double *trial_cost;  // [M*max_trials]
   const int8_t *trial_status;
-  const double *first_cost;    // [M] cost of each material's first trial (full step)
-  const int8_t *first_status;  // [M]
-  int32_t *done;       // [M] step decided by the first trial (or skipped)
+  int32_t *done;       // [M] step decided (accepted a trial, or stalled)
   int32_t *stalled;    // [M] no acceptable trial at some step: the point never moves again
   double *new_theta;   // [M][ld] accepted point
   double *acc_cost;    // [M] cost of the accepted trial
@@ -218,7 +220,7 @@ struct LbfgsArgs {
 };
 hipError_t launch_lbfgs_direction(const LbfgsArgs &a, hipStream_t s);
 hipError_t launch_lbfgs_first(const LbfgsArgs &a, hipStream_t s);
-hipError_t launch_lbfgs_select(const LbfgsArgs &a, hipStream_t s);
+hipError_t launch_lbfgs_select(const LbfgsArgs &a, int32_t t_lo, int32_t t_hi, hipStream_t s);
 hipError_t launch_lbfgs_update(const LbfgsArgs &a, hipStream_t s);
 
 }  // namespace dfit

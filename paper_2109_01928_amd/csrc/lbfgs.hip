@@ -5,18 +5,26 @@
 // the projected displacement p, C(trial) <= C + c1 min(g.p, 0) (clamping can
 // make g.p positive; the cost is then not allowed to rise).  The accepted step
 // is the first trial (largest alpha) that passes, which is what a sequential
-// halving search returns.  The trials are evaluated in two batched cost
-// launches: the full step of every material first; then all further trials,
-// only for the materials whose full step failed (the others' waves exit at
-// once).  A step that accepts no trial leaves the point, gradient and history
-// as they were, so every later step would rebuild and reject the same trials:
-// such a material is marked stalled and left out of all later evaluations.
-// One thread per material.
+// halving search returns.  The trials are evaluated in three batched cost
+// launches: the full step of every material; then the next few halvings, only
+// for the materials whose full step failed; then the rest, only for those
+// still undecided (the waves of decided materials exit at once).  A step that
+// accepts no trial leaves the point, gradient and history as they were, so
+// every later step would rebuild and reject the same trials: such a material
+// is marked stalled and left out of all later evaluations.  One thread per
+// material.
 
 #include "common.hpp"
 #include "fit_eval.hpp"
 
 namespace dfit {
+
+// row of trial t of material m in the trial arrays (stage by stage)
+__device__ __forceinline__ int64_t trial_row(const LbfgsArgs &a, int m, int t) {
+  if (t == 0) return m;
+  if (t <= a.ta) return (int64_t)a.M + (int64_t)m * a.ta + (t - 1);
+  return (int64_t)a.M * (1 + a.ta) + (int64_t)m * a.tb + (t - 1 - a.ta);
+}
 
 __global__ __launch_bounds__(256) void lbfgs_direction_kernel(const LbfgsArgs a) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
@@ -94,7 +102,7 @@ __global__ __launch_bounds__(256) void lbfgs_direction_kernel(const LbfgsArgs a)
   const double lo = a.lb[m], hi = a.ub[m];
   double alpha_t = 1.0;
   for (int t = 0; t < a.max_trials; ++t) {
-    double *tt = a.trial_theta + ((int64_t)m * a.max_trials + t) * ld;
+    double *tt = a.trial_theta + trial_row(a, m, t) * ld;
     for (int i = 0; i < N; ++i) {
       const double v = th[i] + alpha_t * d[i];
       tt[i] = skip ? th[i] : (v < lo ? lo : (v > hi ? hi : v));
@@ -109,7 +117,7 @@ __device__ bool armijo_ok(const LbfgsArgs &a, int m, int t, double cost_t, int8_
   const int N = a.n_poles[m];
   const double *g = a.grad + (int64_t)m * a.ld;
   const double *th = a.theta + (int64_t)m * a.ld;
-  const double *tt = a.trial_theta + ((int64_t)m * a.max_trials + t) * a.ld;
+  const double *tt = a.trial_theta + trial_row(a, m, t) * a.ld;
   double gp = 0.0;
   for (int i = 0; i < N; ++i) gp += g[i] * (tt[i] - th[i]);
   return status_t == ST_OK && cost_t <= a.cost[m] + a.c1 * fmin(gp, 0.0);
@@ -120,7 +128,7 @@ __device__ void decide(const LbfgsArgs &a, int m, int pick, double c) {
   const int N = a.n_poles[m];
   a.accepted[m] = pick >= 0 ? 1 : 0;
   a.acc_cost[m] = pick >= 0 ? c : a.cost[m];
-  const double *src = pick >= 0 ? a.trial_theta + ((int64_t)m * a.max_trials + pick) * a.ld : a.theta + (int64_t)m * a.ld;
+  const double *src = pick >= 0 ? a.trial_theta + trial_row(a, m, pick) * a.ld : a.theta + (int64_t)m * a.ld;
   for (int i = 0; i < N; ++i) a.new_theta[(int64_t)m * a.ld + i] = src[i];
 }
 }  // namespace
@@ -139,8 +147,8 @@ __global__ __launch_bounds__(256) void lbfgs_first_kernel(const LbfgsArgs a) {
     a.stalled[m] = 1;
     return;
   }
-  if (armijo_ok(a, m, 0, a.first_cost[m], a.first_status[m])) {
-    decide(a, m, 0, a.first_cost[m]);
+  if (armijo_ok(a, m, 0, a.trial_cost[m], a.trial_status[m])) {
+    decide(a, m, 0, a.trial_cost[m]);
     a.done[m] = 1;
     return;
   }
@@ -151,22 +159,24 @@ __global__ __launch_bounds__(256) void lbfgs_first_kernel(const LbfgsArgs a) {
   }
 }
 
-// after the second launch: the first of the remaining trials that passes
-__global__ __launch_bounds__(256) void lbfgs_select_kernel(const LbfgsArgs a) {
+// after the launch of trials t_lo .. t_hi: the first of them that passes, for
+// the materials still undecided; after the last stage, no pass is a stall
+__global__ __launch_bounds__(256) void lbfgs_select_kernel(const LbfgsArgs a, int32_t t_lo, int32_t t_hi) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= a.M || a.done[m]) return;
-  int pick = -1;
-  double c = 0.0;
-  for (int t = 1; t < a.max_trials; ++t) {
-    const int64_t r = (int64_t)m * a.max_trials + t;
+  for (int t = t_lo; t <= t_hi; ++t) {
+    const int64_t r = trial_row(a, m, t);
     if (armijo_ok(a, m, t, a.trial_cost[r], a.trial_status[r])) {
-      pick = t;
-      c = a.trial_cost[r];
-      break;
+      decide(a, m, t, a.trial_cost[r]);
+      a.done[m] = 1;
+      return;
     }
   }
-  decide(a, m, pick, c);
-  if (pick < 0) a.stalled[m] = 1;
+  if (t_hi == a.max_trials - 1) {
+    decide(a, m, -1, 0.0);
+    a.done[m] = 1;
+    a.stalled[m] = 1;
+  }
 }
 
 __global__ __launch_bounds__(256) void lbfgs_update_kernel(const LbfgsArgs a) {
@@ -217,8 +227,8 @@ hipError_t launch_lbfgs_first(const LbfgsArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(lbfgs_first_kernel, grid_for(a.M), dim3(256), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_lbfgs_select(const LbfgsArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(lbfgs_select_kernel, grid_for(a.M), dim3(256), 0, s, a);
+hipError_t launch_lbfgs_select(const LbfgsArgs &a, int32_t t_lo, int32_t t_hi, hipStream_t s) {
+  hipLaunchKernelGGL(lbfgs_select_kernel, grid_for(a.M), dim3(256), 0, s, a, t_lo, t_hi);
   return hipGetLastError();
 }
 hipError_t launch_lbfgs_update(const LbfgsArgs &a, hipStream_t s) {
