@@ -317,8 +317,15 @@ __device__ __forceinline__ void chol_solve(const MAT &A, const double *uinv, VEC
 
 // The same factorisation and solves for a matrix in LDS (SP > 1): plain
 // loops, so that the compiler does not pull the whole matrix into registers.
-// Every lane of a candidate runs them on that candidate's region.
-__device__ __noinline__ bool lds_equilibrate_factor(int n, double *A, double *invd, double *uinv, double damping,
+// Every lane of a candidate runs them on that candidate's region.  The
+// pointers are typed as LDS (address space 3): through a generic pointer the
+// calls would read with flat loads, whose latency each step of these serial
+// recurrences waits for.  The inner sums are unrolled by four, so that their
+// loads are issued together (the additions keep their order).
+using lds_ptr = __attribute__((address_space(3))) double *;
+using lds_cptr = const __attribute__((address_space(3))) double *;
+
+__device__ __noinline__ bool lds_equilibrate_factor(int n, lds_ptr A, lds_ptr invd, lds_ptr uinv, double damping,
                                                     double tol) {
   bool ok = true;
   for (int i = 0; i < n; ++i) {
@@ -333,6 +340,7 @@ __device__ __noinline__ bool lds_equilibrate_factor(int n, double *A, double *in
   }
   for (int j = 0; j < n; ++j) {
     double s = A[tri(n, j, j)];
+#pragma unroll 4
     for (int l = 0; l < j; ++l) {
       const double u = A[tri(n, l, j)];
       s = __builtin_fma(-u, u, s);
@@ -344,6 +352,7 @@ __device__ __noinline__ bool lds_equilibrate_factor(int n, double *A, double *in
     A[tri(n, j, j)] = u;
     for (int k = j + 1; k < n; ++k) {
       double t = A[tri(n, j, k)];
+#pragma unroll 4
       for (int l = 0; l < j; ++l) t = __builtin_fma(-A[tri(n, l, j)], A[tri(n, l, k)], t);
       A[tri(n, j, k)] = t * ui;
     }
@@ -351,15 +360,17 @@ __device__ __noinline__ bool lds_equilibrate_factor(int n, double *A, double *in
   return ok;
 }
 
-__device__ __noinline__ void lds_chol_solve(int n, const double *A, const double *uinv, double *x) {
+__device__ __noinline__ void lds_chol_solve(int n, lds_cptr A, lds_cptr uinv, lds_ptr x) {
   for (int i = 0; i < n; ++i) {
     double s = x[i];
+#pragma unroll 4
     for (int l = 0; l < i; ++l) s = __builtin_fma(-A[tri(n, l, i)], x[l], s);
     x[i] = s * uinv[i];
   }
   for (int i = n - 1; i >= 0; --i) {
     double s = x[i];
     const int row = tri(n, i, i);
+#pragma unroll 4
     for (int l = i + 1; l < n; ++l) s = __builtin_fma(-A[row + (l - i)], x[l], s);
     x[i] = s * uinv[i];
   }
@@ -771,9 +782,9 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
       if (p1 < N) vb[p1] = bv[cI];
     }
     __syncthreads();
-    ok = lds_equilibrate_factor(N, A, invd, uinv, damping, tol);
+    ok = lds_equilibrate_factor(N, (lds_ptr)A, (lds_ptr)invd, (lds_ptr)uinv, damping, tol);
     for (int i = 0; i < N; ++i) vz[i] = vb[i] * invd[i];
-    lds_chol_solve(N, A, uinv, vz);
+    lds_chol_solve(N, (lds_cptr)A, (lds_cptr)uinv, (lds_ptr)vz);
     __syncthreads();
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) {
@@ -886,7 +897,7 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
         if (p < N) vw[p] = __builtin_fma(gv[cI], invd_own[cI], -damping * zt[cI]);
       }
       __syncthreads();
-      lds_chol_solve(N, A, uinv, vw);
+      lds_chol_solve(N, (lds_cptr)A, (lds_cptr)uinv, (lds_ptr)vw);
       __syncthreads();
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
@@ -1077,7 +1088,7 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
         if (p < N) vw[p] = mt[cI];
       }
       __syncthreads();
-      lds_chol_solve(N, A, uinv, vw);
+      lds_chol_solve(N, (lds_cptr)A, (lds_cptr)uinv, (lds_ptr)vw);
       __syncthreads();
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
