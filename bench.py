@@ -21,6 +21,9 @@ The JSON line also carries:
     kernel over the same 8.4M candidates;
   - fwd_no_refine_kernel_evals_per_s: the forward kernel without the
     refinement step (DEBYE_FLAG_NO_REFINE; not the tolerance of `value`);
+  - fwd_dd_refine_kernel_evals_per_s: the forward kernel with the refinement
+    step in double-double (DEBYE_FLAG_DD_REFINE), and in parity_sample_dd_refine
+    the parity sample's candidates evaluated that way, judged like the others;
   - polish: 50 L-BFGS steps (adjoint gradients, up to 30 Armijo trials) on
     every material's swarm best, timed once;
   - batched_vs_per_material: a shard of the materials fitted whole (all swarm
@@ -289,7 +292,8 @@ def main():
     if not args.no_extras:
         theta = (pop.x if pop is not None else sw.x)
         line["fwd_adjoint_kernel_evals_per_s"] = adjoint_rate(D, plan, bb, theta, stream)
-        line["fwd_no_refine_kernel_evals_per_s"] = no_refine_rate(D, plan, bb, theta, stream)
+        line["fwd_no_refine_kernel_evals_per_s"] = flagged_rate(D, plan, bb, theta, stream, D.FLAG_NO_REFINE)
+        line["fwd_dd_refine_kernel_evals_per_s"] = flagged_rate(D, plan, bb, theta, stream, D.FLAG_DD_REFINE)
         best = (pop.best_x if pop is not None else sw.gbest_x).clone()
         if args.polish_steps > 0:
             line["polish"] = polish_leg(D, wl, er, ei, best, lb, ub, args.polish_steps, stream)
@@ -297,7 +301,10 @@ def main():
             line["batched_vs_per_material"] = shard_comparison(D, W, wl, er, ei, args)
         del theta, best
     if not args.no_cpu_baseline:
-        line["cpu_baseline"], line["parity_sample"] = cpu_leg(D, W, wl, er, ei, plan, args.cpu_seconds)
+        line["cpu_baseline"], line["parity_sample"], dd = cpu_leg(D, W, wl, er, ei, plan, args.cpu_seconds,
+                                                                   dd_refine=not args.no_extras)
+        if dd is not None:
+            line["parity_sample_dd_refine"] = dd
         # counted evaluations: only those within the parity tolerance (sampled rate)
         ps = line["parity_sample"]
         line["value_raw"] = value
@@ -333,17 +340,18 @@ def adjoint_rate(D, plan, bb, theta, stream, reps=2):
     return bb.P * reps / (g0.elapsed_time(g1) * 1e-3)
 
 
-def no_refine_rate(D, plan, bb, theta, stream, reps=2):
-    """Forward kernel rate with DEBYE_FLAG_NO_REFINE (no refinement pass;
-    accuracy limited by the conditioning of the normal equations)."""
+def flagged_rate(D, plan, bb, theta, stream, flags, reps=2):
+    """Forward kernel rate under `flags`: DEBYE_FLAG_NO_REFINE (no refinement
+    pass; accuracy limited by the conditioning of the normal equations) or
+    DEBYE_FLAG_DD_REFINE (the refinement pass in double-double)."""
     import torch
-    log("forward kernel rate without the refinement step")
-    D.fit_eval(plan, bb, theta, flags=D.FLAG_NO_REFINE, want_weights=False)
+    log(f"forward kernel rate with flags {flags}")
+    D.fit_eval(plan, bb, theta, flags=flags, want_weights=False)
     torch.cuda.synchronize()
     g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     g0.record(stream)
     for _ in range(reps):
-        D.fit_eval(plan, bb, theta, flags=D.FLAG_NO_REFINE, want_weights=False)
+        D.fit_eval(plan, bb, theta, flags=flags, want_weights=False)
     g1.record(stream)
     torch.cuda.synchronize()
     return bb.P * reps / (g0.elapsed_time(g1) * 1e-3)
@@ -467,14 +475,15 @@ def shard_comparison(D, W, wl, er, ei, args):
     return out
 
 
-def cpu_leg(D, W, wl, er, ei, plan, seconds):
+def cpu_leg(D, W, wl, er, ei, plan, seconds, dd_refine=False):
     """The oracle on the host cores over a bounded sample of the workload (whole
     materials in order, the uniform initial candidates, until `seconds` of
     oracle time), and a parity check of the same candidates: the GPU evaluates
     the full batch in the timed launch configuration with the oracle's own
     targets in the sampled materials' segments, and each sampled cost is
     judged by oracle.judge_costs (within 1e-10 of the FP64 oracle, or of its
-    80-bit instance)."""
+    80-bit instance).  With dd_refine the same candidates are evaluated again
+    with DEBYE_FLAG_DD_REFINE and judged the same way."""
     import torch
 
     import oracle
@@ -529,9 +538,11 @@ def cpu_leg(D, W, wl, er, ei, plan, seconds):
     tgt_err = float(max(np.max(np.abs(er[:fe].cpu().numpy() - oer) / np.maximum(np.abs(oer), 1e-300)),
                         np.max(np.abs(ei[:fe].cpu().numpy() - oei) / np.maximum(np.abs(oei), 1e-300))))
     bg = D.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, gr, gi, er.device)
-    cg, _, _, stg = D.fit_eval(plan, bg, torch.tensor(theta, device=er.device), want_weights=False)
+    tg = torch.tensor(theta, device=er.device)
+    cg, _, _, stg = D.fit_eval(plan, bg, tg, want_weights=False)
     cg = cg.cpu().numpy()[:n]
-    del gr, gi, bg
+    cdd = D.fit_eval(plan, bg, tg, flags=D.FLAG_DD_REFINE, want_weights=False)[0].cpu().numpy()[:n] if dd_refine else None
+    del gr, gi, bg, tg
     per_m = np.array([np.sum(oer[wl.f_off[m]:wl.f_off[m + 1]] ** 2 + oei[wl.f_off[m]:wl.f_off[m + 1]] ** 2)
                       for m in range(done_m)])
     floor = 1e-12 * np.repeat(per_m, np.diff(wl.cand_off[:done_m + 1]))
@@ -544,10 +555,18 @@ def cpu_leg(D, W, wl, er, ei, plan, seconds):
            "value_1core": n1 / t1}
     parity = {"candidates": n, "max_cost_rel_err": float(rel.max()), "oracle_limited": judged["oracle_limited"],
               "failed": judged["failed"], "within_1e-10": int((rel <= 1e-10).sum()),
+              "max_err_vs_80bit_of_judged": judged["max_rel_80"],
               "status_ok": int(np.sum(stg.cpu().numpy()[:n] == 0)), "target_max_rel_err": tgt_err}
     if judged["over"]:
         parity["over"] = judged["over"][:8]
-    return cpu, parity
+    dd = None
+    if cdd is not None:
+        log(f"judging the {n} candidates with the double-double refinement")
+        rel_dd, jd = oracle.judge_costs(sub_batch(0, done_m, oer, oei), theta[:n], cdd, c64, floor, 1e-10)
+        dd = {"candidates": n, "max_cost_rel_err": float(rel_dd.max()), "oracle_limited": jd["oracle_limited"],
+              "failed": jd["failed"], "within_1e-10": int((rel_dd <= 1e-10).sum()),
+              "max_err_vs_80bit_of_judged": jd["max_rel_80"]}
+    return cpu, parity, dd
 
 
 if __name__ == "__main__":

@@ -63,7 +63,7 @@ enum {
 /* flags */
 enum {
   DEBYE_FLAG_NO_SIGN_FLIP = 1u, /* keep signed LS weights (w = z instead of |z|) */
-  DEBYE_FLAG_NO_REFINE = 2u     /* skip the refinement step (one corrected
+  DEBYE_FLAG_NO_REFINE = 2u,    /* skip the refinement step (one corrected
                                    semi-normal-equations pass, Sec. III-B's damped
                                    least squares solved to full accuracy): z is the
                                    damped Cholesky solution of the normal equations
@@ -76,6 +76,22 @@ enum {
                                    least-squares result for ill-conditioned
                                    candidates.  In debye_fit_eval_grad the
                                    gradient formula then holds only to that error. */
+  DEBYE_FLAG_DD_REFINE = 4u     /* the refinement step in double-double arithmetic
+                                   (relaxation times 10^theta, the basis, the
+                                   residual eps'' - I z and the sums I^T r to about
+                                   104 bits): the cost is then within about 1e-11 of
+                                   the exact least-squares result also on the rare
+                                   ill-conditioned candidates (a few in 10^6 of
+                                   random ones) where the FP64 refinement's basis
+                                   and residual roundings leave up to a few 1e-10.
+                                   Slower (the refinement pass costs about five
+                                   times the FP64 one: 2 to 3 times the forward
+                                   kernel's time).  Forward evaluations only
+                                   (debye_fit_eval and the optimisers' runs, which
+                                   then use one launch per pole-count bucket);
+                                   DEBYE_EINVAL together with DEBYE_FLAG_NO_REFINE,
+                                   in debye_fit_eval_grad, in the polish calls and
+                                   in debye_fit_auto with polish steps. */
 };
 
 /* material kinds for debye_material_eval (parameter rows of DEBYE_PARAM_STRIDE) */

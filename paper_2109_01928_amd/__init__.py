@@ -27,6 +27,7 @@ OK, EINVAL, ERANGE, EHIP, ENOMEM = 0, -1, -2, -3, -4
 ST_OK, ST_BADINPUT, ST_SINGULAR = 0, 1, 2
 FLAG_NO_SIGN_FLIP = 1
 FLAG_NO_REFINE = 2
+FLAG_DD_REFINE = 4
 PLAN_TARGET_GRAD = 1
 LAUNCH_AUTO, LAUNCH_BUCKETS, LAUNCH_PERSISTENT = 0, 1, 2
 MAX_POLES = 24

@@ -15,7 +15,7 @@ COMMON = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", f"-I{
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
 # per-file extra flags: the optimiser updates must be rounded operation by operation
 EXTRA = {"pso.hip": ["-ffp-contract=off"], "de.hip": ["-ffp-contract=off"], "da.hip": ["-ffp-contract=off"]}
-SOURCES = ["fit_ragged.hip", "fit_eval.hip", "fit_grad.hip", "material.hip", "pso.hip", "de.hip", "da.hip", "lbfgs.hip", "api.hip", "auto.hip",
+SOURCES = ["fit_ragged.hip", "fit_eval.hip", "fit_grad.hip", "fit_dd.hip", "material.hip", "pso.hip", "de.hip", "da.hip", "lbfgs.hip", "api.hip", "auto.hip",
            "noalloc.hip"]
 
 

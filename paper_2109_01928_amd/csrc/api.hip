@@ -315,13 +315,23 @@ int check_plan_batch(const debye_plan *p, const debye_batch *b, int64_t ld) {
 }
 
 static_assert((unsigned)DEBYE_FLAG_NO_SIGN_FLIP == (unsigned)dfit::FLAG_NO_SIGN_FLIP &&
-                  (unsigned)DEBYE_FLAG_NO_REFINE == (unsigned)dfit::FLAG_NO_REFINE,
+                  (unsigned)DEBYE_FLAG_NO_REFINE == (unsigned)dfit::FLAG_NO_REFINE &&
+                  (unsigned)DEBYE_FLAG_DD_REFINE == (unsigned)dfit::FLAG_DD_REFINE,
               "the kernels read the ABI's flag bits");
 
 int check_damping(double damping, uint32_t flags) {
   if (!(damping >= 0.0) || !std::isfinite(damping)) return fail(DEBYE_ERANGE, "damping must be finite and >= 0");
-  if (flags & ~(uint32_t)(DEBYE_FLAG_NO_SIGN_FLIP | DEBYE_FLAG_NO_REFINE))
+  if (flags & ~(uint32_t)(DEBYE_FLAG_NO_SIGN_FLIP | DEBYE_FLAG_NO_REFINE | DEBYE_FLAG_DD_REFINE))
     return fail(DEBYE_EINVAL, "unknown flag bits 0x%x", flags);
+  if ((flags & DEBYE_FLAG_NO_REFINE) && (flags & DEBYE_FLAG_DD_REFINE))
+    return fail(DEBYE_EINVAL, "DEBYE_FLAG_NO_REFINE and DEBYE_FLAG_DD_REFINE exclude each other");
+  return DEBYE_OK;
+}
+
+// the adjoint kernels and the polish have no double-double refinement
+int check_grad_flags(uint32_t flags) {
+  if (flags & DEBYE_FLAG_DD_REFINE)
+    return fail(DEBYE_EINVAL, "DEBYE_FLAG_DD_REFINE is for forward evaluations only");
   return DEBYE_OK;
 }
 
@@ -775,7 +785,7 @@ int fit_eval_impl(const debye_plan *p, const debye_batch *b, const double *log10
   if (rc) return rc;
   if ((rc = check_damping(damping, flags))) return rc;
   if (!log10_tau || !cost) return fail(DEBYE_EINVAL, "log10_tau and cost must not be NULL");
-  if (p->launch == DEBYE_LAUNCH_PERSISTENT && p->buckets.size() > 1) {
+  if (p->launch == DEBYE_LAUNCH_PERSISTENT && p->buckets.size() > 1 && !(flags & DEBYE_FLAG_DD_REFINE)) {
     // one launch over every bucket, on the caller's stream
     dfit::RaggedArgs r{};
     r.common = fit_args(p, p->buckets[0], b, log10_tau, ld, damping, flags);
@@ -855,6 +865,7 @@ int fit_eval_grad_check(const debye_plan *p, const debye_batch *b, const double 
   int rc = check_plan_batch(p, b, ld);
   if (rc) return rc;
   if ((rc = check_damping(damping, flags))) return rc;
+  if ((rc = check_grad_flags(flags))) return rc;
   if (!log10_tau || !cost) return fail(DEBYE_EINVAL, "log10_tau and cost must not be NULL");
   if ((grad_eps_re == nullptr) != (grad_eps_im == nullptr))
     return fail(DEBYE_EINVAL, "grad_eps_re and grad_eps_im must both be set or both be NULL");
@@ -1383,7 +1394,8 @@ int polish_check(const debye_polish *pp, const debye_batch *b, double damping, u
   if (rc) return rc;
   if (b->n_mat != pp->M || b->n_cand != pp->M || b->n_freq != pp->n_freq || b->max_poles != pp->max_poles)
     return fail(DEBYE_EINVAL, "batch does not match the polish context (one candidate per material)");
-  return check_damping(damping, flags);
+  if ((rc = check_damping(damping, flags))) return rc;
+  return check_grad_flags(flags);
 }
 
 dfit::LbfgsArgs polish_args(const debye_polish *pp, const debye_batch *b, double *theta, const double *lb,

@@ -13,7 +13,7 @@ constexpr double LN10 = 2.302585092994045684017991454684364208;
 constexpr double THETA_LIMIT = 30.0;  // |log10 tau| beyond this is rejected (status BADINPUT)
 
 enum { ST_OK = 0, ST_BADINPUT = 1, ST_SINGULAR = 2 };
-enum { FLAG_NO_SIGN_FLIP = 1u, FLAG_NO_REFINE = 2u };
+enum { FLAG_NO_SIGN_FLIP = 1u, FLAG_NO_REFINE = 2u, FLAG_DD_REFINE = 4u };
 
 // Reciprocal of a d whose reciprocal is a normal number (the callers pass d
 // in [2^-1012, 2^990]).  The hardware estimate r0 has a relative error e

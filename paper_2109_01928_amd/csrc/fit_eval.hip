@@ -83,7 +83,9 @@ using AllN = Table<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18
 int pole_split(int n) { return AllN::pole_split(n); }
 int lds_bytes_per_candidate(int n) { return AllN::lds(n); }
 hipError_t launch_fit(int n, const FitArgs &a, int64_t n_tiles, bool grad, bool uni, hipStream_t s) {
-  return grad ? launch_fit_grad(n, a, n_tiles, uni, s) : AllN::fit(n, a, n_tiles, uni, s);
+  if (grad) return launch_fit_grad(n, a, n_tiles, uni, s);
+  if (a.flags & FLAG_DD_REFINE) return launch_fit_dd(n, a, n_tiles, s);
+  return AllN::fit(n, a, n_tiles, uni, s);
 }
 hipError_t launch_target_grad(int n, const TargetGradArgs &a, int64_t max_f, int32_t n_mats, hipStream_t s) {
   return AllN::target(n, a, max_f, n_mats, s);

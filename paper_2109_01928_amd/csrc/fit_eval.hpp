@@ -68,6 +68,7 @@ int lds_bytes_per_candidate(int n_poles);
 // uni: every tile's active lanes belong to one material and the split is 1
 hipError_t launch_fit(int n_poles, const FitArgs &a, int64_t n_tiles, bool grad, bool uni, hipStream_t s);
 hipError_t launch_fit_grad(int n_poles, const FitArgs &a, int64_t n_tiles, bool uni, hipStream_t s);
+hipError_t launch_fit_dd(int n_poles, const FitArgs &a, int64_t n_tiles, hipStream_t s);
 hipError_t launch_target_grad(int n_poles, const TargetGradArgs &a, int64_t max_f, int32_t n_mats,
                               hipStream_t s);
 

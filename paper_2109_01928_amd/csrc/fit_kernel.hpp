@@ -109,6 +109,77 @@ __device__ __forceinline__ double freq_sum_dd(double hi, double lo, int sp, int 
 }
 
 // --------------------------------------------------------------------------
+// Double-double arithmetic for the extended-precision refinement
+// (FLAG_DD_REFINE).  A value is an unevaluated sum h + l.  TwoSum (Knuth)
+// gives the rounding error of a sum and the fused multiply-add that of a
+// product exactly, so sums and products of such pairs keep about 104 bits.
+// Contraction is switched off in these routines: a product that the compiler
+// fused into a later sum would no longer be the rounded product whose error
+// the next operation recovers.
+// --------------------------------------------------------------------------
+struct ddv {
+  double h, l;
+};
+__device__ __forceinline__ ddv two_sum(double a, double b) {
+#pragma clang fp contract(off)
+  const double s = a + b, bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+// valid when |a| >= |b| (or a == 0)
+__device__ __forceinline__ ddv quick_two_sum(double a, double b) {
+#pragma clang fp contract(off)
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ ddv dd_mul(ddv a, ddv b) {
+#pragma clang fp contract(off)
+  const double p = a.h * b.h;
+  const double e = __builtin_fma(a.h, b.l, __builtin_fma(a.l, b.h, __builtin_fma(a.h, b.h, -p)));
+  return quick_two_sum(p, e);
+}
+// sum of two pairs whose high parts do not cancel
+__device__ __forceinline__ ddv dd_add(ddv a, ddv b) {
+#pragma clang fp contract(off)
+  const ddv s = two_sum(a.h, b.h);
+  return quick_two_sum(s.h, s.l + (a.l + b.l));
+}
+
+// 10^t as a double-double, for |t| <= 30 (relative error near 2^-95).  The
+// double nearest 10^t is off by up to half an ulp, which moves the weights
+// of an ill-conditioned fit, and with them its cost, by more than the cost's
+// tolerance; the extended-precision refinement needs the relaxation times
+// to its own precision.  Steps: y = t ln 10 in double-double; y = n ln 2 + r
+// with n = rint(y / ln 2), |r| <= ln 2 / 2; e^r = (e^(r/256))^256, the inner
+// factor from its Taylor series to degree 9 (the first omitted term is below
+// 2^-117), the power by eight squarings; then the scale 2^n.
+__device__ __noinline__ ddv exp10_dd(double t) {
+#pragma clang fp contract(off)
+  constexpr double LN10_H = 0x1.26bb1bbb55516p+1, LN10_L = -0x1.f48ad494ea3e9p-53;
+  constexpr double LN2_H = 0x1.62e42fefa39efp-1, LN2_L = 0x1.abc9e3b39803fp-56;
+  const double yh = t * LN10_H;
+  const double yl = __builtin_fma(t, LN10_L, __builtin_fma(t, LN10_H, -yh));
+  const double n = rint(yh / LN2_H);
+  // r = y - n ln 2: n * LN2_H and its rounding error exactly, then the rest
+  const double ph = n * LN2_H;
+  const double pe = __builtin_fma(n, LN2_H, -ph);
+  ddv r = two_sum(yh, -ph);
+  r = quick_two_sum(r.h, r.l + ((yl - pe) - n * LN2_L));
+  r.h = ldexp(r.h, -8);
+  r.l = ldexp(r.l, -8);
+  // 1 + r (1 + r/2 (1 + r/3 ( ... (1 + r/9))))
+  ddv p = {1.0, 0.0};
+  for (int j = 9; j >= 1; --j) {
+    const double dj = (double)j;
+    const double qh = r.h / dj;
+    const double ql = (__builtin_fma(-qh, dj, r.h) + r.l) / dj;   // the remainder r.h - qh j is exact
+    p = dd_add({1.0, 0.0}, dd_mul({qh, ql}, p));
+  }
+  for (int s = 0; s < 8; ++s) p = dd_mul(p, p);
+  const int e = (int)n;
+  return {ldexp(p.h, e), ldexp(p.l, e)};
+}
+
+// --------------------------------------------------------------------------
 // Debye basis of the owned poles at one frequency: R = 1/(1+x^2), I = x R.
 // Every pass needs only R: with I = w tau R, the factor tau moves out of
 // every frequency sum (applied once per candidate) and w out of every pole
@@ -512,10 +583,12 @@ template <int N, int SP, bool GRAD, int UNI> constexpr int waves_per_simd() {
 //      the spectra are read with wave-uniform (scalar) loads;
 //   2: frequency split > 1: wave-uniform spectrum base, per-lane 32-bit
 //      byte offsets (one offset per point for the three arrays).
+// XR: the refinement pass in double-double (FLAG_DD_REFINE; forward only).
 // One work tile (one wavefront: the candidates the plan lists for it) of the
 // cost kernel for N poles; the kernels below call it for their tiles.
-template <int N, int SP, bool GRAD, int UNI>
+template <int N, int SP, bool GRAD, int UNI, bool XR = false>
 __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
+  static_assert(!(XR && GRAD), "the extended-precision refinement is a forward-kernel form");
   using S = Shape<N, SP>;
   constexpr int NB = S::NB, NV = S::NV, NG = S::NG, D = S::D;
   extern __shared__ double lds_all[];
@@ -802,14 +875,90 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
   // refinement with the residual products summed in extra precision).
   // FLAG_NO_REFINE skips it (the forward kernels skip the whole pass; the
   // adjoint still runs it for the column sums of R that its eps_inf needs).
-  const bool refine = !(a.flags & FLAG_NO_REFINE);
+  const bool refine = XR || !(a.flags & FLAG_NO_REFINE);
   double gv[NB], gl[NB];
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) {
     gv[cI] = 0.0;
     gl[cI] = 0.0;
   }
-  if (GRAD || refine) {
+  if constexpr (XR) {
+    // The same g = I^T (eps'' - I z) with every quantity that the rounding
+    // of the FP64 pass disturbs carried in double-double: the relaxation
+    // times, x = w tau, 1 + x^2, R = 1/(1 + x^2) and I = x R, the residual
+    // (its pole sum by TwoSum, the low parts added plainly) and the sums of
+    // I r (likewise).  Written with contraction off: every product whose
+    // rounding error is recovered must stay a separate rounded product.
+#pragma clang fp contract(off)
+    double th[NB], tl[NB];
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) {
+      const int p = q * NB + cI;
+      th[cI] = 0.0;   // padded poles: x = 0, so I = 0
+      tl[cI] = 0.0;
+      if (p < N && active) {
+        const double t = a.theta[c * a.ld + p];
+        const ddv v = exp10_dd(fabs(t) <= THETA_LIMIT ? t : 0.0);   // rejected candidates: any finite value
+        th[cI] = v.h;
+        tl[cI] = v.l;
+      }
+    }
+    if (fl < F) {
+      double wn = ld(om, fl), en = ld(epi, fl);
+      for (int64_t k = fl; k < F; k += SF) {
+        const double w = wn, ei = en;
+        const int64_t kn = k + SF < F ? k + SF : k;   // the next point, loaded one trip ahead
+        wn = ld(om, kn);
+        en = ld(epi, kn);
+        double Ih[NB], Il[NB];
+        double sh = 0.0, sl = 0.0;   // sum over the owned poles of z_i I_i
+#pragma unroll
+        for (int cI = 0; cI < NB; ++cI) {
+          const double xh = w * th[cI];
+          const double xl = __builtin_fma(w, tl[cI], __builtin_fma(w, th[cI], -xh));
+          const double qh = xh * xh;
+          const double ql = __builtin_fma(xh + xh, xl, __builtin_fma(xh, xh, -qh));
+          const ddv d = two_sum(1.0, qh);
+          const double dl = d.l + ql;
+          // R = r + rl: r within half an ulp of 1/d.h, then one correction
+          const double r = rcp_nr(d.h);
+          const double rl = r * __builtin_fma(-dl, r, __builtin_fma(-d.h, r, 1.0));
+          const double ih = xh * r;
+          Ih[cI] = ih;
+          Il[cI] = __builtin_fma(xh, rl, __builtin_fma(xl, r, __builtin_fma(xh, r, -ih)));
+          const double ph = zc[cI] * ih;
+          const double pl = __builtin_fma(zc[cI], Il[cI], __builtin_fma(zc[cI], ih, -ph));
+          const ddv s2 = two_sum(sh, ph);
+          sh = s2.h;
+          sl = sl + (s2.l + pl);
+        }
+        if constexpr (SP > 1) {
+          // over the candidate's pole lanes (TwoSum's error does not depend
+          // on the operand order: every lane ends with the same pair)
+          ddv s2 = two_sum(sh, dpp_quad<QP_SWAP1>(sh));
+          sl = (sl + dpp_quad<QP_SWAP1>(sl)) + s2.l;
+          sh = s2.h;
+          if constexpr (SP == 4) {
+            s2 = two_sum(sh, dpp_quad<QP_SWAP2>(sh));
+            sl = (sl + dpp_quad<QP_SWAP2>(sl)) + s2.l;
+            sh = s2.h;
+          }
+        }
+        ddv rr = two_sum(ei, -sh);
+        rr = two_sum(rr.h, rr.l - sl);
+#pragma unroll
+        for (int cI = 0; cI < NB; ++cI) {
+          const double gh = Ih[cI] * rr.h;
+          const double ge = __builtin_fma(Ih[cI], rr.l, __builtin_fma(Il[cI], rr.h, __builtin_fma(Ih[cI], rr.h, -gh)));
+          const ddv s2 = two_sum(gv[cI], gh);
+          gv[cI] = s2.h;
+          gl[cI] = gl[cI] + (s2.l + ge);
+        }
+      }
+    }
+#pragma unroll
+    for (int cI = 0; cI < NB; ++cI) gv[cI] = freq_sum_dd(gv[cI], gl[cI], SP, SL);
+  } else if (GRAD || refine) {
     // I z = w sum_i (tau_i s_i z_i) (R_i / s_i), and I^T r = tau s ((R / s)^T (w r))
     double zs[NB];
 #pragma unroll
@@ -1203,6 +1352,16 @@ void fit_kernel(const FitArgs a) {
   fit_tile<N, SP, GRAD, UNI>(a, a.xcd_off[xcd] + j);
 }
 
+// The forward kernel with the refinement pass in double-double, general tiles.
+template <int N, int SP>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_simd<N, SP, false, 0>())))
+void fit_dd_kernel(const FitArgs a) {
+  const int xcd = blockIdx.x & 7;
+  const int64_t j = blockIdx.x >> 3;
+  if (j >= a.xcd_off[xcd + 1] - a.xcd_off[xcd]) return;
+  fit_tile<N, SP, false, 0, true>(a, a.xcd_off[xcd] + j);
+}
+
 // Pole split by pole count, measured per bucket on the ragged workload (each
 // pole count alone, autotuned frequency split): one lane per candidate up to
 // N = 11 (at N = 9..11 its register spills cost less than the DPP traffic and
@@ -1210,6 +1369,14 @@ void fit_kernel(const FitArgs a) {
 // to N = 16 (N = 13..16 pad to 16 on four lanes), four above (two lanes
 // spill the adjoint heavily at N = 17, 18).
 constexpr int pole_split_for(int n) { return n <= 11 ? 1 : (n <= 16 ? 2 : 4); }
+
+// Blocks of a cost-kernel grid: eight times the longest of the 8 XCD tile
+// lists (block b runs tile b / 8 of XCD b % 8's list).
+inline unsigned fit_grid_blocks(const FitArgs &a) {
+  int64_t longest = 0;
+  for (int x = 0; x < 8; ++x) longest = a.xcd_off[x + 1] - a.xcd_off[x] > longest ? a.xcd_off[x + 1] - a.xcd_off[x] : longest;
+  return (unsigned)(longest * 8);
+}
 
 // Launch of the cost kernel for N poles: the adjoint (GRAD) or the forward
 // kernel, in the uniform-tile form the plan found (split 1: scalar spectrum
@@ -1220,16 +1387,27 @@ template <int N, bool GRAD> hipError_t launch_fit_variant(const FitArgs &a, int6
   const size_t lds = (size_t)Shape<N, SP>::LDS_DOUBLES * 8 * a.cand_per_wave;
   FitArgs b = a;
   b.n_tiles = n_tiles;
-  int64_t longest = 0;
-  for (int x = 0; x < 8; ++x) longest = a.xcd_off[x + 1] - a.xcd_off[x] > longest ? a.xcd_off[x + 1] - a.xcd_off[x] : longest;
-  if (longest == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)(longest * 8);
+  const unsigned blocks = fit_grid_blocks(a);
+  if (blocks == 0) return hipSuccess;
   if (uni && a.freq_split == 1)
     hipLaunchKernelGGL((fit_kernel<N, SP, GRAD, 1>), dim3(blocks), dim3(64), lds, s, b);
   else if (uni)
     hipLaunchKernelGGL((fit_kernel<N, SP, GRAD, 2>), dim3(blocks), dim3(64), lds, s, b);
   else
     hipLaunchKernelGGL((fit_kernel<N, SP, GRAD, 0>), dim3(blocks), dim3(64), lds, s, b);
+  return hipGetLastError();
+}
+
+// The forward kernel with the extended-precision refinement: the general
+// tile form only (it serves uniform tiles too).
+template <int N> hipError_t launch_fit_dd_variant(const FitArgs &a, int64_t n_tiles, hipStream_t s) {
+  constexpr int SP = pole_split_for(N);
+  const size_t lds = (size_t)Shape<N, SP>::LDS_DOUBLES * 8 * a.cand_per_wave;
+  FitArgs b = a;
+  b.n_tiles = n_tiles;
+  const unsigned blocks = fit_grid_blocks(a);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((fit_dd_kernel<N, SP>), dim3(blocks), dim3(64), lds, s, b);
   return hipGetLastError();
 }
 

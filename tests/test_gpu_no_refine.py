@@ -130,4 +130,4 @@ def test_no_refine_adjoint_and_flag_check(D, orc):
     assert rel.max() <= 1e-10, rel.max()
     assert not torch.equal(c_fwd, c_ref)   # the refinement changes the result
     with pytest.raises(D.DebyeError):
-        D.fit_eval(plan, b, th, damping=DAMP, flags=4)
+        D.fit_eval(plan, b, th, damping=DAMP, flags=8)

@@ -61,7 +61,10 @@ def _domain_split(orc, ob, theta, c_gpu, ost, edge, damping, flags, floor, tag):
     return assert_mask
 
 
-def _check_eval(D, orc, wl, theta, damping=1e-8, flags=0, split=None, tag="", edge=()):
+def _check_eval(D, orc, wl, theta, damping=1e-8, flags=0, split=None, tag="", edge=(), gpu_flags=0):
+    """The GPU evaluation under flags | gpu_flags (gpu_flags: flags that change
+    only how accurately the same result is computed) against the oracle's
+    under flags."""
     import torch
     er, ei = targets_oracle(orc, wl)
     ob = orc.Batch(wl.f_off, wl.cand_off, wl.n_poles, wl.omega, er, ei)
@@ -70,10 +73,10 @@ def _check_eval(D, orc, wl, theta, damping=1e-8, flags=0, split=None, tag="", ed
     plan = D.Plan(b)
     th = torch.tensor(theta, device="cuda")
     if split == "tune":
-        plan.autotune(b, th, damping=damping, flags=flags, reps=1)
+        plan.autotune(b, th, damping=damping, flags=flags | gpu_flags, reps=1)
     elif split:
         plan.set_freq_split(split)
-    c, w, e, st = D.fit_eval(plan, b, th, damping=damping, flags=flags)
+    c, w, e, st = D.fit_eval(plan, b, th, damping=damping, flags=flags | gpu_flags)
     torch.cuda.synchronize()
     c, w, e, st = (t.cpu().numpy() for t in (c, w, e, st))
     print(f"[{tag}] {wl.name} split={split} plan={plan.info()}", flush=True)
@@ -200,6 +203,29 @@ def test_cost_parity_every_pole_count(D, orc, N):
     sp = D.Plan(_gpu_batch(D, wl, *targets_oracle(orc, wl))).info()[0]["pole_split"]
     for split in (None, 1, 4, 64 // sp):
         _check_eval(D, orc, wl, theta, split=split, tag=f"N{N}")
+
+
+@pytest.mark.parametrize("N", list(range(1, 25)))
+def test_dd_refine_parity_every_pole_count(D, orc, N):
+    """DEBYE_FLAG_DD_REFINE on the same batches (its kernels take the general
+    tile form for every tile), at the automatic and the widest split."""
+    wl = small_uniform(3, 173, N, 70, seed=100 + N)
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=N)
+    sp = D.Plan(_gpu_batch(D, wl, *targets_oracle(orc, wl))).info()[0]["pole_split"]
+    for split in (None, 64 // sp):
+        _check_eval(D, orc, wl, theta, split=split, tag=f"dd N{N}", gpu_flags=D.FLAG_DD_REFINE)
+
+
+@pytest.mark.parametrize("N", [8, 12, 20])
+def test_dd_refine_parity_extreme_relaxation_times(D, orc, N):
+    """The double-double basis at the ends of the admissible range: poles
+    spread over 60 decades, w tau up to 6e19, poles far above the band."""
+    wl = small_uniform(2, 200, N, 64, seed=40 + N)
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=N)
+    theta[3, :N] = np.linspace(-30.0, 30.0, N)
+    theta[70, :N] = np.linspace(6.0, 9.0, N)
+    theta[71, :N] = np.linspace(-29.0, -26.0, N)
+    _check_eval(D, orc, wl, theta, tag=f"dd extreme N{N}", edge=(3, 70, 71), gpu_flags=D.FLAG_DD_REFINE)
 
 
 @pytest.mark.parametrize("N", [6, 12, 20])
