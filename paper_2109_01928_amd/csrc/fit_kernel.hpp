@@ -386,64 +386,79 @@ __device__ __forceinline__ void chol_solve(const MAT &A, const double *uinv, VEC
   }
 }
 
-// The same factorisation and solves for a matrix in LDS (SP > 1): plain
-// loops, so that the compiler does not pull the whole matrix into registers.
-// Every lane of a candidate runs them on that candidate's region.  The
-// pointers are typed as LDS (address space 3): through a generic pointer the
-// calls would read with flat loads, whose latency each step of these serial
-// recurrences waits for.  The inner sums are unrolled by four, so that their
-// loads are issued together (the additions keep their order).
+// The same factorisation and solves for a matrix in LDS (SP > 1).  Every
+// lane of a candidate runs them on that candidate's region.  The pointers are
+// typed as LDS (address space 3): through a generic pointer the calls would
+// read with flat loads, whose latency each step of these serial recurrences
+// waits for.  The upper triangle is packed by columns (element (i, j), i <= j,
+// at j (j + 1) / 2 + i), so that every inner sum of the factorisation and of
+// the forward solve reads consecutive elements: one base address and
+// immediate offsets, no per-term address arithmetic.  Those sums are unrolled
+// by four (their loads issued together, the additions in their order); the
+// backward solve is unrolled whole (all its addresses are constants).  The
+// operations and their order are those of the register form above.
 using lds_ptr = __attribute__((address_space(3))) double *;
 using lds_cptr = const __attribute__((address_space(3))) double *;
 
-__device__ __noinline__ bool lds_equilibrate_factor(int n, lds_ptr A, lds_ptr invd, lds_ptr uinv, double damping,
+constexpr __host__ __device__ int tcol(int i, int j) { return j * (j + 1) / 2 + i; }
+
+template <int N>
+__device__ __noinline__ bool lds_equilibrate_factor(lds_ptr A, lds_ptr invd, lds_ptr uinv, double damping,
                                                     double tol) {
   bool ok = true;
-  for (int i = 0; i < n; ++i) {
-    const double g = A[tri(n, i, i)];
+  double dv[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double g = A[tcol(i, i)];
     ok = ok && (g > 0.0) && (g < INFINITY);
-    invd[i] = 1.0 / sqrt(g);
+    dv[i] = 1.0 / sqrt(g);
+    invd[i] = dv[i];
   }
-  for (int i = 0; i < n; ++i) {
-    const int row = tri(n, i, i);
-    for (int j = i + 1; j < n; ++j) A[row + (j - i)] = A[row + (j - i)] * invd[i] * invd[j];
-    A[row] = 1.0 + damping;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+#pragma unroll
+    for (int i = 0; i < j; ++i) A[tcol(i, j)] = A[tcol(i, j)] * dv[i] * dv[j];
+    A[tcol(j, j)] = 1.0 + damping;
   }
-  for (int j = 0; j < n; ++j) {
-    double s = A[tri(n, j, j)];
+  for (int j = 0; j < N; ++j) {
+    const lds_ptr cj = A + tcol(0, j);
+    double s = cj[j];
 #pragma unroll 4
-    for (int l = 0; l < j; ++l) {
-      const double u = A[tri(n, l, j)];
-      s = __builtin_fma(-u, u, s);
-    }
+    for (int l = 0; l < j; ++l) s = __builtin_fma(-cj[l], cj[l], s);
     ok = ok && (s > tol);
     const double u = sqrt(s);
     const double ui = 1.0 / u;
     uinv[j] = ui;
-    A[tri(n, j, j)] = u;
-    for (int k = j + 1; k < n; ++k) {
-      double t = A[tri(n, j, k)];
+    cj[j] = u;
+    for (int k = j + 1; k < N; ++k) {
+      const lds_ptr ck = A + tcol(0, k);
+      double t = ck[j];
 #pragma unroll 4
-      for (int l = 0; l < j; ++l) t = __builtin_fma(-A[tri(n, l, j)], A[tri(n, l, k)], t);
-      A[tri(n, j, k)] = t * ui;
+      for (int l = 0; l < j; ++l) t = __builtin_fma(-cj[l], ck[l], t);
+      ck[j] = t * ui;
     }
   }
   return ok;
 }
 
-__device__ __noinline__ void lds_chol_solve(int n, lds_cptr A, lds_cptr uinv, lds_ptr x) {
-  for (int i = 0; i < n; ++i) {
+template <int N> __device__ __noinline__ void lds_chol_solve(lds_cptr A, lds_cptr uinv, lds_ptr x) {
+  double xv[N];
+  for (int i = 0; i < N; ++i) {
+    const lds_cptr ci = A + tcol(0, i);
     double s = x[i];
 #pragma unroll 4
-    for (int l = 0; l < i; ++l) s = __builtin_fma(-A[tri(n, l, i)], x[l], s);
+    for (int l = 0; l < i; ++l) s = __builtin_fma(-ci[l], x[l], s);
     x[i] = s * uinv[i];
   }
-  for (int i = n - 1; i >= 0; --i) {
-    double s = x[i];
-    const int row = tri(n, i, i);
-#pragma unroll 4
-    for (int l = i + 1; l < n; ++l) s = __builtin_fma(-A[row + (l - i)], x[l], s);
-    x[i] = s * uinv[i];
+#pragma unroll
+  for (int i = 0; i < N; ++i) xv[i] = x[i];
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double s = xv[i];
+#pragma unroll
+    for (int l = i + 1; l < N; ++l) s = __builtin_fma(-A[tcol(i, l)], xv[l], s);
+    xv[i] = s * uinv[i];
+    x[i] = xv[i];
   }
 }
 
@@ -849,15 +864,15 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
         if (p2 >= S::NP) p2 -= S::NP;
         if (p1 < N && p2 < N) {
           const int i = p1 < p2 ? p1 : p2, j = p1 < p2 ? p2 : p1;
-          A[tri(N, i, j)] = G[cI * (D + 1) + d];
+          A[tcol(i, j)] = G[cI * (D + 1) + d];
         }
       }
       if (p1 < N) vb[p1] = bv[cI];
     }
     __syncthreads();
-    ok = lds_equilibrate_factor(N, (lds_ptr)A, (lds_ptr)invd, (lds_ptr)uinv, damping, tol);
+    ok = lds_equilibrate_factor<N>((lds_ptr)A, (lds_ptr)invd, (lds_ptr)uinv, damping, tol);
     for (int i = 0; i < N; ++i) vz[i] = vb[i] * invd[i];
-    lds_chol_solve(N, (lds_cptr)A, (lds_cptr)uinv, (lds_ptr)vz);
+    lds_chol_solve<N>((lds_cptr)A, (lds_cptr)uinv, (lds_ptr)vz);
     __syncthreads();
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) {
@@ -1046,7 +1061,7 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
         if (p < N) vw[p] = __builtin_fma(gv[cI], invd_own[cI], -damping * zt[cI]);
       }
       __syncthreads();
-      lds_chol_solve(N, (lds_cptr)A, (lds_cptr)uinv, (lds_ptr)vw);
+      lds_chol_solve<N>((lds_cptr)A, (lds_cptr)uinv, (lds_ptr)vw);
       __syncthreads();
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
@@ -1237,7 +1252,7 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
         if (p < N) vw[p] = mt[cI];
       }
       __syncthreads();
-      lds_chol_solve(N, (lds_cptr)A, (lds_cptr)uinv, (lds_ptr)vw);
+      lds_chol_solve<N>((lds_cptr)A, (lds_cptr)uinv, (lds_ptr)vw);
       __syncthreads();
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
