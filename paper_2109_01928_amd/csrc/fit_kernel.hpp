@@ -82,6 +82,25 @@ __device__ __forceinline__ double freq_sum(double v, int sp, int s_lanes) {
   return v;
 }
 
+// freq_sum of K values at once.  Each step's exchanges go through the LDS
+// crossbar; issued eight at a time, they wait for it once per eight values
+// instead of once per value (value by value, the additions and so the
+// results are those of freq_sum).
+template <int K> __device__ __forceinline__ void freq_sum_n(double *v, int sp, int s_lanes) {
+  for (int m = sp; m < s_lanes; m <<= 1) {
+#pragma unroll
+    for (int e0 = 0; e0 < K; e0 += 8) {
+      double o[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (e0 + e < K) o[e] = __shfl_xor(v[e0 + e], m, WAVE);
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (e0 + e < K) v[e0 + e] += o[e];
+    }
+  }
+}
+
 // Compensated accumulation sum += a * b (Kahan's summation with the running
 // correction c folded into the product by a fused multiply-add): the error of
 // a length-F sum stays at a few units of roundoff of the terms' magnitude
@@ -93,19 +112,32 @@ __device__ __forceinline__ void kahan_fma_acc(double &sum, double &c, double a, 
   sum = t;
 }
 
-// xor-butterfly of a double-double over the SF frequency lanes; TwoSum's
-// error term does not depend on the operand order, so all lanes end with the
-// same bits
-__device__ __forceinline__ double freq_sum_dd(double hi, double lo, int sp, int s_lanes) {
+// xor-butterfly of K double-doubles (hi[e] + lo_in[e]) over the SF frequency
+// lanes, the exchanges issued together as in freq_sum_n; hi[e] receives the
+// sum rounded to a double.  TwoSum's error term does not depend on the
+// operand order, so all lanes end with the same bits.
+template <int K> __device__ __forceinline__ void freq_sum_dd_n(double *hi, const double *lo_in, int sp, int s_lanes) {
+  double lo[K];
+#pragma unroll
+  for (int e = 0; e < K; ++e) lo[e] = lo_in[e];
   for (int m = sp; m < s_lanes; m <<= 1) {
-    const double oh = __shfl_xor(hi, m, WAVE), ol = __shfl_xor(lo, m, WAVE);
-    const double s = hi + oh;
-    const double bv = s - hi;
-    const double se = (hi - (s - bv)) + (oh - bv);
-    hi = s;
-    lo = (lo + ol) + se;
+    double oh[K], ol[K];
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+      oh[e] = __shfl_xor(hi[e], m, WAVE);
+      ol[e] = __shfl_xor(lo[e], m, WAVE);
+    }
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+      const double s = hi[e] + oh[e];
+      const double bv = s - hi[e];
+      const double se = (hi[e] - (s - bv)) + (oh[e] - bv);
+      hi[e] = s;
+      lo[e] = (lo[e] + ol[e]) + se;
+    }
   }
-  return hi + lo;
+#pragma unroll
+  for (int e = 0; e < K; ++e) hi[e] = hi[e] + lo[e];
 }
 
 // --------------------------------------------------------------------------
@@ -796,8 +828,7 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
     }
     if (k < F) gram_point(wa_n, era_n, eia_n);
   }
-#pragma unroll
-  for (int e = 0; e < NG; ++e) G[e] = freq_sum(G[e], SP, SL);
+  freq_sum_n<NG>(G, SP, SL);
   if constexpr (SP > 1) {
     double tv[NV];
 #pragma unroll
@@ -812,9 +843,10 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
 #pragma unroll
       for (int j = i; j < N; ++j) G[tri(N, i, j)] *= ts[i] * ts[j];
   }
+  freq_sum_n<NB>(bv, SP, SL);
 #pragma unroll
   for (int cI = 0; cI < NB; ++cI) {
-    bv[cI] = freq_sum(bv[cI], SP, SL) * ts[cI];
+    bv[cI] = bv[cI] * ts[cI];
     bad = bad || !(fabs(bv[cI]) < INFINITY);
   }
   sum_er = freq_sum(sum_er, SP, SL);
@@ -971,8 +1003,7 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
         }
       }
     }
-#pragma unroll
-    for (int cI = 0; cI < NB; ++cI) gv[cI] = freq_sum_dd(gv[cI], gl[cI], SP, SL);
+    freq_sum_dd_n<NB>(gv, gl, SP, SL);
   } else if (GRAD || refine) {
     // I z = w sum_i (tau_i s_i z_i) (R_i / s_i), and I^T r = tau s ((R / s)^T (w r))
     double zs[NB];
@@ -1034,10 +1065,17 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], 1.0, pb[cI]);
     }
+    {
+      double ngl[NB];
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) ngl[cI] = -gl[cI];
+      freq_sum_dd_n<NB>(gv, ngl, SP, SL);
+    }
+    if constexpr (GRAD) freq_sum_n<NB>(Sv, SP, SL);
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) {
-      gv[cI] = freq_sum_dd(gv[cI], -gl[cI], SP, SL) * ts[cI];
-      if constexpr (GRAD) Sv[cI] = freq_sum(Sv[cI], SP, SL) * pole_scale<NB>(sq, cI);
+      gv[cI] = gv[cI] * ts[cI];
+      if constexpr (GRAD) Sv[cI] = Sv[cI] * pole_scale<NB>(sq, cI);
     }
   }
 
@@ -1233,9 +1271,11 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
     // ---- adjoint: mu = M^-1 (s o g_w), M = D A D
     if (a.grad_cost) gc = active ? a.grad_cost[c] : 0.0;
     double mt[NB], mu[NB];
+    freq_sum_n<NB>(gw2, SP, SL);
+    freq_sum_n<NB>(gw, SP, SL);
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) {
-      gw[cI] = -2.0 * pole_scale<NB>(sq, cI) * __builtin_fma(tau_of(cI), freq_sum(gw2[cI], SP, SL), freq_sum(gw[cI], SP, SL));
+      gw[cI] = -2.0 * pole_scale<NB>(sq, cI) * __builtin_fma(tau_of(cI), gw2[cI], gw[cI]);
       const double s = (flip && zc[cI] < 0.0) ? -1.0 : 1.0;
       mt[cI] = s * gw[cI] * invd_own[cI];
     }
@@ -1317,12 +1357,16 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
         }
       }
     }
+    freq_sum_n<NB>(T1, SP, SL);
+    freq_sum_n<NB>(T2, SP, SL);
+    freq_sum_n<NB>(T3, SP, SL);
+    freq_sum_n<NB>(T4, SP, SL);
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) {
-      T1[cI] = LN10 * freq_sum(T1[cI], SP, SL);
-      T2[cI] = LN10 * freq_sum(T2[cI], SP, SL);
-      T3[cI] = LN10 * freq_sum(T3[cI], SP, SL);
-      T4[cI] = LN10 * freq_sum(T4[cI], SP, SL);
+      T1[cI] = LN10 * T1[cI];
+      T2[cI] = LN10 * T2[cI];
+      T3[cI] = LN10 * T3[cI];
+      T4[cI] = LN10 * T4[cI];
     }
     if (writer) {
       // padding entries of the row (poles beyond this material's count) are 0
