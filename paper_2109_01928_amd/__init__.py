@@ -565,6 +565,8 @@ class DebyeCost(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, theta, eps_re, eps_im, plan, batch, damping=DEFAULT_DAMPING, flags=0):
+        if flags & FLAG_DD_REFINE:
+            raise ValueError("FLAG_DD_REFINE is a forward-evaluation flag: the adjoint has no double-double form")
         b = batch.with_targets(eps_re.detach(), eps_im.detach())
         cost = fit_eval(plan, b, theta.detach().contiguous(), damping, flags, want_weights=False)[0]
         ctx.save_for_backward(theta, eps_re, eps_im)

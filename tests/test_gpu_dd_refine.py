@@ -12,8 +12,8 @@ the flag.  The checks:
   - a persistent-launch plan evaluates the flag with per-bucket launches:
     results bit-identical to a per-bucket plan's;
   - a swarm run with the flag records the flag's costs;
-  - the flag's exclusions: together with DEBYE_FLAG_NO_REFINE, in the adjoint
-    and in the polish."""
+  - the flag's exclusions: together with DEBYE_FLAG_NO_REFINE, in the adjoint,
+    in the polish and in the autograd function."""
 import numpy as np
 import pytest
 
@@ -135,6 +135,8 @@ def test_dd_refine_flag_rules(D, orc):
     ub = torch.tensor(wl.ub, device="cuda")
     with pytest.raises(D.DebyeError):
         pol.run(b1, best, lb, ub, flags=D.FLAG_DD_REFINE)
+    with pytest.raises(ValueError):
+        D.DebyeCost.apply(th.clone().requires_grad_(True), b.eps_re, b.eps_im, plan, b, 1e-8, D.FLAG_DD_REFINE)
     # the flag with the sign flip off is accepted
     D.fit_eval(plan, b, th, flags=D.FLAG_DD_REFINE | D.FLAG_NO_SIGN_FLIP)
     torch.cuda.synchronize()
