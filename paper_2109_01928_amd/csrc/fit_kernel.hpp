@@ -211,6 +211,25 @@ __device__ __noinline__ ddv exp10_dd(double t) {
   return {ldexp(p.h, e), ldexp(p.l, e)};
 }
 
+// The Debye basis term I = x / (1 + x^2), x = w tau, as a double-double from
+// tau = th + tl: x by TwoProduct, x^2 likewise (its cross term 2 xh xl added
+// to the error), 1 + x^2 by TwoSum, R = 1 / (1 + x^2) from a reciprocal of
+// the high part within half an ulp and one correction r (1 + e), e = 1 - d r
+// formed with fused operations, then I = x R.
+__device__ __forceinline__ ddv dd_debye_I(double w, double th, double tl) {
+#pragma clang fp contract(off)
+  const double xh = w * th;
+  const double xl = __builtin_fma(w, tl, __builtin_fma(w, th, -xh));
+  const double qh = xh * xh;
+  const double ql = __builtin_fma(xh + xh, xl, __builtin_fma(xh, xh, -qh));
+  const ddv d = two_sum(1.0, qh);
+  const double dl = d.l + ql;
+  const double r = rcp_nr(d.h);
+  const double rl = r * __builtin_fma(-dl, r, __builtin_fma(-d.h, r, 1.0));
+  const double ih = xh * r;
+  return {ih, __builtin_fma(xh, rl, __builtin_fma(xl, r, __builtin_fma(xh, r, -ih)))};
+}
+
 // --------------------------------------------------------------------------
 // Debye basis of the owned poles at one frequency: R = 1/(1+x^2), I = x R.
 // Every pass needs only R: with I = w tau R, the factor tau moves out of
@@ -961,18 +980,10 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
         double sh = 0.0, sl = 0.0;   // sum over the owned poles of z_i I_i
 #pragma unroll
         for (int cI = 0; cI < NB; ++cI) {
-          const double xh = w * th[cI];
-          const double xl = __builtin_fma(w, tl[cI], __builtin_fma(w, th[cI], -xh));
-          const double qh = xh * xh;
-          const double ql = __builtin_fma(xh + xh, xl, __builtin_fma(xh, xh, -qh));
-          const ddv d = two_sum(1.0, qh);
-          const double dl = d.l + ql;
-          // R = r + rl: r within half an ulp of 1/d.h, then one correction
-          const double r = rcp_nr(d.h);
-          const double rl = r * __builtin_fma(-dl, r, __builtin_fma(-d.h, r, 1.0));
-          const double ih = xh * r;
-          Ih[cI] = ih;
-          Il[cI] = __builtin_fma(xh, rl, __builtin_fma(xl, r, __builtin_fma(xh, r, -ih)));
+          const ddv I = dd_debye_I(w, th[cI], tl[cI]);
+          Ih[cI] = I.h;
+          Il[cI] = I.l;
+          const double ih = I.h;
           const double ph = zc[cI] * ih;
           const double pl = __builtin_fma(zc[cI], Il[cI], __builtin_fma(zc[cI], ih, -ph));
           const ddv s2 = two_sum(sh, ph);
