@@ -377,6 +377,46 @@ __device__ __forceinline__ void basis_Us(double w, double w2, const double *tau2
   if constexpr ((NB - C) & 1) U[NB - 1] = w * rcp_nr(__builtin_fma(w2, tau2s[NB - 1], 1.0));
 }
 
+// Owned poles left over after the groups of four and the pairs: one (the
+// last) or none.
+template <int NB> constexpr bool odd_pole() { return ((NB - 4 * Groups<NB>::NQ) & 1) != 0; }
+
+// The basis at two points a and b (w2 = w^2).  With an odd last pole, that
+// pole's two values share one reciprocal, r = 1/(d_a d_b), R_a = d_b r,
+// R_b = d_a r, as two poles of one point do (the odd pole lies outside the
+// groups, so d <= 1e150 and d_a d_b cannot overflow); the other poles as in
+// basis_Rs / basis_Us at each point.
+template <int NB>
+__device__ __forceinline__ void basis_Rs2(double w2a, double w2b, const double *tau2s, const double *sq, double *Ra,
+                                          double *Rb) {
+  if constexpr (odd_pole<NB>()) {
+    basis_Rs<NB - 1>(w2a, tau2s, sq, Ra);
+    basis_Rs<NB - 1>(w2b, tau2s, sq, Rb);
+    const double da = __builtin_fma(w2a, tau2s[NB - 1], 1.0), db = __builtin_fma(w2b, tau2s[NB - 1], 1.0);
+    const double r = rcp_nr(da * db);
+    Ra[NB - 1] = db * r;
+    Rb[NB - 1] = da * r;
+  } else {
+    basis_Rs<NB>(w2a, tau2s, sq, Ra);
+    basis_Rs<NB>(w2b, tau2s, sq, Rb);
+  }
+}
+template <int NB>
+__device__ __forceinline__ void basis_Us2(double wa, double wb, const double *tau2s, const double *sq, double *Ua,
+                                          double *Ub) {
+  if constexpr (odd_pole<NB>()) {
+    basis_Us<NB - 1>(wa, wa * wa, tau2s, sq, Ua);
+    basis_Us<NB - 1>(wb, wb * wb, tau2s, sq, Ub);
+    const double da = __builtin_fma(wa * wa, tau2s[NB - 1], 1.0), db = __builtin_fma(wb * wb, tau2s[NB - 1], 1.0);
+    const double r = rcp_nr(da * db);
+    Ua[NB - 1] = wa * (db * r);
+    Ub[NB - 1] = wb * (da * r);
+  } else {
+    basis_Us<NB>(wa, wa * wa, tau2s, sq, Ua);
+    basis_Us<NB>(wb, wb * wb, tau2s, sq, Ub);
+  }
+}
+
 // --------------------------------------------------------------------------
 // Dense solve helpers on a packed upper triangle held in registers (SP == 1)
 // or in LDS (SP > 1).  A = U^T U, U upper, diagonal stored as reciprocals in uinv.
@@ -754,9 +794,8 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
   }
   double sum_er = 0.0;
   // one point of the Gram pass
-  auto gram_point = [&](double w, double er, double ei) {
-    double Iv[NV];
-    basis_Us<NB>(w, w * w, tau2s, sq, Iv);
+  // one point of the Gram pass, from its basis values Iv[0 .. NB-1]
+  auto gram_acc = [&](double *Iv, double er, double ei) {
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) bv[cI] = __builtin_fma(Iv[cI], ei, bv[cI]);
     if constexpr (SP > 1) {
@@ -773,6 +812,11 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
         for (int j = i; j < N; ++j) G[tri(N, i, j)] = __builtin_fma(Iv[i], Iv[j], G[tri(N, i, j)]);
     }
     sum_er += er;
+  };
+  auto gram_point = [&](double w, double er, double ei) {
+    double Iv[NV];
+    basis_Us<NB>(w, w * w, tau2s, sq, Iv);
+    gram_acc(Iv, er, ei);
   };
   // Two points per trip let the reciprocal chains of their bases interleave.
   // With no DPP in the body (SP == 1) the compiler pairs the points itself.
@@ -842,8 +886,10 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
       wb_n = ld(om, kb);
       erb_n = ld(epr, kb);
       eib_n = ld(epi, kb);
-      gram_point(wa, era, eia);
-      gram_point(wb, erb, eib);
+      double Ia[NV], Ib[NV];
+      basis_Us2<NB>(wa, wb, tau2s, sq, Ia, Ib);
+      gram_acc(Ia, era, eia);
+      gram_acc(Ib, erb, eib);
     }
     if (k < F) gram_point(wa_n, era_n, eia_n);
   }
@@ -1021,8 +1067,9 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
 #pragma unroll
     for (int cI = 0; cI < NB; ++cI) zs[cI] = zc[cI] * ts[cI];
     // R / s at point k (for the adjoint its column sums taken on the way) and w_k r_k
-    auto resid = [&](double w, double ei, double *Rv) {
-      basis_Rs<NB>(w * w, tau2s, sq, Rv);
+    // w_k r_k from the basis values Rv at point k (for the adjoint the column
+    // sums of R taken on the way)
+    auto resid_R = [&](double w, double ei, const double *Rv) {
       double part = 0.0;
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) {
@@ -1031,24 +1078,49 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
       }
       return w * __builtin_fma(-w, group_sum<SP>(part), ei);
     };
+    auto resid = [&](double w, double ei, double *Rv) {
+      basis_Rs<NB>(w * w, tau2s, sq, Rv);
+      return resid_R(w, ei, Rv);
+    };
     // The compensated sum takes the terms of four points at a time, summed
     // plainly (at most four roundings of terms of the same four points, so
     // the error bound stays a small multiple of the roundoff of the terms'
     // magnitudes; a CPU emulation of the whole solve put the cost error
     // against the 80-bit oracle at the level of single-term compensation).
     auto block4 = [&](int64_t k0) {
-      double pb[NB], R[NB];
-      {
-        const double wr = resid(ld(om, k0), ld(epi, k0), R);
+      double pb[NB];
+      if constexpr (odd_pole<NB>() && SP == 4) {
+        // the points in pairs: the odd pole's values of two points share a
+        // reciprocal (the terms and their order as below; on the four-lane
+        // split only, where the extra registers are free: with one lane per
+        // candidate they spill)
 #pragma unroll
-        for (int cI = 0; cI < NB; ++cI) pb[cI] = R[cI] * wr;
-      }
+        for (int t = 0; t < 4; t += 2) {
+          const int64_t ka = k0 + t * SF, kb = ka + SF;
+          const double wa = ld(om, ka), wb = ld(om, kb);
+          double Ra[NB], Rb[NB];
+          basis_Rs2<NB>(wa * wa, wb * wb, tau2s, sq, Ra, Rb);
+          const double wra = resid_R(wa, ld(epi, ka), Ra);
 #pragma unroll
-      for (int t = 1; t < 4; ++t) {
-        const int64_t kk = k0 + t * SF;
-        const double wr = resid(ld(om, kk), ld(epi, kk), R);
+          for (int cI = 0; cI < NB; ++cI) pb[cI] = t == 0 ? Ra[cI] * wra : __builtin_fma(Ra[cI], wra, pb[cI]);
+          const double wrb = resid_R(wb, ld(epi, kb), Rb);
 #pragma unroll
-        for (int cI = 0; cI < NB; ++cI) pb[cI] = __builtin_fma(R[cI], wr, pb[cI]);
+          for (int cI = 0; cI < NB; ++cI) pb[cI] = __builtin_fma(Rb[cI], wrb, pb[cI]);
+        }
+      } else {
+        double R[NB];
+        {
+          const double wr = resid(ld(om, k0), ld(epi, k0), R);
+#pragma unroll
+          for (int cI = 0; cI < NB; ++cI) pb[cI] = R[cI] * wr;
+        }
+#pragma unroll
+        for (int t = 1; t < 4; ++t) {
+          const int64_t kk = k0 + t * SF;
+          const double wr = resid(ld(om, kk), ld(epi, kk), R);
+#pragma unroll
+          for (int cI = 0; cI < NB; ++cI) pb[cI] = __builtin_fma(R[cI], wr, pb[cI]);
+        }
       }
 #pragma unroll
       for (int cI = 0; cI < NB; ++cI) kahan_fma_acc(gv[cI], gl[cI], 1.0, pb[cI]);
