@@ -87,3 +87,29 @@ def test_rejected_lane_does_not_push_the_wave_out_of_range():
     with np.errstate(over="raise", under="ignore", invalid="raise", divide="raise"):
         R, U, inter = grouped(w, tau2, np.full(len(w), 253))
     assert all(np.all(np.isfinite(v)) and np.all(v >= TINY) for v in inter)
+
+
+def test_odd_pole_shared_by_two_points():
+    """The pole left over after the groups and pairs (outside the scaled
+    groups, d = 1 + w^2 tau^2 unscaled) takes one reciprocal for two points a
+    and b: r = 1/(d_a d_b), R_a = d_b r, R_b = d_a r, U_a = w_a (d_b r).
+    Over the whole admissible range the product stays finite (d < 1e150) and
+    the values are within a few ulp of 1/d and w/d."""
+    rng = np.random.default_rng(4)
+    n = 200_000
+    tau2 = (10.0 ** rng.uniform(-30.0, 30.0, size=n)) ** 2
+    tau2[: n // 8] = 1e60          # the largest admissible tau
+    tau2[n // 8: n // 4] = 1e-60   # the smallest
+    w = 10.0 ** rng.uniform(-30.0, np.log10(OMEGA_BOUND) - 1e-9, size=(n, 2))
+    w[: n // 16] = OMEGA_BOUND * (1 - 1e-12)
+    with np.errstate(over="raise", under="ignore", invalid="raise", divide="raise"):
+        d = w ** 2 * tau2[:, None] + 1.0
+        p = d[:, 0] * d[:, 1]
+        r = 1.0 / p
+        R = np.stack([d[:, 1] * r, d[:, 0] * r], axis=1)
+        U = w * R
+    for v in (d, p, r, R, U):
+        assert np.all(np.isfinite(v)) and np.all(v >= TINY)
+    eps = np.finfo(np.float64).eps
+    assert np.abs(R * d - 1.0).max() < 8 * eps
+    assert np.abs(U * d / w - 1.0).max() < 8 * eps
