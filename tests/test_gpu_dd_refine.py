@@ -11,7 +11,8 @@ the flag.  The checks:
     pole splits): no candidate beyond 1e-10 of the FP64 or 80-bit oracle;
   - a persistent-launch plan evaluates the flag with per-bucket launches:
     results bit-identical to a per-bucket plan's;
-  - a swarm run with the flag records the flag's costs;
+  - swarm, differential-evolution and annealing runs with the flag record the
+    flag's costs;
   - the flag's exclusions: together with DEBYE_FLAG_NO_REFINE, in the adjoint,
     in the polish and in the autograd function."""
 import numpy as np
@@ -115,6 +116,16 @@ def test_dd_refine_persistent_plan_and_swarm(D, orc):
     ok = torch.isfinite(sw.pbest_cost)
     assert ok.any()
     assert torch.equal(c_best[ok], sw.pbest_cost[ok])
+    # the same for differential evolution and annealing: the fitness they keep
+    # for their current members is the flag's cost of those members
+    for run in (D.de_run, D.da_run):
+        pop = D.Population.empty(wl.P, wl.M, wl.ld, 6)
+        run(pb, b, lb, ub, pop, 5, seed=4, flags=D.FLAG_DD_REFINE)
+        c_now = D.fit_eval(pb, b, pop.x, flags=D.FLAG_DD_REFINE, want_weights=False)[0]
+        torch.cuda.synchronize()
+        ok = torch.isfinite(pop.fit)
+        assert ok.any(), run.__name__
+        assert torch.equal(c_now[ok], pop.fit[ok]), run.__name__
 
 
 def test_dd_refine_flag_rules(D, orc):
