@@ -101,6 +101,11 @@ def test_uniform_detection():
     assert not D.schedule_preview(_offsets([100] * 16), _offsets([12] * 16), range(16), 20, 4, 2)[3]
     # one material padded to a whole wave is still uniform
     assert D.schedule_preview(_offsets([100]), _offsets([10]), [0], 5, 1, 1)[3]
+    # a spectrum of 2^29 points or more is past the uniform form's 32-bit
+    # byte offsets: the general form (64-bit point indices) takes it
+    assert D.schedule_preview(_offsets([2**29 - 1]), _offsets([8]), [0], 2, 1, 64)[3]
+    assert not D.schedule_preview(_offsets([2**29]), _offsets([8]), [0], 2, 1, 64)[3]
+    assert not D.schedule_preview(_offsets([100, 2**29 + 5]), _offsets([64, 64]), [0, 1], 2, 1, 1)[3]
 
 
 def test_empty_bucket_and_bad_arguments():
