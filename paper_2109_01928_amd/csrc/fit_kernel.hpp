@@ -417,6 +417,33 @@ __device__ __forceinline__ void basis_Us2(double wa, double wb, const double *ta
   }
 }
 
+// R / s of the poles of two owner lanes of the four-lane split (a
+// half-candidate): their two groups of four at the wave's group scale s
+// (t2[0..7], tau^2 s), then their LO leftover poles each (t2[8..], tau^2,
+// unscaled, so that d <= 1e150) in pairs sharing a reciprocal.
+template <int LO>
+__device__ __forceinline__ void basis_half(double w2, const double *t2, double s, double *R) {
+#pragma unroll
+  for (int c = 0; c < 8; c += 4) {
+    const double d0 = __builtin_fma(w2, t2[c], s), d1 = __builtin_fma(w2, t2[c + 1], s);
+    const double d2 = __builtin_fma(w2, t2[c + 2], s), d3 = __builtin_fma(w2, t2[c + 3], s);
+    const double p01 = d0 * d1, p23 = d2 * d3;
+    const double r = rcp_nr(p01 * p23);
+    const double r01 = r * p23, r23 = r * p01;
+    R[c] = d1 * r01;
+    R[c + 1] = d0 * r01;
+    R[c + 2] = d3 * r23;
+    R[c + 3] = d2 * r23;
+  }
+#pragma unroll
+  for (int c = 8; c < 8 + 2 * LO; c += 2) {
+    const double d0 = __builtin_fma(w2, t2[c], 1.0), d1 = __builtin_fma(w2, t2[c + 1], 1.0);
+    const double r = rcp_nr(d0 * d1);
+    R[c] = d1 * r;
+    R[c + 1] = d0 * r;
+  }
+}
+
 // --------------------------------------------------------------------------
 // Dense solve helpers on a packed upper triangle held in registers (SP == 1)
 // or in LDS (SP > 1).  A = U^T U, U upper, diagonal stored as reciprocals in uinv.
@@ -1061,6 +1088,108 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
       }
     }
     freq_sum_dd_n<NB>(gv, gl, SP, SL);
+  } else if constexpr (SP == 4 && !GRAD) {
+    if (refine) {
+      // The four-lane split runs this pass over half-candidates: lane q takes
+      // the poles of owner lanes 2h and 2h + 1 (h = q & 1; their groups of four,
+      // then their leftover poles) and every other point of its frequency
+      // lane's points (subset q >> 1).  A point's model sum then needs one
+      // exchange (between the two halves) instead of two, and each point's
+      // basis is formed by two lanes instead of four.  The owners' tau^2 s and
+      // tau s z reach the halves through the candidate's LDS region (its
+      // right-hand-side and correction vectors are free during this pass), and
+      // the sums of (R / s)(w r), added over the point subsets and frequency
+      // lanes, return to the owners the same way.
+      constexpr int LO = NB - 4;        // leftover poles per owner
+      constexpr int H = 8 + 2 * LO;     // poles of a half
+      const int h = q & 1;
+      // the pole of element e of the half: owner 2h's group, owner 2h + 1's,
+      // then owner 2h's leftovers, owner 2h + 1's
+      auto pole = [&](int e) -> int {
+        const int own = 2 * h + (e < 8 ? e / 4 : (e - 8) / LO);
+        const int cI = e < 8 ? e % 4 : 4 + (e - 8) % LO;
+        return own * NB + cI;
+      };
+      const LdsLayout<N> lay(L);
+      double *st2 = lay.vb, *stz = lay.vw;
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) {
+        const int p = q * NB + cI;
+        if (p < N) {   // (every frequency lane of the owner writes the same values)
+          st2[p] = tau2s[cI];
+          stz[p] = zc[cI] * ts[cI];
+        }
+      }
+      __syncthreads();
+      double t2h[H], zh[H];
+#pragma unroll
+      for (int e = 0; e < H; ++e) {
+        const int p = pole(e);
+        t2h[e] = p < N ? st2[p] : 0.0;   // padded poles: no weight
+        zh[e] = p < N ? stz[p] : 0.0;
+      }
+      const double s0 = sq[0];
+      double gh[H], gc[H];
+#pragma unroll
+      for (int e = 0; e < H; ++e) gh[e] = gc[e] = 0.0;
+      // four points of the lane at a time (the two halves of a point subset
+      // take the same points, so their exchanges pair up), compensated as above
+      const int64_t s2 = 2 * (int64_t)SF;
+      // w r at point kk, with the point's R / s in R
+      auto half_resid = [&](int64_t kk, double *R) {
+        const double w = ld(om, kk);
+        basis_half<LO>(w * w, t2h, s0, R);
+        double part = 0.0;
+#pragma unroll
+        for (int e = 0; e < H; ++e) part = __builtin_fma(R[e], zh[e], part);
+        return w * __builtin_fma(-w, part + dpp_quad<QP_SWAP1>(part), ld(epi, kk));
+      };
+      auto blk = [&](int64_t k0, int np) {   // np >= 1 points
+        double pb[H], R[H];
+        {
+          const double wr = half_resid(k0, R);
+#pragma unroll
+          for (int e = 0; e < H; ++e) pb[e] = R[e] * wr;
+        }
+        for (int t = 1; t < np; ++t) {
+          const double wr = half_resid(k0 + t * s2, R);
+#pragma unroll
+          for (int e = 0; e < H; ++e) pb[e] = __builtin_fma(R[e], wr, pb[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < H; ++e) kahan_fma_acc(gh[e], gc[e], 1.0, pb[e]);
+      };
+      // (two blocks per trip, so that the compensated sums alternate between
+      // two registers instead of being copied back every update)
+      int64_t k = (q >> 1) * SF + fl;
+      for (; k + 7 * s2 < F; k += 8 * s2) {
+        blk(k, 4);
+        blk(k + 4 * s2, 4);
+      }
+      if (k + 3 * s2 < F) {
+        blk(k, 4);
+        k += 4 * s2;
+      }
+      if (k < F) blk(k, (int)((F - 1 - k) / s2) + 1);
+      {
+        double ngc[H];
+#pragma unroll
+        for (int e = 0; e < H; ++e) ngc[e] = -gc[e];
+        freq_sum_dd_n<H>(gh, ngc, 2, SL);   // the point subsets and the frequency lanes
+      }
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < H; ++e) {
+        const int p = pole(e);
+        if (p < N) st2[p] = gh[e];   // (both point subsets hold the same sums)
+      }
+      __syncthreads();
+#pragma unroll
+      for (int cI = 0; cI < NB; ++cI) {
+        const int p = q * NB + cI;
+        gv[cI] = (p < N ? st2[p] : 0.0) * ts[cI];
+      }
+    }
   } else if (GRAD || refine) {
     // I z = w sum_i (tau_i s_i z_i) (R_i / s_i), and I^T r = tau s ((R / s)^T (w r))
     double zs[NB];
