@@ -417,14 +417,16 @@ __device__ __forceinline__ void basis_Us2(double wa, double wb, const double *ta
   }
 }
 
-// R / s of the poles of two owner lanes of the four-lane split (a
-// half-candidate): their two groups of four at the wave's group scale s
-// (t2[0..7], tau^2 s), then their LO leftover poles each (t2[8..], tau^2,
+// R / s of the poles of two owner lanes (a half-candidate of the four-lane
+// split, a whole candidate of the two-lane split): each owner's NQ groups of
+// four at the wave's group scales (t2[0 .. 8 NQ), owner A's groups then
+// owner B's, tau^2 s), then their LO leftover poles each (t2[8 NQ ..), tau^2,
 // unscaled, so that d <= 1e150) in pairs sharing a reciprocal.
-template <int LO>
-__device__ __forceinline__ void basis_half(double w2, const double *t2, double s, double *R) {
+template <int NQ, int LO>
+__device__ __forceinline__ void basis_two_owners(double w2, const double *t2, const double *sq, double *R) {
 #pragma unroll
-  for (int c = 0; c < 8; c += 4) {
+  for (int c = 0; c < 8 * NQ; c += 4) {
+    const double s = sq[(c / 4) % NQ];
     const double d0 = __builtin_fma(w2, t2[c], s), d1 = __builtin_fma(w2, t2[c + 1], s);
     const double d2 = __builtin_fma(w2, t2[c + 2], s), d3 = __builtin_fma(w2, t2[c + 3], s);
     const double p01 = d0 * d1, p23 = d2 * d3;
@@ -436,7 +438,7 @@ __device__ __forceinline__ void basis_half(double w2, const double *t2, double s
     R[c + 3] = d2 * r23;
   }
 #pragma unroll
-  for (int c = 8; c < 8 + 2 * LO; c += 2) {
+  for (int c = 8 * NQ; c < 8 * NQ + 2 * LO; c += 2) {
     const double d0 = __builtin_fma(w2, t2[c], 1.0), d1 = __builtin_fma(w2, t2[c + 1], 1.0);
     const double r = rcp_nr(d0 * d1);
     R[c] = d1 * r;
@@ -1088,26 +1090,32 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
       }
     }
     freq_sum_dd_n<NB>(gv, gl, SP, SL);
-  } else if constexpr (SP == 4 && !GRAD) {
+  } else if constexpr (!GRAD && (SP == 4 || (SP == 2 && NB <= 6))) {
     if (refine) {
-      // The four-lane split runs this pass over half-candidates: lane q takes
-      // the poles of owner lanes 2h and 2h + 1 (h = q & 1; their groups of four,
-      // then their leftover poles) and every other point of its frequency
-      // lane's points (subset q >> 1).  A point's model sum then needs one
-      // exchange (between the two halves) instead of two, and each point's
-      // basis is formed by two lanes instead of four.  The owners' tau^2 s and
-      // tau s z reach the halves through the candidate's LDS region (its
-      // right-hand-side and correction vectors are free during this pass), and
-      // the sums of (R / s)(w r), added over the point subsets and frequency
-      // lanes, return to the owners the same way.
-      constexpr int LO = NB - 4;        // leftover poles per owner
-      constexpr int H = 8 + 2 * LO;     // poles of a half
-      const int h = q & 1;
-      // the pole of element e of the half: owner 2h's group, owner 2h + 1's,
-      // then owner 2h's leftovers, owner 2h + 1's
+      // The pole splits run this pass over pairs of owner lanes: lane q takes
+      // the poles of owner lanes 2h and 2h + 1 (their groups of four, then
+      // their leftover poles) on every other point of its frequency lane's
+      // points.  On the four-lane split h = q & 1 and the point subset is
+      // q >> 1, so a point's model sum needs one exchange (between the two
+      // halves) instead of two; on the two-lane split h = 0, the subset is q,
+      // and a lane holds the whole candidate: no exchange.  Each point's
+      // basis is formed by half the lanes.  The owners' tau^2 s and tau s z
+      // reach the lanes through the candidate's LDS region (its
+      // right-hand-side and correction vectors are free during this pass),
+      // and the sums of (R / s)(w r), added over the point subsets and
+      // frequency lanes, return to the owners the same way.  (On the
+      // two-lane split only up to N = 12: beyond, its 2 NB poles per lane
+      // spill registers.)
+      constexpr int NQ = Groups<NB>::NQ;   // groups of four per owner
+      constexpr int LO = NB - 4 * NQ;      // leftover poles per owner
+      constexpr int H = 2 * NB;            // poles per lane
+      constexpr int HP = SP / 2;           // owner pairs per candidate
+      const int h = q % HP;
+      // the pole of element e: owner 2h's groups, owner 2h + 1's, then owner
+      // 2h's leftovers, owner 2h + 1's
       auto pole = [&](int e) -> int {
-        const int own = 2 * h + (e < 8 ? e / 4 : (e - 8) / LO);
-        const int cI = e < 8 ? e % 4 : 4 + (e - 8) % LO;
+        const int own = 2 * h + (e < 8 * NQ ? e / (4 * NQ) : (e - 8 * NQ) / (LO > 0 ? LO : 1));
+        const int cI = e < 8 * NQ ? e % (4 * NQ) : 4 * NQ + (e - 8 * NQ) % (LO > 0 ? LO : 1);
         return own * NB + cI;
       };
       const LdsLayout<N> lay(L);
@@ -1128,31 +1136,32 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
         t2h[e] = p < N ? st2[p] : 0.0;   // padded poles: no weight
         zh[e] = p < N ? stz[p] : 0.0;
       }
-      const double s0 = sq[0];
       double gh[H], gc[H];
 #pragma unroll
       for (int e = 0; e < H; ++e) gh[e] = gc[e] = 0.0;
-      // four points of the lane at a time (the two halves of a point subset
-      // take the same points, so their exchanges pair up), compensated as above
+      // four points of the lane at a time (on the four-lane split the two
+      // halves of a point subset take the same points, so their exchanges
+      // pair up), compensated as below
       const int64_t s2 = 2 * (int64_t)SF;
       // w r at point kk, with the point's R / s in R
-      auto half_resid = [&](int64_t kk, double *R) {
+      auto pair_resid = [&](int64_t kk, double *R) {
         const double w = ld(om, kk);
-        basis_half<LO>(w * w, t2h, s0, R);
+        basis_two_owners<NQ, LO>(w * w, t2h, sq, R);
         double part = 0.0;
 #pragma unroll
         for (int e = 0; e < H; ++e) part = __builtin_fma(R[e], zh[e], part);
-        return w * __builtin_fma(-w, part + dpp_quad<QP_SWAP1>(part), ld(epi, kk));
+        if constexpr (HP == 2) part = part + dpp_quad<QP_SWAP1>(part);
+        return w * __builtin_fma(-w, part, ld(epi, kk));
       };
       auto blk = [&](int64_t k0, int np) {   // np >= 1 points
         double pb[H], R[H];
         {
-          const double wr = half_resid(k0, R);
+          const double wr = pair_resid(k0, R);
 #pragma unroll
           for (int e = 0; e < H; ++e) pb[e] = R[e] * wr;
         }
         for (int t = 1; t < np; ++t) {
-          const double wr = half_resid(k0 + t * s2, R);
+          const double wr = pair_resid(k0 + t * s2, R);
 #pragma unroll
           for (int e = 0; e < H; ++e) pb[e] = __builtin_fma(R[e], wr, pb[e]);
         }
@@ -1161,7 +1170,7 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
       };
       // (two blocks per trip, so that the compensated sums alternate between
       // two registers instead of being copied back every update)
-      int64_t k = (q >> 1) * SF + fl;
+      int64_t k = (q / HP) * SF + fl;
       for (; k + 7 * s2 < F; k += 8 * s2) {
         blk(k, 4);
         blk(k + 4 * s2, 4);
@@ -1175,7 +1184,7 @@ __device__ __forceinline__ void fit_tile(const FitArgs &a, const int64_t tile) {
         double ngc[H];
 #pragma unroll
         for (int e = 0; e < H; ++e) ngc[e] = -gc[e];
-        freq_sum_dd_n<H>(gh, ngc, 2, SL);   // the point subsets and the frequency lanes
+        freq_sum_dd_n<H>(gh, ngc, HP, SL);   // the point subsets and the frequency lanes
       }
       __syncthreads();
 #pragma unroll
