@@ -228,6 +228,25 @@ def test_dd_refine_parity_extreme_relaxation_times(D, orc, N):
     _check_eval(D, orc, wl, theta, tag=f"dd extreme N{N}", edge=(3, 70, 71), gpu_flags=D.FLAG_DD_REFINE)
 
 
+@pytest.mark.parametrize("N", [12, 17, 20, 24])
+def test_cost_parity_short_spectra(D, orc, N):
+    """Spectra shorter than a candidate's lanes (F from 1 to 21 at frequency
+    splits up to 64 / SP): lanes and point subsets with no points, the
+    refinement pass's tails of one to three points, and fewer points than
+    poles (the damped system stays definite)."""
+    Fm = [1, 2, 3, 5, 8, 13, 21]
+    M = len(Fm)
+    kind, params = W.draw_mixed(M, 500 + N, 1e6, 1e10)
+    lb, ub = W.tau_bounds(1e6, 1e10)
+    om = np.concatenate([W.log_grid(1e6, 1e10, f) for f in Fm])
+    wl = W.Workload(f"short spectra N{N}", kind, params, W.offsets(Fm), om, np.full(M, N, np.int32),
+                    W.offsets([24] * M), np.full(M, lb), np.full(M, ub), 1, seed=500 + N)
+    theta = W.draw_theta(wl.cand_off, wl.n_poles, wl.lb, wl.ub, wl.ld, seed=N)
+    sp = D.Plan(_gpu_batch(D, wl, *targets_oracle(orc, wl))).info()[0]["pole_split"]
+    for split in sorted({1, 2, 8, 64 // sp}):
+        _check_eval(D, orc, wl, theta, split=split, tag=f"short N{N}")
+
+
 @pytest.mark.parametrize("N", [6, 12, 20])
 def test_cost_parity_uniform_and_mixed_tiles(D, orc, N):
     """Both tile forms at split 1 and wider splits: whole swarms of 64 (every
